@@ -1,0 +1,310 @@
+"""FP64 CPU oracle for the discrete Helmholtz hot path.
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by the tests, by the
+smoke check and by the benchmark's CPU-baseline leg, never by the product
+path.  It shares no code with the HIP library (``paper_2301_10762_amd``):
+the operator, the banded LU and all formulas below are written separately.
+
+Paper: Downing, Gazzola, Graham, Spence, "Optimising seismic imaging design
+parameters via bilevel learning" (arXiv 2301.10762).
+
+What each function follows:
+  * operator  A(m, w) = S - w^2 M(m) - i w B(m), nodal quadrature
+    (App. A.1, "Numerical forward model")                -> C: or_factor/or_apply
+  * wavefield A u = e_s for a grid-point source (App. A.1, "Computing the
+    wavefield"), adjoint solves with A^* (App. A.1)      -> Factor.solve / adjoint_solve
+  * misfit   phi = 1/2 sum_s sum_w |eps|^2 + 1/2 m^T Gamma m, eps = d - R u
+    (eqs (phi), (resd), (newphi), (resdbi))              -> misfit_grad
+  * gradient dphi/dm_k = -Re sum (G(beta_k u), lambda) + Gamma m, with
+    lambda = S^*(R^* eps, 0) (Thm A.1, eqs (I4), (lambda)); discrete form
+    -Re((w^2 d_k + b_k i w/(2 sqrt m_k)) u_k conj(lambda_k)) (App. B.1)
+                                                          -> misfit_grad
+  * Gauss-Newton product H^(1) mt via v = S G(mt u), z = S^*(R^*R v)
+    (Lemma "Adjoint-state formula for H^(1)", eqs (defv), (H1v))  -> gn_hvp
+  * regulariser Gamma = alpha (Dx^T Dx + Dz^T Dz) + mu I (eqs (Gamma),
+    (ThisGamma))                                          -> regulariser
+
+Readings where the paper is silent (each pinned by a test in tests/):
+  * corner mass weight hx*hz/4 (mean of the two triangulation directions);
+  * b_k = half the length of each boundary edge touching node k;
+  * (f, g) = sum f conj(g) (linear in the first argument), Re taken last;
+  * on-node receivers: R samples u at the node, R^* scatters onto that node;
+  * D_n keeps the printed factor (n - 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "helm_oracle.c")
+_LIB = os.path.join(_HERE, "_helm_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, IEEE arithmetic)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.or_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.or_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp,
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.or_factor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp,
+                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        lib.or_factor.restype = ctypes.c_void_p
+        lib.or_factor_free.argtypes = [ctypes.c_void_p]
+        lib.or_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.or_band_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.or_band_bytes.restype = ctypes.c_size_t
+        lib.or_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+class Grid:
+    """n_x x n_z nodes, spacings h_x, h_z; node k = j*n_x + i, j = 0 on top."""
+
+    def __init__(self, nx: int, nz: int, hx: float, hz: float):
+        self.nx, self.nz, self.hx, self.hz = int(nx), int(nz), float(hx), float(hz)
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.nz
+
+    @classmethod
+    def of(cls, w) -> "Grid":
+        return cls(w.nx, w.nz, w.hx, w.hz)
+
+
+def weights(g: Grid):
+    """Nodal quadrature weights (d, b) of App. A.1: M = diag(d m), B = diag(b sqrt m)."""
+    d = np.empty(g.N)
+    b = np.empty(g.N)
+    _load().or_weights(g.nx, g.nz, g.hx, g.hz, _dp(d), _dp(b))
+    return d, b
+
+
+def _check_model(g: Grid, m) -> np.ndarray:
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    if m.shape != (g.N,):
+        raise ValueError("model must have one value per node")
+    if not np.all(np.isfinite(m)) or np.any(m <= 0):
+        raise ValueError("model must be finite and positive (m in R^M_+)")
+    return m
+
+
+def _as_cols(B, N) -> np.ndarray:
+    """Accept [S][N] or [N] complex arrays; return contiguous complex128 [S][N]."""
+    B = np.asarray(B, dtype=np.complex128)
+    if B.ndim == 1:
+        B = B[None, :]
+    if B.shape[1] != N:
+        raise ValueError("right-hand sides must be [S][N]")
+    return np.ascontiguousarray(B)
+
+
+def apply(g: Grid, m, omega: float, X, adjoint: bool = False) -> np.ndarray:
+    """A(m, w) X, or A(m, w)^* X."""
+    m = _check_model(g, m)
+    X = _as_cols(X, g.N)
+    Y = np.empty_like(X)
+    _load().or_apply(g.nx, g.nz, g.hx, g.hz, _dp(m), float(omega), int(adjoint), X.shape[0],
+                     _dp(X.view(np.float64)), _dp(Y.view(np.float64)))
+    return Y
+
+
+def matrix(g: Grid, m, omega: float) -> sp.csr_matrix:
+    """A(m, w) as a sparse matrix, extracted column by column through `apply`."""
+    E = np.eye(g.N, dtype=np.complex128)
+    cols = apply(g, m, omega, E)
+    return sp.csr_matrix(cols.T)
+
+
+class Factor:
+    """Banded LU (partial pivoting) of A(m, w); solves with A and with A^*."""
+
+    def __init__(self, g: Grid, m, omega: float):
+        self.g = g
+        self.omega = float(omega)
+        self.m = _check_model(g, m)
+        st = ctypes.c_int(0)
+        self._h = _load().or_factor(g.nx, g.nz, g.hx, g.hz, _dp(self.m), self.omega, ctypes.byref(st))
+        if not self._h:
+            raise MemoryError("oracle factor allocation failed")
+        if st.value != 0:
+            _load().or_factor_free(self._h)
+            self._h = None
+            raise ZeroDivisionError(f"exactly singular pivot in column {st.value - 1}")
+        self.solves = 0
+
+    def _run(self, trans: int, B) -> np.ndarray:
+        B = _as_cols(B, self.g.N)
+        X = np.empty_like(B)
+        _load().or_solve(self._h, trans, B.shape[0], _dp(B.view(np.float64)), _dp(X.view(np.float64)))
+        self.solves += B.shape[0]
+        return X
+
+    def solve(self, B) -> np.ndarray:
+        """X with A X = B (columns [S][N])."""
+        return self._run(0, B)
+
+    def adjoint_solve(self, R) -> np.ndarray:
+        """L with A^* L = R."""
+        return self._run(1, R)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().or_factor_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def band_bytes(g: Grid) -> int:
+    return int(_load().or_band_bytes(g.nx, g.nz))
+
+
+def unit_sources(g: Grid, nodes) -> np.ndarray:
+    """e_s for each grid-point source s (App. A.1, "Computing the wavefield")."""
+    E = np.zeros((len(nodes), g.N), dtype=np.complex128)
+    E[np.arange(len(nodes)), np.asarray(nodes, dtype=np.int64)] = 1.0
+    return E
+
+
+def restrict(U: np.ndarray, receivers) -> np.ndarray:
+    """R u for on-node receivers (eq (Rv)): the nodal values at the sensors."""
+    return U[:, np.asarray(receivers, dtype=np.int64)]
+
+
+def restrict_adjoint(Z: np.ndarray, receivers, N: int) -> np.ndarray:
+    """R^* z (eq (Rstar)) for on-node receivers: z_p placed on node p (summed if repeated)."""
+    out = np.zeros((Z.shape[0], N), dtype=np.complex128)
+    rec = np.asarray(receivers, dtype=np.int64)
+    for q, k in enumerate(rec):
+        out[:, k] += Z[:, q]
+    return out
+
+
+def relres(g: Grid, m, omega: float, X, B, adjoint: bool = False) -> np.ndarray:
+    """Per-column ||B - A X||_2 / ||B||_2."""
+    B = _as_cols(B, g.N)
+    R = B - apply(g, m, omega, X, adjoint)
+    return np.linalg.norm(R, axis=1) / np.linalg.norm(B, axis=1)
+
+
+def grad_weight(g: Grid, m, omega: float) -> np.ndarray:
+    """Nodal form of G_{m,w}(beta_k .): w^2 d_k + b_k i w / (2 sqrt(m_k)) (App. B.1)."""
+    d, b = weights(g)
+    return omega ** 2 * d + 1j * omega * b / (2.0 * np.sqrt(m))
+
+
+def synth_data(g: Grid, m_true, omegas, sources, receivers) -> np.ndarray:
+    """d(w, s) = R u(m', w, s) on the same grid (eq (resdbi)); [n_omega][S][Nr]."""
+    out = []
+    for w in omegas:
+        F = Factor(g, m_true, w)
+        out.append(restrict(F.solve(unit_sources(g, sources)), receivers))
+        F.close()
+    return np.ascontiguousarray(np.array(out))
+
+
+def regulariser(g: Grid, alpha: float, mu: float) -> sp.csr_matrix:
+    """Gamma(alpha, mu) = alpha (Dx^T Dx + Dz^T Dz) + mu I (eqs (Gamma), (ThisGamma)).
+
+    The paper orders unknowns with z fastest (Dx = D_{n1} (x) I_{n2}); the grid
+    here orders x fastest, so the matrix is built in the paper's order and
+    permuted."""
+    def Dn(n):
+        return (n - 1) * sp.diags([np.ones(n - 1), -np.ones(n - 1)], [0, 1], shape=(n - 1, n))
+    n1, n2 = g.nx, g.nz
+    Dx = sp.kron(Dn(n1), sp.identity(n2))
+    Dz = sp.kron(sp.identity(n1), Dn(n2))
+    Rp = (Dx.T @ Dx + Dz.T @ Dz).tocsr()
+    # paper index p = i*n2 + j  <->  grid index k = j*n1 + i
+    k_of_p = np.array([(p % n2) * n1 + p // n2 for p in range(n1 * n2)])
+    P = sp.csr_matrix((np.ones(n1 * n2), (k_of_p, np.arange(n1 * n2))), shape=(n1 * n2, n1 * n2))
+    R = (P @ Rp @ P.T).tocsr()
+    return (alpha * R + mu * sp.identity(n1 * n2)).tocsr()
+
+
+def misfit_grad(g: Grid, m, omegas, d_obs, sources, receivers, alpha: float = 0.0,
+                mu: float = 0.0, return_fields: bool = False):
+    """phi and grad phi (Alg. "Computing phi, grad phi"; Thm A.1; App. B.1).
+
+    For each frequency: u_s = A^{-1} e_s, eps_s = d_s - R u_s,
+    lambda_s = A^{-*} R^* eps_s, then
+    g_k = -Re sum_w sum_s (w^2 d_k + b_k i w/(2 sqrt m_k)) u_{s,k} conj(lambda_{s,k}),
+    plus the regulariser terms 1/2 m^T Gamma m and Gamma m."""
+    m = _check_model(g, m)
+    phi = 0.0
+    grad = np.zeros(g.N)
+    fields = []
+    for iw, w in enumerate(omegas):
+        F = Factor(g, m, w)
+        U = F.solve(unit_sources(g, sources))
+        eps = np.asarray(d_obs[iw]) - restrict(U, receivers)
+        phi += 0.5 * float(np.sum(np.abs(eps) ** 2))
+        Lam = F.adjoint_solve(restrict_adjoint(eps, receivers, g.N))
+        wk = grad_weight(g, m, w)
+        grad += -np.real(np.sum(wk[None, :] * U * np.conj(Lam), axis=0))
+        if return_fields:
+            fields.append((U, Lam, F.solves))
+        F.close()
+    if alpha != 0.0 or mu != 0.0:
+        G = regulariser(g, alpha, mu)
+        phi += 0.5 * float(m @ (G @ m))
+        grad += G @ m
+    if return_fields:
+        return phi, grad, fields
+    return phi, grad
+
+
+def gn_hvp(g: Grid, m, omegas, sources, receivers, directions, alpha: float = 0.0,
+           mu: float = 0.0):
+    """Gauss-Newton products H^(1) mt for each direction mt (Lemma for H^(1)).
+
+    Per frequency and source: u = A^{-1} e_s, gt = (w^2 d + b i w/(2 sqrt m)) u,
+    v = A^{-1}(gt * mt), z = A^{-*}(R^* R v), (H^(1) mt)_j = Re sum gt_j conj(z_j).
+    Returns (H1 mt, (H1 + Gamma) mt) as [n_dir][N] arrays."""
+    m = _check_model(g, m)
+    dirs = [np.asarray(t, dtype=np.float64) for t in directions]
+    out = np.zeros((len(dirs), g.N))
+    for w in omegas:
+        F = Factor(g, m, w)
+        U = F.solve(unit_sources(g, sources))
+        gt = grad_weight(g, m, w)[None, :] * U
+        for a, mt in enumerate(dirs):
+            V = F.solve(gt * mt[None, :])
+            RV = restrict(V, receivers)
+            Z = F.adjoint_solve(restrict_adjoint(RV, receivers, g.N))
+            out[a] += np.real(np.sum(gt * np.conj(Z), axis=0))
+        F.close()
+    G = regulariser(g, alpha, mu)
+    with_reg = out + np.array([G @ t for t in dirs]) if dirs else out
+    return out, with_reg

@@ -1,0 +1,91 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by its pins.
+
+Each test swaps one piece of the oracle for a plausible wrong version (a
+dropped term, a wrong sign, a missing conjugate, a transposed operand, an
+off-by-one index) and checks that the finite-difference or identity pin that
+guards that piece then fails.  The real oracle passes the same checks in
+test_oracle.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Grid
+from paper_2301_10762_amd import inputs as I
+
+
+def _fd_gradient_error(seed=4):
+    w = I.small_layered(13, seed, 3, 5, ppws=(8.0,))
+    g = Grid.of(w)
+    d_obs = oracle.synth_data(g, w.m_true, w.omegas, w.sources, w.receivers)
+    _, grad = oracle.misfit_grad(g, w.m, w.omegas, d_obs, w.sources, w.receivers)
+    rng = np.random.default_rng(1)
+    t = 1e-6
+    worst = 0.0
+    d, b = oracle.weights(g)
+    for kind in range(3):
+        dlt = rng.standard_normal(g.N) if kind < 2 else np.where(b > 0, 1.0, 0.0)
+        dlt /= np.linalg.norm(dlt)
+        fp, _ = oracle.misfit_grad(g, w.m + t * dlt, w.omegas, d_obs, w.sources, w.receivers)
+        fm, _ = oracle.misfit_grad(g, w.m - t * dlt, w.omegas, d_obs, w.sources, w.receivers)
+        fd = (fp - fm) / (2 * t)
+        worst = max(worst, abs(fd - grad @ dlt) / abs(fd))
+    return worst
+
+
+def test_unmutated_oracle_passes():
+    assert _fd_gradient_error() < 1e-6
+
+
+def test_dropped_boundary_term_caught(monkeypatch):
+    d_b = oracle.weights
+
+    def no_boundary(g, m, omega):
+        d, _ = d_b(g)
+        return omega ** 2 * d + 0j
+    monkeypatch.setattr(oracle, "grad_weight", no_boundary)
+    assert _fd_gradient_error() > 1e-4
+
+
+def test_wrong_boundary_sign_caught(monkeypatch):
+    def flipped(g, m, omega):
+        d, b = oracle.weights(g)
+        return omega ** 2 * d - 1j * omega * b / (2.0 * np.sqrt(m))
+    monkeypatch.setattr(oracle, "grad_weight", flipped)
+    assert _fd_gradient_error() > 1e-4
+
+
+def test_transpose_instead_of_adjoint_caught(monkeypatch):
+    # A^{-T} = A^{-1} for complex-symmetric A: solving with A instead of A^*
+    monkeypatch.setattr(oracle.Factor, "adjoint_solve", lambda self, R: self.solve(R))
+    assert _fd_gradient_error() > 1e-4
+
+
+def test_off_by_one_receiver_scatter_caught(monkeypatch):
+    real = oracle.restrict_adjoint
+
+    def shifted(Z, receivers, N):
+        return real(Z, np.asarray(receivers) + 1, N)
+    monkeypatch.setattr(oracle, "restrict_adjoint", shifted)
+    assert _fd_gradient_error() > 1e-4
+
+
+def test_residual_sign_caught(monkeypatch):
+    real = oracle.restrict
+
+    def neg(U, receivers):
+        return -real(U, receivers)
+    # eps = d + R u instead of d - R u changes phi and its gradient inconsistently
+    monkeypatch.setattr(oracle, "restrict", neg)
+    assert _fd_gradient_error() > 1e-4
+
+
+def test_gn_missing_conjugate_caught(monkeypatch):
+    """H^(1) symmetry fails if z is not conjugated in the final inner product."""
+    w = I.small_layered(9, 2, 2, 4, ppws=(9.0,))
+    g = Grid.of(w)
+    rng = np.random.default_rng(9)
+    d1, d2 = rng.standard_normal(g.N), rng.standard_normal(g.N)
+    monkeypatch.setattr(np, "conj", lambda x: x)
+    (h1, h2), _ = oracle.gn_hvp(g, w.m, w.omegas, w.sources, w.receivers, [d1, d2])
+    assert abs(d2 @ h1 - d1 @ h2) > 1e-6 * abs(d2 @ h1)
