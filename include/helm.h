@@ -1,0 +1,170 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) Helmholtz hot-path library, libhelm.so.
+ *
+ * The library factors and solves the discrete 2-D Helmholtz systems of
+ * Downing, Gazzola, Graham & Spence, "Optimising seismic imaging design
+ * parameters via bilevel learning" (arXiv 2301.10762):
+ *
+ *   A(m, w) = S - w^2 M(m) - i w B(m)                       (App. A.1)
+ *
+ * on an n_x x n_z node grid (P1 elements with nodal quadrature, i.e. the
+ * five-point stencil with halved boundary couplings; M = diag(d_k m_k),
+ * B = diag(b_k sqrt(m_k)), first-order impedance boundary condition of
+ * eq (forward)).  Each system is factored as a block-tridiagonal LU with one
+ * dense n_x x n_x block per grid row, the explicit inverse of every Schur
+ * complement being kept so that the sweeps are matrix products.
+ *
+ * Conventions used by every entry point
+ *   - Node k = j*nx + i, x_i = i*hx, z_j = j*hz, j = 0 is the top row.
+ *   - Complex vectors are interleaved (re, im) doubles, i.e. complex128.
+ *     A block of S vectors is column-major: vector s starts at element s*ld
+ *     (ld >= nx*nz, counted in complex elements).
+ *   - "_dev" pointers are device (HBM) addresses on the current HIP device;
+ *     "_host" pointers are host addresses.  The caller owns all of them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is queued on it; entry points that return a status computed on
+ *     the GPU (pivot failures, refinement residuals, phi) synchronise it.
+ *   - Return value: HELM_OK (0) or a negative HELM_E* code; a description
+ *     of the last error on the calling thread is given by helm_last_error().
+ *     No exception crosses the ABI.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nx, nz;   /* nodes per row, number of rows */
+    double hx, hz;    /* grid spacings */
+} helm_grid;
+
+/* Opaque factorisation of one A(m, w); owns its device memory. */
+typedef struct helm_factor_s* helm_factor_t;
+
+typedef struct {
+    int32_t ir_iters;    /* refinement corrections applied (0 for a plain FP64 solve) */
+    double max_relres;   /* max over columns of ||b - A x||_2 / ||b||_2 (FP64), or -1 if not measured */
+    int32_t bad_block;   /* grid row j of the first failed pivot, -1 if none */
+    int32_t bad_row;     /* row inside that block, -1 if none */
+    int64_t solves;      /* right-hand sides solved by this call (forward + adjoint) */
+} helm_info;
+
+enum { HELM_FP64 = 0, HELM_FP32_IR = 1 };
+
+enum {
+    HELM_OK = 0,
+    HELM_EINVAL = -1,     /* bad argument: sizes, m_k <= 0 or NaN, node index out of range,
+                             source coinciding with a receiver, aliasing B and X */
+    HELM_ENOMEM = -2,     /* device allocation failed */
+    HELM_ESINGULAR = -3,  /* zero pivot in a diagonal tile of a Schur complement */
+    HELM_ENOCONV = -4,    /* refinement did not reach the tolerance in max iterations */
+    HELM_EDEVICE = -5     /* HIP runtime error */
+};
+
+/* ---- factorisation -------------------------------------------------------
+ * helm_factor: factor A(m, w) (App. A.1).  m_dev: nx*nz positive doubles
+ * (squared slowness, eq (disc_to_cont) with nodal basis), copied into the
+ * factor.  precision: HELM_FP64 (complex128 blocks) or HELM_FP32_IR
+ * (complex64 blocks; solves are refined in FP64 to `tol`).  On success *out
+ * owns ~nz*np^2*(16 or 8) bytes of HBM, np = nx rounded up to 16.
+ * Returns HELM_ESINGULAR with no factor if a tile pivot is exactly zero.
+ * Synchronises `stream`.                                                   */
+int helm_factor(const helm_grid* grid, const double* m_dev, double omega, int precision,
+                void* stream, helm_factor_t* out);
+
+/* helm_factor_batch: factor `count` independent systems together (their
+ * block chains advance in lockstep inside shared kernel launches).  Grids may
+ * differ.  outs[c] receives the factor of (grids[c], m_devs[c], omegas[c]).
+ * On failure no factor is returned.  Synchronises `stream`.               */
+int helm_factor_batch(int32_t count, const helm_grid* grids, const double* const* m_devs,
+                      const double* omegas, int precision, void* stream, helm_factor_t* outs);
+
+/* Bytes of HBM a factor of this grid and precision holds (for admission). */
+int helm_factor_bytes(const helm_grid* grid, int precision, size_t* bytes);
+
+void helm_factor_destroy(helm_factor_t f);
+
+/* ---- solves ----------------------------------------------------------------
+ * helm_solve: X = A^{-1} B for S columns (the wavefield of App. A.1,
+ * "Computing the wavefield", is the case B = e_s).  helm_adjoint_solve:
+ * L = A^{-*} R, the conjugate-transpose solve behind eq (lambda), reusing the
+ * same factors.  B/R and X/L: device complex128, column-major with leading
+ * dimension ld (>= nx*nz); X must not overlap B.  For an FP32 factor the
+ * result is refined in FP64 until max_s ||b_s - A x_s|| / ||b_s|| <= tol
+ * (tol <= 0 selects 1e-10), at most 10 corrections, else HELM_ENOCONV.  For
+ * an FP64 factor tol > 0 also measures the residual into info (and refines
+ * in FP64 if needed).  info may be NULL.  Synchronises when a residual is
+ * measured.                                                                 */
+int helm_solve(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, int64_t ld,
+               double tol, void* stream, helm_info* info);
+int helm_adjoint_solve(helm_factor_t f, const double* R_dev, double* L_dev, int32_t S, int64_t ld,
+                       double tol, void* stream, helm_info* info);
+
+/* helm_solve_batch: the same as helm_solve for `count` factors at once (the
+ * sweeps of all factors share kernel launches).  Bs/Xs/Ss/lds per factor.  */
+int helm_solve_batch(int32_t count, const helm_factor_t* fs, const double* const* B_devs,
+                     double* const* X_devs, const int32_t* S, const int64_t* ld, int adjoint,
+                     double tol, void* stream, helm_info* infos);
+
+/* ---- lower-level FWI objective and derivatives ---------------------------
+ * helm_misfit_grad: phi and grad phi of eq (phi)/(newphi) by the
+ * adjoint-state method (Thm A.1, algorithm "Computing phi, grad phi", App.
+ * B.1):  for every frequency w_f and source s,
+ *     u = A^{-1} e_s,  eps = d - R u,  lambda = A^{-*} R^* eps,
+ *     grad_k += -Re (w^2 d_k + b_k i w / (2 sqrt m_k)) u_k conj(lambda_k),
+ *     phi += |eps|^2 / 2,
+ * plus 1/2 m^T Gamma m and Gamma m with Gamma = alpha (Dx^T Dx + Dz^T Dz) +
+ * mu I (eqs (Gamma), (ThisGamma)).  Receivers and sources are grid nodes
+ * (R samples u at the node).  dobs_dev: complex128 [n_omega][S][Nr].
+ * omegas_host, src_host, rec_host: host arrays.  grad_dev: nx*nz doubles,
+ * overwritten.  *phi_host written on return (synchronises).               */
+int helm_misfit_grad(const helm_grid* grid, const double* m_dev, int32_t n_omega,
+                     const double* omegas_host, const double* dobs_dev, int32_t S,
+                     const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
+                     double alpha, double mu, int precision, double tol, void* stream,
+                     double* phi_host, double* grad_dev, helm_info* info);
+
+/* helm_gn_hvp: Gauss-Newton products (H^(1) + Gamma) mt_a for n_dir
+ * directions (lemma "Adjoint-state formula for multiplication by H^(1)",
+ * eqs (defv), (H1v)): per frequency and source
+ *     u = A^{-1} e_s,  g~ = (w^2 d + b i w/(2 sqrt m)) u,  v = A^{-1}(g~ mt),
+ *     z = A^{-*}(R^* R v),  (H^(1) mt)_j += Re g~_j conj(z_j).
+ * mt_dev: doubles [n_dir][nx*nz]; hv_dev: same shape, overwritten.         */
+int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega,
+                const double* omegas_host, int32_t S, const int32_t* src_host, int32_t Nr,
+                const int32_t* rec_host, int32_t n_dir, const double* mt_dev, double alpha,
+                double mu, int precision, double tol, void* stream, double* hv_dev,
+                helm_info* info);
+
+/* ---- building blocks exposed for tests and measurement ------------------ */
+
+/* r = B - A(m, w) X (FP64, five-point form of App. A.1) and, per column,
+ * ||r||_2^2 and ||B||_2^2 into norms_dev[2*s], norms_dev[2*s+1].  r_dev may
+ * be NULL (norms only).  adjoint != 0 uses A^* instead of A.               */
+int helm_residual(const helm_grid* grid, const double* m_dev, double omega, int adjoint,
+                  const double* B_dev, const double* X_dev, double* r_dev, int32_t S, int64_t ld,
+                  double* norms_dev, void* stream);
+
+/* Diagonal-tile Gauss-Jordan inverse (pivoting inside the tile) of `count`
+ * kb x kb complex128 matrices (kb in {16, 32}, row-major, contiguous): the
+ * building block of the block factorisation, exposed to test it alone.     */
+int helm_tile_inverse(int32_t count, int32_t kb, const double* A_dev, double* T_dev, void* stream);
+
+/* Lane-layout check of the matrix-core instruction used by the kernels:
+ * D = A(16x4) * B(4x16) in FP64 (prec 0) or FP32 (prec 1) on one wavefront. */
+int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* D_dev, void* stream);
+
+/* Number of kernel launches and right-hand-side solves issued since load. */
+int64_t helm_counter(int which);   /* 0 = launches, 1 = solves */
+
+const char* helm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

@@ -1,0 +1,808 @@
+// Host side of libhelm: factor handles, batched block-chain drivers, solves
+// with FP64 iterative refinement, and the misfit / gradient / Gauss-Newton
+// drivers.  Every arithmetic step runs in the kernels of helm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "helm.h"
+#include "helm_internal.h"
+
+using namespace helm;
+
+struct helm_factor_s {
+    helm_grid g;
+    int np;
+    int prec;
+    double omega;
+    void* G;       // nz * np * np complex (16 B for FP64, 8 B for FP32)
+    double* m;     // device copy of the model
+    size_t bytes;
+};
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<int64_t> g_launches{0}, g_solves{0};
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(x)                                                                      \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) return fail(HELM_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline hipStream_t S_(void* s) { return (hipStream_t)s; }
+inline int pad16(int n) { return (n + 15) / 16 * 16; }
+inline int64_t N_of(const helm_grid& g) { return (int64_t)g.nx * g.nz; }
+inline size_t elem_bytes(int prec) { return prec == HELM_FP32_IR ? 8 : 16; }
+
+size_t factor_bytes_of(const helm_grid& g, int prec) {
+    size_t np = (size_t)pad16(g.nx);
+    return np * np * (size_t)g.nz * elem_bytes(prec) + (size_t)N_of(g) * sizeof(double);
+}
+
+int check_grid(const helm_grid* g) {
+    if (!g) return fail(HELM_EINVAL, "grid is NULL");
+    if (g->nx < 2 || g->nz < 2) return fail(HELM_EINVAL, "grid needs nx >= 2 and nz >= 2");
+    if (g->nx > 8192 || (int64_t)g->nx * g->nz > (int64_t)1 << 30)
+        return fail(HELM_EINVAL, "grid too large");
+    if (!(g->hx > 0.0) || !(g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hz))
+        return fail(HELM_EINVAL, "grid spacings must be positive and finite");
+    return HELM_OK;
+}
+
+// stream-ordered scratch memory, released on scope exit (after the work that
+// uses it, in stream order)
+struct Scratch {
+    hipStream_t st;
+    std::vector<void*> ptrs;
+    explicit Scratch(hipStream_t s) : st(s) {}
+    ~Scratch() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, st);
+    }
+    template <typename T>
+    int get(T** out, size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMallocAsync(&p, bytes, st);
+        if (e != hipSuccess) return fail(HELM_ENOMEM, std::string("scratch allocation failed: ") + hipGetErrorString(e));
+        ptrs.push_back(p);
+        *out = (T*)p;
+        return HELM_OK;
+    }
+};
+
+// Pinned host staging for the small per-launch chain tables: a slot is only
+// rewritten after the copy that last used it has completed.
+struct PinnedRing {
+    static constexpr int NSLOT = 64;
+    static constexpr size_t SLOT = 4096;
+    char* host = nullptr;
+    hipEvent_t ev[NSLOT];
+    bool used[NSLOT] = {};
+    int next = 0;
+    std::mutex mu;
+    int upload(void* dev, const void* src, size_t bytes, hipStream_t st) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (bytes > SLOT) return fail(HELM_EINVAL, "chain table too large");
+        if (!host) {
+            if (hipHostMalloc((void**)&host, SLOT * NSLOT, hipHostMallocDefault) != hipSuccess) {
+                host = nullptr;
+                return fail(HELM_ENOMEM, "pinned staging allocation failed");
+            }
+            for (int q = 0; q < NSLOT; ++q) HIPCHECK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+        }
+        const int q = next;
+        next = (next + 1) % NSLOT;
+        if (used[q]) HIPCHECK(hipEventSynchronize(ev[q]));
+        std::memcpy(host + q * SLOT, src, bytes);
+        HIPCHECK(hipMemcpyAsync(dev, host + q * SLOT, bytes, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipEventRecord(ev[q], st));
+        used[q] = true;
+        return HELM_OK;
+    }
+};
+PinnedRing g_ring;
+
+Coef coef_of(const helm_factor_s* f) {
+    Coef c;
+    c.m = f->m;
+    c.omega = f->omega;
+    c.hx = f->g.hx;
+    c.hz = f->g.hz;
+    c.nx = f->g.nx;
+    c.nz = f->g.nz;
+    return c;
+}
+
+// m_k > 0 and finite for every node (m in R^M_+); synchronises
+int check_model(const double* m, int64_t n, hipStream_t st) {
+    Scratch sc(st);
+    int* flag;
+    int rc = sc.get(&flag, sizeof(int));
+    if (rc) return rc;
+    launch_zero(flag, sizeof(int), st);
+    launch_check_model(m, n, flag, st);
+    g_launches += 2;
+    int h = 0;
+    HIPCHECK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (h) return fail(HELM_EINVAL, "model must be finite and positive at every node");
+    return HELM_OK;
+}
+
+// ------------------------------------------------------------ factorisation --
+// Factor a group of at most MAXB chains of one precision in lockstep.
+int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
+    const bool fp32 = fs[0]->prec == HELM_FP32_IR;
+    const size_t es = elem_bytes(fs[0]->prec);
+    Scratch sc(st);
+    std::vector<ChainInfo> tab(n);
+    int ptot = 0, utot = 0, itot = 0, Tmax = 0;
+    size_t buf = 0;
+    for (int c = 0; c < n; ++c) buf += 2 * (size_t)fs[c]->np * KB * es + 64;
+    char* arena;
+    int rc = sc.get(&arena, buf);
+    if (rc) return rc;
+    int* status;
+    if ((rc = sc.get(&status, sizeof(int) * 4 * n))) return rc;
+    launch_zero(status, sizeof(int) * 4 * n, st);
+    size_t off = 0;
+    for (int c = 0; c < n; ++c) {
+        helm_factor_s* f = fs[c];
+        ChainInfo& ci = tab[c];
+        ci.G = f->G;
+        ci.W = arena + off;
+        off += (size_t)f->np * KB * es;
+        ci.Vt = arena + off;
+        off += (size_t)f->np * KB * es;
+        off = (off + 63) / 64 * 64;
+        ci.status = status + 4 * c;
+        ci.cf = coef_of(f);
+        ci.np = f->np;
+        ci.npan = (f->np + KB - 1) / KB;
+        ci.T = ci.npan * f->g.nz;
+        ci.ptile0 = ptot;
+        ptot += (f->np + PR - 1) / PR;
+        const int tx = (f->np + TILE - 1) / TILE;
+        ci.utile0 = utot;
+        utot += tx * tx;
+        ci.itile0 = itot;
+        itot += (int)(((int64_t)f->np * f->np + 255) / 256);
+        Tmax = std::max(Tmax, ci.T);
+    }
+    ChainInfo* dtab;
+    if ((rc = sc.get(&dtab, sizeof(ChainInfo) * n))) return rc;
+    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(ChainInfo) * n, st))) return rc;
+    launch_init_block0(dtab, n, itot, fp32, st);
+    for (int t = 0; t < Tmax; ++t) {
+        launch_panel(dtab, n, t, ptot, fp32, st);
+        launch_update(dtab, n, t, utot, fp32, st);
+    }
+    g_launches += 2 + 2 * (int64_t)Tmax;
+    HIPCHECK(hipGetLastError());
+    std::vector<int> hs(4 * n);
+    HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * 4 * n, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < n; ++c)
+        if (hs[4 * c])
+            return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: chain " + std::to_string(c) + ", block " +
+                                            std::to_string(hs[4 * c + 1]) + ", row " + std::to_string(hs[4 * c + 2]));
+    return HELM_OK;
+}
+
+void destroy(helm_factor_s* f) {
+    if (!f) return;
+    if (f->G) (void)hipFree(f->G);
+    if (f->m) (void)hipFree(f->m);
+    delete f;
+}
+
+int factor_many(int count, const helm_grid* grids, const double* const* m_devs, const double* omegas, int prec,
+                hipStream_t st, helm_factor_t* outs) {
+    if (count <= 0 || !grids || !m_devs || !omegas || !outs) return fail(HELM_EINVAL, "bad batch arguments");
+    if (prec != HELM_FP64 && prec != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
+    for (int c = 0; c < count; ++c) {
+        int rc = check_grid(&grids[c]);
+        if (rc) return rc;
+        if (!m_devs[c]) return fail(HELM_EINVAL, "model pointer is NULL");
+        if (!std::isfinite(omegas[c]) || omegas[c] < 0.0) return fail(HELM_EINVAL, "omega must be finite and >= 0");
+        if ((rc = check_model(m_devs[c], N_of(grids[c]), st))) return rc;
+    }
+    std::vector<helm_factor_s*> fs(count, nullptr);
+    auto cleanup = [&]() {
+        for (auto* f : fs) destroy(f);
+    };
+    for (int c = 0; c < count; ++c) {
+        helm_factor_s* f = new helm_factor_s();
+        fs[c] = f;
+        f->g = grids[c];
+        f->np = pad16(grids[c].nx);
+        f->prec = prec;
+        f->omega = omegas[c];
+        f->bytes = factor_bytes_of(grids[c], prec);
+        size_t gb = (size_t)f->np * f->np * (size_t)grids[c].nz * elem_bytes(prec);
+        if (hipMalloc(&f->G, gb) != hipSuccess) {
+            f->G = nullptr;
+            cleanup();
+            return fail(HELM_ENOMEM, "factor allocation of " + std::to_string(gb) + " bytes failed");
+        }
+        if (hipMalloc((void**)&f->m, sizeof(double) * N_of(grids[c])) != hipSuccess) {
+            f->m = nullptr;
+            cleanup();
+            return fail(HELM_ENOMEM, "model copy allocation failed");
+        }
+        if (hipMemcpyAsync(f->m, m_devs[c], sizeof(double) * N_of(grids[c]), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess) {
+            cleanup();
+            return fail(HELM_EDEVICE, "model copy failed");
+        }
+    }
+    for (int c0 = 0; c0 < count; c0 += MAXB) {
+        int rc = factor_group(fs.data() + c0, std::min(MAXB, count - c0), st);
+        if (rc) {
+            cleanup();
+            return rc;
+        }
+    }
+    for (int c = 0; c < count; ++c) outs[c] = fs[c];
+    return HELM_OK;
+}
+
+// ----------------------------------------------------------------- sweeps --
+// X = A^{-1} Y for a group of factors of one precision: forward then
+// backward block sweep.  FP64: Y, X complex128; FP32: complex64.  With
+// conj_b the forward sweep reads conj(Y) (the adjoint solve A^{-*} r =
+// conj(A^{-1} conj r); the caller conjugates the result).
+int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const int64_t* ldy, void* const* Xs,
+                const int64_t* ldx, const int* Ss, bool conj_b, hipStream_t st) {
+    const bool fp32 = fs[0]->prec == HELM_FP32_IR;
+    Scratch sc(st);
+    std::vector<SweepInfo> tab(n);
+    int tot = 0, steps = 0;
+    for (int c = 0; c < n; ++c) {
+        const helm_factor_s* f = fs[c];
+        SweepInfo& si = tab[c];
+        si.G = f->G;
+        si.B = Ys[c];
+        si.X = Xs[c];
+        si.ldb = ldy[c];
+        si.ldx = ldx[c];
+        si.S = Ss[c];
+        si.nx = f->g.nx;
+        si.nz = f->g.nz;
+        si.np = f->np;
+        si.cz = f->g.hx / f->g.hz;
+        si.tiles_s = (Ss[c] + 15) / 16;
+        si.tile0 = tot;
+        tot += (f->np / 16) * si.tiles_s;
+        steps = std::max(steps, f->g.nz);
+        g_solves += Ss[c];
+    }
+    SweepInfo* dtab;
+    int rc = sc.get(&dtab, sizeof(SweepInfo) * n);
+    if (rc) return rc;
+    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * n, st))) return rc;
+    for (int t = 0; t < steps; ++t) launch_sweep(dtab, n, t, tot, fp32, true, conj_b, st);
+    for (int t = 0; t + 1 < steps; ++t) launch_sweep(dtab, n, t, tot, fp32, false, false, st);
+    g_launches += 2 * (int64_t)steps - 1;
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+struct SolveJob {
+    helm_factor_s* f;
+    const double* B;   // complex128, column-major, ld
+    double* X;
+    int S;
+    int64_t ld;
+    helm_info* info;
+};
+
+// residual norms: max over columns of ||B - A X|| / ||B||; optionally writes
+// r (complex128, ld N) and/or its complex64 copy (conjugated when adjoint)
+int residual_norms(const helm_factor_s* f, int adjoint, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                   double* R, float* R32, int S, hipStream_t st, double* maxrel) {
+    Scratch sc(st);
+    const int64_t N = N_of(f->g);
+    const int nblk = (int)((N + 255) / 256);
+    double *partial, *norms;
+    int rc = sc.get(&partial, sizeof(double) * 2 * (size_t)nblk * S);
+    if (rc) return rc;
+    if ((rc = sc.get(&norms, sizeof(double) * 2 * S))) return rc;
+    launch_residual(coef_of(f), adjoint, B, ldb, X, ldx, R, N, R32, S, partial, nblk, st);
+    launch_norms_finish(partial, nblk, S, norms, st);
+    g_launches += 2;
+    std::vector<double> h(2 * S);
+    HIPCHECK(hipMemcpyAsync(h.data(), norms, sizeof(double) * 2 * S, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (int s = 0; s < S; ++s) {
+        double rr = std::sqrt(h[2 * s]), bb = std::sqrt(h[2 * s + 1]);
+        double rel = bb > 0.0 ? rr / bb : (rr > 0.0 ? INFINITY : 0.0);
+        if (!(rel <= mx)) mx = rel;   // NaN propagates
+    }
+    *maxrel = mx;
+    return HELM_OK;
+}
+
+constexpr int MAX_IR = 10;
+
+// Solve a group of jobs that share one precision.
+int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_t st) {
+    const int n = (int)jobs.size();
+    if (n == 0) return HELM_OK;
+    const bool fp32 = jobs[0].f->prec == HELM_FP32_IR;
+    for (auto& jb : jobs) {
+        if (jb.info) {
+            jb.info->ir_iters = 0;
+            jb.info->max_relres = -1.0;
+            jb.info->bad_block = -1;
+            jb.info->bad_row = -1;
+            jb.info->solves = 0;
+        }
+    }
+    std::vector<helm_factor_s*> fs(n);
+    for (int c = 0; c < n; ++c) fs[c] = jobs[c].f;
+    if (!fp32) {
+        std::vector<const void*> Ys(n);
+        std::vector<void*> Xs(n);
+        std::vector<int64_t> ldy(n), ldx(n);
+        std::vector<int> Ss(n);
+        for (int c = 0; c < n; ++c) {
+            Ys[c] = jobs[c].B;
+            Xs[c] = jobs[c].X;
+            ldy[c] = ldx[c] = jobs[c].ld;
+            Ss[c] = jobs[c].S;
+        }
+        for (int c0 = 0; c0 < n; c0 += MAXB) {
+            int k = std::min(MAXB, n - c0);
+            int rc = sweep_group(fs.data() + c0, k, Ys.data() + c0, ldy.data() + c0, Xs.data() + c0, ldx.data() + c0,
+                                 Ss.data() + c0, adjoint, st);
+            if (rc) return rc;
+        }
+        for (int c = 0; c < n; ++c) {
+            if (adjoint) {
+                launch_conj_inplace(jobs[c].X, jobs[c].ld, N_of(jobs[c].f->g), jobs[c].S, st);
+                g_launches += 1;
+            }
+            if (jobs[c].info) jobs[c].info->solves = jobs[c].S;
+        }
+        if (tol <= 0.0) return HELM_OK;
+        // measure, and refine in FP64 if the residual is above tol
+        for (int c = 0; c < n; ++c) {
+            SolveJob& jb = jobs[c];
+            const int64_t N = N_of(jb.f->g);
+            Scratch sc(st);
+            double *R = nullptr, *D = nullptr;
+            int it = 0;
+            double rel = 0.0;
+            for (;;) {
+                if (!R) {
+                    int rc = sc.get(&R, sizeof(double) * 2 * (size_t)N * jb.S);
+                    if (rc) return rc;
+                }
+                int rc = residual_norms(jb.f, adjoint, jb.B, jb.ld, jb.X, jb.ld, R, nullptr, jb.S, st, &rel);
+                if (rc) return rc;
+                if (rel <= tol || it >= MAX_IR) break;
+                if (!D && (rc = sc.get(&D, sizeof(double) * 2 * (size_t)N * jb.S))) return rc;
+                helm_factor_s* f1[1] = {jb.f};
+                const void* y1[1] = {R};
+                void* x1[1] = {D};
+                int64_t l1[1] = {N};
+                int s1[1] = {jb.S};
+                if ((rc = sweep_group(f1, 1, y1, l1, x1, l1, s1, adjoint, st))) return rc;
+                if (adjoint) launch_conj_inplace(D, N, N, jb.S, st);
+                launch_axpy_c128(D, N, jb.X, jb.ld, N, jb.S, st);
+                g_launches += 2;
+                ++it;
+            }
+            if (jb.info) {
+                jb.info->ir_iters = it;
+                jb.info->max_relres = rel;
+                jb.info->solves = (int64_t)jb.S * (1 + it);
+            }
+            if (!(rel <= tol))
+                return fail(HELM_ENOCONV, "FP64 solve residual " + std::to_string(rel) + " above tolerance");
+        }
+        return HELM_OK;
+    }
+    // FP32 factor: solve in complex64, refine in FP64
+    if (tol <= 0.0) tol = 1e-10;
+    Scratch sc(st);
+    std::vector<float*> Y32(n), X32(n);
+    std::vector<double*> R64(n);
+    for (int c = 0; c < n; ++c) {
+        const int64_t N = N_of(jobs[c].f->g);
+        size_t bytes32 = sizeof(float) * 2 * (size_t)N * jobs[c].S;
+        int rc = sc.get(&Y32[c], bytes32);
+        if (rc) return rc;
+        if ((rc = sc.get(&X32[c], bytes32))) return rc;
+        if ((rc = sc.get(&R64[c], sizeof(double) * 2 * (size_t)N * jobs[c].S))) return rc;
+        launch_c128_to_c64(jobs[c].B, jobs[c].ld, Y32[c], N, N, jobs[c].S, adjoint ? 1 : 0, st);
+        g_launches += 1;
+    }
+    std::vector<int> active(n, 1), iters(n, 0);
+    std::vector<double> rels(n, 0.0);
+    bool first = true;
+    for (int round = 0;; ++round) {
+        std::vector<helm_factor_s*> af;
+        std::vector<const void*> ay;
+        std::vector<void*> ax;
+        std::vector<int64_t> al;
+        std::vector<int> as, idx;
+        for (int c = 0; c < n; ++c)
+            if (active[c]) {
+                af.push_back(fs[c]);
+                ay.push_back(Y32[c]);
+                ax.push_back(X32[c]);
+                al.push_back(N_of(fs[c]->g));
+                as.push_back(jobs[c].S);
+                idx.push_back(c);
+            }
+        if (af.empty()) break;
+        for (size_t c0 = 0; c0 < af.size(); c0 += MAXB) {
+            int k = (int)std::min<size_t>(MAXB, af.size() - c0);
+            int rc = sweep_group(af.data() + c0, k, ay.data() + c0, al.data() + c0, ax.data() + c0, al.data() + c0,
+                                 as.data() + c0, false, st);
+            if (rc) return rc;
+        }
+        for (int c : idx) {
+            const int64_t N = N_of(fs[c]->g);
+            // x (+)= conj?(y32); r = b - A x; y32 = conj?(r) for the next correction
+            launch_c64_to_c128(X32[c], N, jobs[c].X, jobs[c].ld, N, jobs[c].S, adjoint ? 1 : 0, first ? 0 : 1, st);
+            g_launches += 1;
+            if (!first) iters[c] += 1;
+            double rel = 0.0;
+            int rc = residual_norms(fs[c], adjoint, jobs[c].B, jobs[c].ld, jobs[c].X, jobs[c].ld, R64[c], Y32[c],
+                                    jobs[c].S, st, &rel);
+            if (rc) return rc;
+            rels[c] = rel;
+            if (rel <= tol) active[c] = 0;
+            else if (iters[c] >= MAX_IR) active[c] = 0;
+        }
+        first = false;
+    }
+    int worst = HELM_OK;
+    for (int c = 0; c < n; ++c) {
+        if (jobs[c].info) {
+            jobs[c].info->ir_iters = iters[c];
+            jobs[c].info->max_relres = rels[c];
+            jobs[c].info->solves = (int64_t)jobs[c].S * (1 + iters[c]);
+        }
+        if (!(rels[c] <= tol)) worst = fail(HELM_ENOCONV, "refinement stopped at relative residual " +
+                                                              std::to_string(rels[c]) + " > " + std::to_string(tol));
+    }
+    return worst;
+}
+
+// host -> device copy of caller-owned host data, complete on return
+int upload_sync(void* dev, const void* src, size_t bytes, hipStream_t st) {
+    HIPCHECK(hipMemcpyAsync(dev, src, bytes, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+}
+
+int check_solve_args(const helm_factor_s* f, const double* B, double* X, int S, int64_t ld) {
+    if (!f) return fail(HELM_EINVAL, "factor is NULL");
+    if (!B || !X) return fail(HELM_EINVAL, "NULL right-hand side or solution pointer");
+    if (S <= 0) return fail(HELM_EINVAL, "S must be positive");
+    const int64_t N = N_of(f->g);
+    if (ld < N) return fail(HELM_EINVAL, "ld must be >= nx*nz");
+    const char* b0 = (const char*)B;
+    const char* b1 = b0 + 16 * ((size_t)(S - 1) * ld + N);
+    const char* x0 = (const char*)X;
+    const char* x1 = x0 + 16 * ((size_t)(S - 1) * ld + N);
+    if (x0 < b1 && b0 < x1) return fail(HELM_EINVAL, "X must not overlap B");
+    return HELM_OK;
+}
+
+int check_nodes(const int32_t* nodes, int count, int64_t N, const char* what) {
+    if (count > 0 && !nodes) return fail(HELM_EINVAL, std::string(what) + " list is NULL");
+    for (int q = 0; q < count; ++q)
+        if (nodes[q] < 0 || nodes[q] >= N)
+            return fail(HELM_EINVAL, std::string(what) + " node index out of range");
+    return HELM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI ==
+extern "C" {
+
+const char* helm_last_error(void) { return g_err.c_str(); }
+
+int64_t helm_counter(int which) { return which == 0 ? g_launches.load() : g_solves.load(); }
+
+int helm_factor_bytes(const helm_grid* grid, int precision, size_t* bytes) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!bytes) return fail(HELM_EINVAL, "bytes is NULL");
+    if (precision != HELM_FP64 && precision != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
+    *bytes = factor_bytes_of(*grid, precision);
+    return HELM_OK;
+}
+
+int helm_factor(const helm_grid* grid, const double* m_dev, double omega, int precision, void* stream,
+                helm_factor_t* out) {
+    if (!grid) return fail(HELM_EINVAL, "grid is NULL");
+    const double* ms[1] = {m_dev};
+    return factor_many(1, grid, ms, &omega, precision, S_(stream), out);
+}
+
+int helm_factor_batch(int32_t count, const helm_grid* grids, const double* const* m_devs, const double* omegas,
+                      int precision, void* stream, helm_factor_t* outs) {
+    return factor_many(count, grids, m_devs, omegas, precision, S_(stream), outs);
+}
+
+void helm_factor_destroy(helm_factor_t f) {
+    if (f) (void)hipDeviceSynchronize();
+    destroy(f);
+}
+
+int helm_solve(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, int64_t ld, double tol, void* stream,
+               helm_info* info) {
+    int rc = check_solve_args(f, B_dev, X_dev, S, ld);
+    if (rc) return rc;
+    std::vector<SolveJob> jobs{{f, B_dev, X_dev, S, ld, info}};
+    return solve_jobs(jobs, false, tol, S_(stream));
+}
+
+int helm_adjoint_solve(helm_factor_t f, const double* R_dev, double* L_dev, int32_t S, int64_t ld, double tol,
+                       void* stream, helm_info* info) {
+    int rc = check_solve_args(f, R_dev, L_dev, S, ld);
+    if (rc) return rc;
+    std::vector<SolveJob> jobs{{f, R_dev, L_dev, S, ld, info}};
+    return solve_jobs(jobs, true, tol, S_(stream));
+}
+
+int helm_solve_batch(int32_t count, const helm_factor_t* fs, const double* const* B_devs, double* const* X_devs,
+                     const int32_t* S, const int64_t* ld, int adjoint, double tol, void* stream, helm_info* infos) {
+    if (count <= 0 || !fs || !B_devs || !X_devs || !S || !ld) return fail(HELM_EINVAL, "bad batch arguments");
+    std::vector<SolveJob> j64, j32;
+    for (int c = 0; c < count; ++c) {
+        int rc = check_solve_args(fs[c], B_devs[c], X_devs[c], S[c], ld[c]);
+        if (rc) return rc;
+        SolveJob jb{fs[c], B_devs[c], X_devs[c], S[c], ld[c], infos ? &infos[c] : nullptr};
+        (fs[c]->prec == HELM_FP32_IR ? j32 : j64).push_back(jb);
+    }
+    int rc = solve_jobs(j64, adjoint != 0, tol, S_(stream));
+    if (rc) return rc;
+    return solve_jobs(j32, adjoint != 0, tol, S_(stream));
+}
+
+int helm_residual(const helm_grid* grid, const double* m_dev, double omega, int adjoint, const double* B_dev,
+                  const double* X_dev, double* r_dev, int32_t S, int64_t ld, double* norms_dev, void* stream) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!m_dev || !B_dev || !X_dev || !norms_dev || S <= 0 || ld < N_of(*grid))
+        return fail(HELM_EINVAL, "bad residual arguments");
+    hipStream_t st = S_(stream);
+    Scratch sc(st);
+    const int64_t N = N_of(*grid);
+    const int nblk = (int)((N + 255) / 256);
+    double* partial;
+    if ((rc = sc.get(&partial, sizeof(double) * 2 * (size_t)nblk * S))) return rc;
+    Coef cf{m_dev, omega, grid->hx, grid->hz, grid->nx, grid->nz};
+    // r is written with leading dimension ld when requested
+    launch_residual(cf, adjoint, B_dev, ld, X_dev, ld, r_dev, ld, nullptr, S, partial, nblk, st);
+    launch_norms_finish(partial, nblk, S, norms_dev, st);
+    g_launches += 2;
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int helm_misfit_grad(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host,
+                     const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
+                     double alpha, double mu, int precision, double tol, void* stream, double* phi_host,
+                     double* grad_dev, helm_info* info) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (n_omega <= 0 || S <= 0 || Nr <= 0 || !omegas_host || !dobs_dev || !phi_host || !grad_dev || !m_dev)
+        return fail(HELM_EINVAL, "bad misfit_grad arguments");
+    const int64_t N = N_of(*grid);
+    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
+    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
+    for (int s = 0; s < S; ++s)
+        for (int p = 0; p < Nr; ++p)
+            if (src_host[s] == rec_host[p]) return fail(HELM_EINVAL, "a source coincides with a receiver");
+    hipStream_t st = S_(stream);
+    std::vector<helm_grid> grids(n_omega, *grid);
+    std::vector<const double*> ms(n_omega, m_dev);
+    std::vector<helm_factor_t> F(n_omega, nullptr);
+    if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, F.data()))) return rc;
+    struct Guard {
+        std::vector<helm_factor_t>& F;
+        ~Guard() {
+            for (auto f : F) destroy(f);
+        }
+    } guard{F};
+    Scratch sc(st);
+    int *dsrc, *drec;
+    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
+    if ((rc = sc.get(&drec, sizeof(int) * Nr))) return rc;
+    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
+    if ((rc = upload_sync(drec, rec_host, sizeof(int) * Nr, st))) return rc;
+    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
+    double *E, *eps, *phip;
+    std::vector<double*> U(n_omega), L(n_omega), Radj(n_omega);
+    if ((rc = sc.get(&E, fb))) return rc;
+    if ((rc = sc.get(&eps, sizeof(double) * 2 * (size_t)Nr * S * n_omega))) return rc;
+    if ((rc = sc.get(&phip, sizeof(double) * (size_t)S * n_omega + 8))) return rc;
+    for (int w = 0; w < n_omega; ++w) {
+        if ((rc = sc.get(&U[w], fb))) return rc;
+        if ((rc = sc.get(&L[w], fb))) return rc;
+        if ((rc = sc.get(&Radj[w], fb))) return rc;
+    }
+    launch_unit_sources(E, N, N, dsrc, S, st);
+    // forward wavefields u = A^{-1} e_s for all frequencies
+    std::vector<SolveJob> jobs;
+    std::vector<helm_info> infos(n_omega);
+    for (int w = 0; w < n_omega; ++w) jobs.push_back({F[w], E, U[w], S, N, &infos[w]});
+    if ((rc = solve_jobs(jobs, false, precision == HELM_FP32_IR ? tol : tol, st))) return rc;
+    // residuals at the receivers, phi, and the adjoint sources R^* eps
+    for (int w = 0; w < n_omega; ++w) {
+        launch_misfit(U[w], N, dobs_dev + 2 * (size_t)w * S * Nr, drec, Nr, S, eps + 2 * (size_t)w * S * Nr,
+                      phip + (size_t)w * S, st);
+        launch_zero(Radj[w], fb, st);
+        launch_scatter_adj(eps + 2 * (size_t)w * S * Nr, drec, Nr, S, Radj[w], N, st);
+        g_launches += 3;
+    }
+    // adjoint wavefields lambda = A^{-*} R^* eps
+    std::vector<SolveJob> ajobs;
+    std::vector<helm_info> ainfos(n_omega);
+    for (int w = 0; w < n_omega; ++w) ajobs.push_back({F[w], Radj[w], L[w], S, N, &ainfos[w]});
+    if ((rc = solve_jobs(ajobs, true, tol, st))) return rc;
+    launch_zero(grad_dev, sizeof(double) * N, st);
+    for (int w = 0; w < n_omega; ++w) launch_grad(coef_of(F[w]), U[w], N, L[w], N, S, grad_dev, st);
+    g_launches += 1 + n_omega;
+    double reg = 0.0;
+    if (alpha != 0.0 || mu != 0.0) {
+        const int nblk = (int)((N + 255) / 256);
+        double *part, *q;
+        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
+        if ((rc = sc.get(&q, sizeof(double)))) return rc;
+        launch_gamma(m_dev, grid->nx, grid->nz, alpha, mu, grad_dev, part, nblk, st);
+        launch_sum_scalar(part, nblk, q, st);
+        g_launches += 2;
+        HIPCHECK(hipMemcpyAsync(&reg, q, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    std::vector<double> hp((size_t)S * n_omega);
+    HIPCHECK(hipMemcpyAsync(hp.data(), phip, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double phi = 0.0;
+    for (double v : hp) phi += v;
+    *phi_host = phi + 0.5 * reg;
+    if (info) {
+        info->ir_iters = 0;
+        info->max_relres = 0.0;
+        info->bad_block = info->bad_row = -1;
+        info->solves = 0;
+        for (int w = 0; w < n_omega; ++w) {
+            info->ir_iters = std::max(info->ir_iters, std::max(infos[w].ir_iters, ainfos[w].ir_iters));
+            info->max_relres = std::max(info->max_relres, std::max(infos[w].max_relres, ainfos[w].max_relres));
+            info->solves += infos[w].solves + ainfos[w].solves;
+        }
+    }
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host, int32_t S,
+                const int32_t* src_host, int32_t Nr, const int32_t* rec_host, int32_t n_dir, const double* mt_dev,
+                double alpha, double mu, int precision, double tol, void* stream, double* hv_dev, helm_info* info) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (n_omega <= 0 || S <= 0 || Nr <= 0 || n_dir <= 0 || !omegas_host || !mt_dev || !hv_dev || !m_dev)
+        return fail(HELM_EINVAL, "bad gn_hvp arguments");
+    const int64_t N = N_of(*grid);
+    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
+    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
+    hipStream_t st = S_(stream);
+    std::vector<helm_grid> grids(n_omega, *grid);
+    std::vector<const double*> ms(n_omega, m_dev);
+    std::vector<helm_factor_t> F(n_omega, nullptr);
+    if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, F.data()))) return rc;
+    struct Guard {
+        std::vector<helm_factor_t>& F;
+        ~Guard() {
+            for (auto f : F) destroy(f);
+        }
+    } guard{F};
+    Scratch sc(st);
+    int *dsrc, *drec;
+    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
+    if ((rc = sc.get(&drec, sizeof(int) * Nr))) return rc;
+    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
+    if ((rc = upload_sync(drec, rec_host, sizeof(int) * Nr, st))) return rc;
+    const int cols = n_dir * S;
+    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
+    const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
+    double *E, *U, *Vr, *V, *RV, *Z;
+    if ((rc = sc.get(&E, fb))) return rc;
+    if ((rc = sc.get(&U, fb))) return rc;
+    if ((rc = sc.get(&Vr, vb))) return rc;
+    if ((rc = sc.get(&V, vb))) return rc;
+    if ((rc = sc.get(&RV, vb))) return rc;
+    if ((rc = sc.get(&Z, vb))) return rc;
+    launch_unit_sources(E, N, N, dsrc, S, st);
+    launch_zero(hv_dev, sizeof(double) * N * n_dir, st);
+    g_launches += 2;
+    int64_t solves = 0;
+    int ir = 0;
+    double worst = 0.0;
+    for (int w = 0; w < n_omega; ++w) {
+        helm_info i1, i2, i3;
+        std::vector<SolveJob> j1{{F[w], E, U, S, N, &i1}};
+        if ((rc = solve_jobs(j1, false, tol, st))) return rc;
+        launch_gn_rhs(coef_of(F[w]), U, N, S, mt_dev, n_dir, Vr, N, st);
+        std::vector<SolveJob> j2{{F[w], Vr, V, cols, N, &i2}};
+        if ((rc = solve_jobs(j2, false, tol, st))) return rc;
+        launch_zero(RV, vb, st);
+        launch_sample_scatter(V, N, drec, Nr, cols, RV, N, st);
+        std::vector<SolveJob> j3{{F[w], RV, Z, cols, N, &i3}};
+        if ((rc = solve_jobs(j3, true, tol, st))) return rc;
+        launch_hv(coef_of(F[w]), U, N, S, Z, N, n_dir, hv_dev, N, st);
+        g_launches += 4;
+        solves += i1.solves + i2.solves + i3.solves;
+        ir = std::max(ir, std::max(i1.ir_iters, std::max(i2.ir_iters, i3.ir_iters)));
+        worst = std::max(worst, std::max(i1.max_relres, std::max(i2.max_relres, i3.max_relres)));
+    }
+    if (alpha != 0.0 || mu != 0.0) {
+        const int nblk = (int)((N + 255) / 256);
+        double* part;
+        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
+        for (int a = 0; a < n_dir; ++a)
+            launch_gamma(mt_dev + (size_t)a * N, grid->nx, grid->nz, alpha, mu, hv_dev + (size_t)a * N, part, nblk,
+                         st);
+        g_launches += n_dir;
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    if (info) {
+        info->ir_iters = ir;
+        info->max_relres = worst;
+        info->bad_block = info->bad_row = -1;
+        info->solves = solves;
+    }
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int helm_tile_inverse(int32_t count, int32_t kb, const double* A_dev, double* T_dev, void* stream) {
+    if (count <= 0 || (kb != 16 && kb != 32) || !A_dev || !T_dev) return fail(HELM_EINVAL, "bad tile arguments");
+    hipStream_t st = S_(stream);
+    Scratch sc(st);
+    int* status;
+    int rc = sc.get(&status, sizeof(int) * count);
+    if (rc) return rc;
+    launch_zero(status, sizeof(int) * count, st);
+    launch_tile_inverse(count, kb, A_dev, T_dev, status, st);
+    g_launches += 2;
+    std::vector<int> h(count);
+    HIPCHECK(hipMemcpyAsync(h.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < count; ++c)
+        if (h[c]) return fail(HELM_ESINGULAR, "zero pivot in tile " + std::to_string(c));
+    return HELM_OK;
+}
+
+int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* D_dev, void* stream) {
+    if ((prec != 0 && prec != 1) || !A_dev || !B_dev || !D_dev) return fail(HELM_EINVAL, "bad probe arguments");
+    launch_mfma_probe(prec, A_dev, B_dev, D_dev, S_(stream));
+    g_launches += 1;
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+}  // extern "C"

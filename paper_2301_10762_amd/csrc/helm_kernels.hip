@@ -1,0 +1,885 @@
+// HIP kernels of libhelm for gfx950 (CDNA4).
+//
+// The discrete operator (App. A.1 of arXiv 2301.10762) is
+//     A(m, w) = S - w^2 diag(d m) - i w diag(b sqrt m),
+// with S the five-point stiffness (x-edge coupling hz/hx, z-edge coupling
+// hx/hz, halved on boundary edges), d the nodal mass weights (hx*hz, halved
+// per boundary direction) and b the boundary-edge weights.  Grouping the
+// unknowns by grid row j makes A block tridiagonal: diagonal blocks A_j are
+// tridiagonal n_x x n_x, the couplings between rows are E = diag(e),
+// e_i = -(hx/hz) (halved at i = 0, nx-1).
+//
+// Block LU with explicit Schur-complement inverses:
+//     D_0 = A_0,  G_j = D_j^{-1},  D_{j+1} = A_{j+1} - E G_j E,
+// forward sweep  w_j = G_j (b_j - E w_{j-1}),
+// backward sweep x_j = w_j - G_j E x_{j+1}.
+// G_j is computed in place by block Gauss-Jordan with pivoting inside each
+// kb x kb diagonal tile: per panel K, T = (A_KK)^{-1} and
+//     A <- A' + W V,  W = [-A_{:,K} T ; T - I],  V = [A_{K,:} with V_KK = I],
+// A' = A with the K columns cleared (A'_KK = I).
+// Blocks are padded to np = nx rounded up to 16 with an identity tail.
+//
+// Dense contractions (the rank-kb update and the sweeps) run on the matrix
+// cores: v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32, complex products as
+// four real products.  Lane l supplies A[l%16][k] and B[k][l%16] with the
+// k index owned by lane group l/16; each lane loads four consecutive k of
+// its row/column (64 contiguous bytes) and feeds them to four successive
+// instructions, so every operand load is a contiguous vector load.
+#include "helm_internal.h"
+
+namespace helm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct CT;
+template <> struct CT<double> { using c = double2; using v4 = v4d; };
+template <> struct CT<float> { using c = float2; using v4 = v4f; };
+
+template <typename C> __device__ __forceinline__ C mk(double re, double im) { C r; r.x = re; r.y = im; return r; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cscale(C a, double s) { return mk<C>(a.x * s, a.y * s); }
+template <typename C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
+template <typename C> __device__ __forceinline__ C cinv(C a) {
+    // 1/a with the larger component factored out (Smith's scaling)
+    if (fabs((double)a.x) >= fabs((double)a.y)) {
+        double r = (double)a.y / (double)a.x, den = (double)a.x + (double)a.y * r;
+        return mk<C>(1.0 / den, -r / den);
+    } else {
+        double r = (double)a.x / (double)a.y, den = (double)a.x * r + (double)a.y;
+        return mk<C>(r / den, -1.0 / den);
+    }
+}
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 result held in accumulator element e by lane group g
+// (lanes 16g .. 16g+15 hold columns 0..15): the FP64 instruction interleaves
+// the rows (g + 4e), the FP32 one keeps them contiguous (4g + e).
+template <typename T> __device__ __forceinline__ int acc_row(int g, int e);
+template <> __device__ __forceinline__ int acc_row<double>(int g, int e) { return g + 4 * e; }
+template <> __device__ __forceinline__ int acc_row<float>(int g, int e) { return 4 * g + e; }
+
+// (cr + i ci) += (ar + i ai)(br + i bi) for one 16x16x4 block
+template <typename T, typename V>
+__device__ __forceinline__ void cmfma(V& cr, V& ci, T ar, T ai, T br, T bi) {
+    cr = mfma16(ar, br, cr);
+    cr = mfma16(-ai, bi, cr);
+    ci = mfma16(ar, bi, ci);
+    ci = mfma16(ai, br, ci);
+}
+
+// ---------------------------------------------------------------- assembly --
+__device__ __forceinline__ double half_at_ends(int idx, int n) { return (idx == 0 || idx == n - 1) ? 0.5 : 1.0; }
+__device__ __forceinline__ double x_coupling(const Coef& c, int j) { return (c.hz / c.hx) * half_at_ends(j, c.nz); }
+__device__ __forceinline__ double z_coupling(const Coef& c, int i) { return (c.hx / c.hz) * half_at_ends(i, c.nx); }
+
+// A(m, w) at node (i, j), diagonal entry
+__device__ __forceinline__ double2 diag_entry(const Coef& c, int i, int j) {
+    double cx = x_coupling(c, j), cz = z_coupling(c, i);
+    double s = 0.0;
+    if (i > 0) s += cx;
+    if (i < c.nx - 1) s += cx;
+    if (j > 0) s += cz;
+    if (j < c.nz - 1) s += cz;
+    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
+    double bnd = 0.0;
+    if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
+    if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
+    double mk_ = c.m[(size_t)j * c.nx + i];
+    return make_double2(s - c.omega * c.omega * mass * mk_, -c.omega * bnd * sqrt(mk_));
+}
+
+// entry (r, q) of the padded diagonal block A_j (identity in the padding)
+__device__ __forceinline__ double2 block_entry(const Coef& c, int j, int r, int q) {
+    if (r >= c.nx || q >= c.nx) return make_double2(r == q ? 1.0 : 0.0, 0.0);
+    if (r == q) return diag_entry(c, r, j);
+    if (r == q + 1 || q == r + 1) return make_double2(-x_coupling(c, j), 0.0);
+    return make_double2(0.0, 0.0);
+}
+
+// coupling E_ii between rows j and j+1 (zero in the padding)
+__device__ __forceinline__ double row_coupling(const Coef& c, int i) { return i < c.nx ? -z_coupling(c, i) : 0.0; }
+
+// chain owning workgroup `bid`, given each chain's first workgroup
+template <typename Info, typename F>
+__device__ __forceinline__ int find_chain(const Info* tab, int n, int bid, F first) {
+    int c = 0;
+    while (c + 1 < n && bid >= first(tab[c + 1])) ++c;
+    return c;
+}
+
+// the panel step a chain performs at global step t
+struct PanelStep {
+    int j, k0, kb, last;
+};
+__device__ __forceinline__ PanelStep panel_step(const ChainInfo& c, int t) {
+    PanelStep s;
+    s.j = t / c.npan;
+    const int p = t - s.j * c.npan;
+    s.k0 = p * KB;
+    s.kb = min(KB, c.np - s.k0);
+    s.last = (p == c.npan - 1) && (s.j + 1 < c.cf.nz);
+    return s;
+}
+
+// --------------------------------------------------------- block 0 init --
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_block0(const ChainInfo* tab, int n) {
+    using C = typename CT<T>::c;
+    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
+    const ChainInfo& d = tab[ci];
+    int64_t e = (int64_t)(blockIdx.x - d.itile0) * 256 + threadIdx.x;
+    int64_t n2 = (int64_t)d.np * d.np;
+    if (e >= n2) return;
+    int r = (int)(e / d.np), q = (int)(e % d.np);
+    double2 v = block_entry(d.cf, 0, r, q);
+    ((C*)d.G)[e] = mk<C>(v.x, v.y);
+}
+
+// ------------------------------------------- diagonal-tile Gauss-Jordan --
+// In-place Gauss-Jordan inversion of a kb x kb tile (kb in {16, 32}) held
+// in registers by 256 threads: thread t owns row r = t/8 and columns
+// 4*(t%8) .. +3.  Partial pivoting over the not-yet-used rows of the tile,
+// without moving rows: the pivot of column p is taken in row rowOf[p], and
+// the inverse is recovered as T[i][c] = M[rowOf[i]][stepOf[c]].
+// Returns false (uniformly) if some pivot column was exactly zero.
+template <typename T>
+__device__ bool tile_gauss_jordan(typename CT<T>::c (&a)[4], int kb,
+                                  typename CT<T>::c* sRow, T* candv, int* candr,
+                                  int* rowOf, int* stepOf, int* zero_at) {
+    using C = typename CT<T>::c;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < kb) && (4 * cg < kb);
+    bool used = false;
+    bool ok = true;
+    for (int p = 0; p < kb; ++p) {
+        const int pc = p >> 2, pe = p & 3;
+        C apk = a[0];
+#pragma unroll
+        for (int e = 1; e < 4; ++e) if (e == pe) apk = a[e];
+        T v = (act && cg == pc && !used) ? (T)(apk.x * apk.x + apk.y * apk.y) : (T)-1;
+        int vr = r;
+#pragma unroll
+        for (int off = 8; off < 64; off <<= 1) {
+            T ov = __shfl_xor(v, off);
+            int orr = __shfl_xor(vr, off);
+            if (ov > v || (ov == v && orr < vr)) { v = ov; vr = orr; }
+        }
+        if (lane == pc) { candv[w] = v; candr[w] = vr; }
+        __syncthreads();
+        T bv = candv[0];
+        int br = candr[0];
+        for (int q = 1; q < (kb >> 3); ++q) {
+            T cv = candv[q];
+            int cr = candr[q];
+            if (cv > bv || (cv == bv && cr < br)) { bv = cv; br = cr; }
+        }
+        const int rp = br;
+        const bool good = bv > (T)0;
+        if (!good) ok = false;
+        if (t == 0) { rowOf[p] = rp; stepOf[rp] = p; if (!good && *zero_at < 0) *zero_at = p; }
+        // value of column p in this thread's row, from the lane holding it
+        const int src = (lane & ~7) | pc;
+        C f;
+        f.x = __shfl(apk.x, src);
+        f.y = __shfl(apk.y, src);
+        if (act && r == rp) {
+            C dv = good ? cinv(f) : mk<C>(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int c = 4 * cg + e;
+                a[e] = (c == p) ? dv : cmul(a[e], dv);
+                sRow[c] = a[e];
+            }
+            used = true;
+        }
+        __syncthreads();
+        if (act && r != rp) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int c = 4 * cg + e;
+                C pr = sRow[c];
+                a[e] = (c == p) ? mk<C>(-(f.x * pr.x - f.y * pr.y), -(f.x * pr.y + f.y * pr.x))
+                                : csub(a[e], cmul(f, pr));
+            }
+        }
+    }
+    return ok;
+}
+
+// Panel step: T = (A_KK)^{-1}; W rows [32 rb, 32 rb + 32) and the matching
+// columns of Vt.  Every workgroup of a chain inverts the tile itself.
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel(const ChainInfo* tab, int n, int tstep) {
+    using C = typename CT<T>::c;
+    __shared__ C sM[32][33];
+    __shared__ C sT[32][33];
+    __shared__ C sA[32][33];
+    __shared__ C sRow[32];
+    __shared__ T candv[4];
+    __shared__ int candr[4];
+    __shared__ int rowOf[32], stepOf[32];
+    __shared__ int zero_at;
+
+    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.ptile0; });
+    const ChainInfo& d = tab[ci];
+    if (tstep >= d.T) return;
+    const PanelStep ps = panel_step(d, tstep);
+    const int rb = blockIdx.x - d.ptile0;
+    const int np = d.np, kb = ps.kb, k0 = ps.k0;
+    const C* A = (const C*)d.G + (size_t)ps.j * np * np;
+    const int t = threadIdx.x;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < kb) && (4 * cg < kb);
+    if (t == 0) zero_at = -1;
+
+    C a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        a[e] = act ? A[(size_t)(k0 + r) * np + k0 + 4 * cg + e] : mk<C>(0.0, 0.0);
+    // stage the rows of A whose multipliers this workgroup produces
+    const int r0 = rb * PR;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int idx = t + 256 * e;
+        int rr = idx >> 5, tt = idx & 31;
+        C v = mk<C>(0.0, 0.0);
+        if (r0 + rr < np && tt < kb) v = A[(size_t)(r0 + rr) * np + k0 + tt];
+        sA[rr][tt] = v;
+    }
+    __syncthreads();
+
+    bool ok = tile_gauss_jordan<T>(a, kb, sRow, candv, candr, rowOf, stepOf, &zero_at);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sM[r][4 * cg + e] = a[e];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int c = 4 * cg + e;
+            sT[r][c] = sM[rowOf[r]][stepOf[c]];
+        }
+    }
+    __syncthreads();
+    if (!ok && rb == 0 && t == 0) {
+        if (atomicCAS(&d.status[0], 0, 1) == 0) {
+            d.status[1] = ps.j;
+            d.status[2] = k0 + zero_at;
+        }
+    }
+
+    // W = [-A_{:,K} T ; T - I] for rows r0 .. r0+31
+    {
+        const int row = r0 + r;
+        if (row < np && 4 * cg < kb) {
+            C* W = (C*)d.W;
+            const bool inK = row >= k0 && row < k0 + kb;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 4 * cg + e;
+                C v;
+                if (inK) {
+                    v = sT[row - k0][c];
+                    if (row - k0 == c) v.x -= (T)1;
+                } else {
+                    T sr = 0, si = 0;
+                    for (int tt = 0; tt < kb; ++tt) {
+                        C x = sA[r][tt], y = sT[tt][c];
+                        sr += x.x * y.x - x.y * y.y;
+                        si += x.x * y.y + x.y * y.x;
+                    }
+                    v = mk<C>(-sr, -si);
+                }
+                W[(size_t)row * kb + c] = v;
+            }
+        }
+    }
+    // Vt[c][t] = A[k0 + t][c] for columns c in [r0, r0 + 32), identity on K
+    {
+        const int cc = t & 31, tg = t >> 5;
+        const int col = r0 + cc;
+        if (col < np && 4 * tg < kb) {
+            C* Vt = (C*)d.Vt;
+            const bool inK = col >= k0 && col < k0 + kb;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int tt = 4 * tg + e;
+                C v = inK ? mk<C>(tt == col - k0 ? 1.0 : 0.0, 0.0) : A[(size_t)(k0 + tt) * np + col];
+                Vt[(size_t)col * kb + tt] = v;
+            }
+        }
+    }
+}
+
+// Rank-kb update A <- A' + W V on 64 x 64 tiles; on the last panel of a
+// block also writes D_{j+1} = A_{j+1} - E G_j E into the next slot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const ChainInfo* tab, int n, int tstep) {
+    using C = typename CT<T>::c;
+    using V = typename CT<T>::v4;
+    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
+    const ChainInfo& d = tab[ci];
+    if (tstep >= d.T) return;
+    const PanelStep ps = panel_step(d, tstep);
+    const int np = d.np, kb = ps.kb, k0 = ps.k0;
+    const int tiles_x = (np + TILE - 1) / TILE;
+    const int ti = blockIdx.x - d.utile0;
+    const int ty = ti / tiles_x, tx = ti % tiles_x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int lr = l & 15, lg = l >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    C* A = (C*)d.G + (size_t)ps.j * np * np;
+    const C* W = (const C*)d.W;
+    const C* Vt = (const C*)d.Vt;
+
+    int R[2], Cc[2];
+    bool vr[2], vc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        R[q] = ty * TILE + 32 * wr + 16 * q;
+        Cc[q] = tx * TILE + 32 * wc + 16 * q;
+        vr[q] = R[q] < np;
+        vc[q] = Cc[q] < np;
+    }
+    V accr[2][2], acci[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { accr[bi][bj][e] = 0; acci[bi][bj][e] = 0; }
+            if (vr[bi] && vc[bj]) {
+                const int col = Cc[bj] + lr;
+                const bool inK = col >= k0 && col < k0 + kb;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = R[bi] + acc_row<T>(lg, e);
+                    C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : A[(size_t)row * np + col];
+                    accr[bi][bj][e] = v.x;
+                    acci[bi][bj][e] = v.y;
+                }
+            }
+        }
+
+    for (int kk = 0; kk < kb; kk += 16) {
+        C av[2][4], bv[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                av[q][s] = vr[q] ? W[(size_t)(R[q] + lr) * kb + kk + 4 * lg + s] : mk<C>(0.0, 0.0);
+                bv[q][s] = vc[q] ? Vt[(size_t)(Cc[q] + lr) * kb + kk + 4 * lg + s] : mk<C>(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    if (vr[bi] && vc[bj])
+                        cmfma<T, V>(accr[bi][bj], acci[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
+                                    bv[bj][s].y);
+    }
+
+    C* An = A + (size_t)np * np;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            if (!(vr[bi] && vc[bj])) continue;
+            const int col = Cc[bj] + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = R[bi] + acc_row<T>(lg, e);
+                C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
+                A[(size_t)row * np + col] = g;
+                if (ps.last) {
+                    double2 a1 = block_entry(d.cf, ps.j + 1, row, col);
+                    double s = row_coupling(d.cf, row) * row_coupling(d.cf, col);
+                    An[(size_t)row * np + col] = mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
+                }
+            }
+        }
+}
+
+// One block step of the forward (X_j = G_j (B_j - E X_{j-1})) or backward
+// (X_j -= G_j E X_{j+1}) sweep, for a 16 x 16 tile of (rows, right-hand
+// sides); the four waves split the contraction dimension and are summed in
+// a fixed order.
+template <typename T, bool FWD, bool CONJB>
+__global__ __launch_bounds__(256) void k_sweep(const SweepInfo* tab, int n, int tstep) {
+    using C = typename CT<T>::c;
+    using V = typename CT<T>::v4;
+    __shared__ T red[4][2][4][64];
+    const int ci = find_chain(tab, n, blockIdx.x, [](const SweepInfo& c) { return c.tile0; });
+    const SweepInfo& d = tab[ci];
+    const int j = FWD ? tstep : d.nz - 2 - tstep;
+    if (j < 0 || j >= d.nz) return;
+    const int ti = blockIdx.x - d.tile0;
+    const int i0 = 16 * (ti / d.tiles_s), s0 = 16 * (ti % d.tiles_s);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int lr = l & 15, lg = l >> 4;
+    const int np = d.np, nx = d.nx;
+    const C* G = (const C*)d.G + (size_t)j * np * np;
+    const C* Bm = (const C*)d.B;
+    C* X = (C*)d.X;
+    const int s = s0 + lr;
+    const bool scol = s < d.S;
+    const C* Xprev = FWD ? X + (size_t)s * d.ldx + (size_t)(j - 1) * nx : X + (size_t)s * d.ldx + (size_t)(j + 1) * nx;
+    const C* Bcol = FWD ? Bm + (size_t)s * d.ldb + (size_t)j * nx : nullptr;
+
+    V cr, cim;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { cr[e] = 0; cim[e] = 0; }
+    const int nch = np / 16;
+    for (int ch = w; ch < nch; ch += 4) {
+        const int kb0 = 16 * ch + 4 * lg;
+        C av[4], bv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) av[q] = G[(size_t)(i0 + lr) * np + kb0 + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = kb0 + q;
+            C y = mk<C>(0.0, 0.0);
+            if (scol && k < nx) {
+                const T e = (T)(k == 0 || k == nx - 1 ? -0.5 * d.cz : -d.cz);
+                if (FWD) {
+                    y = Bcol[k];
+                    if (CONJB) y.y = -y.y;
+                    if (j > 0) { C xp = Xprev[k]; y.x -= e * xp.x; y.y -= e * xp.y; }
+                } else {
+                    C xp = Xprev[k];
+                    y = mk<C>(e * xp.x, e * xp.y);
+                }
+            }
+            bv[q] = y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cmfma<T, V>(cr, cim, av[q].x, av[q].y, bv[q].x, bv[q].y);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { red[w][0][e][l] = cr[e]; red[w][1][e][l] = cim[e]; }
+    __syncthreads();
+    if (w == 0 && scol) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + acc_row<T>(lg, e);
+            if (i >= nx) continue;
+            T sr = red[0][0][e][l], si = red[0][1][e][l];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) { sr += red[q][0][e][l]; si += red[q][1][e][l]; }
+            C* out = X + (size_t)s * d.ldx + (size_t)j * nx + i;
+            if (FWD) {
+                *out = mk<C>(sr, si);
+            } else {
+                C o = *out;
+                *out = mk<C>(o.x - sr, o.y - si);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ elementwise / FP64 --
+__global__ void k_check_model(const double* m, int64_t n, int* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        double v = m[i];
+        if (!(v > 0.0) || !isfinite(v)) atomicOr(flag, 1);
+    }
+}
+
+__global__ void k_zero(uint32_t* p, size_t n32) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n32) p[i] = 0u;
+}
+
+// r = B - A X (or A^*), FP64; per-block partial sums of |r|^2 and |B|^2
+__global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const double2* B, int64_t ldb,
+                                                  const double2* X, int64_t ldx, double2* R, int64_t ldr,
+                                                  float2* R32, int S, double* partial, int nblk) {
+    __shared__ double sr[256], sb[256];
+    const int s = blockIdx.y;
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rr = 0.0, bb = 0.0;
+    if (k < N) {
+        const int i = (int)(k % cf.nx), j = (int)(k / cf.nx);
+        const double2* x = X + (size_t)s * ldx;
+        double2 dg = diag_entry(cf, i, j);
+        if (adjoint) dg.y = -dg.y;
+        double2 xk = x[k];
+        double ar = dg.x * xk.x - dg.y * xk.y, ai = dg.x * xk.y + dg.y * xk.x;
+        const double cx = x_coupling(cf, j), cz = z_coupling(cf, i);
+        if (i > 0) { ar -= cx * x[k - 1].x; ai -= cx * x[k - 1].y; }
+        if (i < cf.nx - 1) { ar -= cx * x[k + 1].x; ai -= cx * x[k + 1].y; }
+        if (j > 0) { ar -= cz * x[k - cf.nx].x; ai -= cz * x[k - cf.nx].y; }
+        if (j < cf.nz - 1) { ar -= cz * x[k + cf.nx].x; ai -= cz * x[k + cf.nx].y; }
+        double2 bk = B[(size_t)s * ldb + k];
+        double2 r = make_double2(bk.x - ar, bk.y - ai);
+        if (R) R[(size_t)s * ldr + k] = r;
+        if (R32) R32[(size_t)s * ldr + k] = make_float2((float)r.x, (float)(adjoint ? -r.y : r.y));
+        rr = r.x * r.x + r.y * r.y;
+        bb = bk.x * bk.x + bk.y * bk.y;
+    }
+    sr[threadIdx.x] = rr;
+    sb[threadIdx.x] = bb;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) { sr[threadIdx.x] += sr[threadIdx.x + h]; sb[threadIdx.x] += sb[threadIdx.x + h]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[((size_t)s * nblk + blockIdx.x) * 2 + 0] = sr[0];
+        partial[((size_t)s * nblk + blockIdx.x) * 2 + 1] = sb[0];
+    }
+}
+
+__global__ void k_norms_finish(const double* partial, int nblk, int S, double* norms) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double a = 0.0, c = 0.0;
+    for (int q = 0; q < nblk; ++q) { a += partial[((size_t)s * nblk + q) * 2]; c += partial[((size_t)s * nblk + q) * 2 + 1]; }
+    norms[2 * s] = a;
+    norms[2 * s + 1] = c;
+}
+
+__global__ void k_c128_to_c64(const double2* src, int64_t lds, float2* dst, int64_t ldd, int64_t N, int conj) {
+    const int s = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double2 v = src[(size_t)s * lds + k];
+    dst[(size_t)s * ldd + k] = make_float2((float)v.x, (float)(conj ? -v.y : v.y));
+}
+
+__global__ void k_c64_to_c128(const float2* src, int64_t lds, double2* dst, int64_t ldd, int64_t N, int conj,
+                              int accumulate) {
+    const int s = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    float2 v = src[(size_t)s * lds + k];
+    double re = v.x, im = conj ? -(double)v.y : (double)v.y;
+    double2* o = dst + (size_t)s * ldd + k;
+    if (accumulate) { double2 p = *o; *o = make_double2(p.x + re, p.y + im); }
+    else *o = make_double2(re, im);
+}
+
+__global__ void k_conj(double2* X, int64_t ld, int64_t N) {
+    const int s = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) X[(size_t)s * ld + k].y = -X[(size_t)s * ld + k].y;
+}
+
+__global__ void k_axpy(const double2* D, int64_t ldd, double2* X, int64_t ldx, int64_t N) {
+    const int s = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double2 a = D[(size_t)s * ldd + k], x = X[(size_t)s * ldx + k];
+    X[(size_t)s * ldx + k] = make_double2(x.x + a.x, x.y + a.y);
+}
+
+__global__ void k_unit_sources(double2* E, int64_t ld, int64_t N, const int* nodes) {
+    const int s = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) E[(size_t)s * ld + k] = make_double2(k == nodes[s] ? 1.0 : 0.0, 0.0);
+}
+
+// eps_s = d_s - R u_s and 1/2 |eps_s|^2 (one thread per source, receivers in order)
+__global__ void k_misfit(const double2* U, int64_t ldu, const double2* dobs, const int* rec, int Nr, int S,
+                         double2* eps, double* phi_part) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double acc = 0.0;
+    for (int p = 0; p < Nr; ++p) {
+        double2 u = U[(size_t)s * ldu + rec[p]];
+        double2 dv = dobs[(size_t)s * Nr + p];
+        double2 e = make_double2(dv.x - u.x, dv.y - u.y);
+        eps[(size_t)s * Nr + p] = e;
+        acc += e.x * e.x + e.y * e.y;
+    }
+    phi_part[s] = 0.5 * acc;
+}
+
+// R^* eps: add eps_p onto node rec[p] (buffer zeroed beforehand)
+__global__ void k_scatter_adj(const double2* eps, const int* rec, int Nr, int S, double2* R, int64_t ldr) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    for (int p = 0; p < Nr; ++p) {
+        double2* o = R + (size_t)s * ldr + rec[p];
+        double2 e = eps[(size_t)s * Nr + p];
+        *o = make_double2(o->x + e.x, o->y + e.y);
+    }
+}
+
+// nodal weight of G_{m,w}(beta_k .): w^2 d_k + b_k i w / (2 sqrt m_k)
+__device__ __forceinline__ double2 grad_weight(const Coef& c, int i, int j) {
+    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
+    double bnd = 0.0;
+    if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
+    if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
+    double mk_ = c.m[(size_t)j * c.nx + i];
+    return make_double2(c.omega * c.omega * mass, c.omega * bnd / (2.0 * sqrt(mk_)));
+}
+
+// g_k += -Re sum_s wk u_{s,k} conj(l_{s,k})
+__global__ __launch_bounds__(256) void k_grad(Coef cf, const double2* U, int64_t ldu, const double2* L,
+                                              int64_t ldl, int S, double* g) {
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= N) return;
+    double2 wk = grad_weight(cf, (int)(k % cf.nx), (int)(k / cf.nx));
+    double sr = 0.0, si = 0.0;   // sum_s u conj(l)
+    for (int s = 0; s < S; ++s) {
+        double2 u = U[(size_t)s * ldu + k], l = L[(size_t)s * ldl + k];
+        sr += u.x * l.x + u.y * l.y;
+        si += u.y * l.x - u.x * l.y;
+    }
+    g[k] += -(wk.x * sr - wk.y * si);
+}
+
+// V[(a*S + s)] = wk * mt_a[k] * u_s[k]
+__global__ void k_gn_rhs(Coef cf, const double2* U, int64_t ldu, int S, const double* mt, int n_dir,
+                         double2* V, int64_t ldv) {
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    const int col = blockIdx.y;   // a*S + s
+    const int a = col / S, s = col % S;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double2 wk = grad_weight(cf, (int)(k % cf.nx), (int)(k / cf.nx));
+    double2 u = U[(size_t)s * ldu + k];
+    double t = mt[(size_t)a * N + k];
+    V[(size_t)col * ldv + k] = make_double2(t * (wk.x * u.x - wk.y * u.y), t * (wk.x * u.y + wk.y * u.x));
+}
+
+// RV = R^* R V column by column (buffer zeroed beforehand)
+__global__ void k_sample_scatter(const double2* V, int64_t ldv, const int* rec, int Nr, int cols, double2* RV,
+                                 int64_t ldr) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    for (int p = 0; p < Nr; ++p) {
+        double2 v = V[(size_t)c * ldv + rec[p]];
+        double2* o = RV + (size_t)c * ldr + rec[p];
+        *o = make_double2(o->x + v.x, o->y + v.y);
+    }
+}
+
+// hv_a[k] += Re sum_s wk u_s[k] conj(z_{a,s}[k])
+__global__ void k_hv(Coef cf, const double2* U, int64_t ldu, int S, const double2* Z, int64_t ldz, int n_dir,
+                     double* hv) {
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    const int a = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double2 wk = grad_weight(cf, (int)(k % cf.nx), (int)(k / cf.nx));
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < S; ++s) {
+        double2 u = U[(size_t)s * ldu + k], z = Z[(size_t)(a * S + s) * ldz + k];
+        sr += u.x * z.x + u.y * z.y;
+        si += u.y * z.x - u.x * z.y;
+    }
+    hv[(size_t)a * N + k] += wk.x * sr - wk.y * si;
+}
+
+// g += Gamma m and partial sums of m^T Gamma m, Gamma = alpha (Dx^T Dx + Dz^T Dz) + mu I,
+// D_n = (n - 1) bidiag(1, -1)
+__global__ __launch_bounds__(256) void k_gamma(const double* m, int nx, int nz, double alpha, double mu,
+                                               double* g, double* part) {
+    __shared__ double sq[256];
+    const int64_t N = (int64_t)nx * nz;
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double q = 0.0;
+    if (k < N) {
+        const int i = (int)(k % nx), j = (int)(k / nx);
+        const double ax = (double)(nx - 1) * (nx - 1), az = (double)(nz - 1) * (nz - 1);
+        double mk_ = m[k], rm = 0.0;
+        if (i > 0) rm += ax * (mk_ - m[k - 1]);
+        if (i < nx - 1) rm += ax * (mk_ - m[k + 1]);
+        if (j > 0) rm += az * (mk_ - m[k - nx]);
+        if (j < nz - 1) rm += az * (mk_ - m[k + nx]);
+        double gm = alpha * rm + mu * mk_;
+        g[k] += gm;
+        q = mk_ * gm;
+    }
+    sq[threadIdx.x] = q;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sq[threadIdx.x] += sq[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
+}
+
+__global__ void k_sum_scalar(const double* part, int n, double* out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double a = 0.0;
+        for (int q = 0; q < n; ++q) a += part[q];
+        *out = a;
+    }
+}
+
+// standalone tile inverses (the panel's building block, for tests)
+__global__ __launch_bounds__(256) void k_tile_inverse(int kb, const double2* A, double2* Tout, int* status) {
+    __shared__ double2 sM[32][33];
+    __shared__ double2 sRow[32];
+    __shared__ double candv[4];
+    __shared__ int candr[4];
+    __shared__ int rowOf[32], stepOf[32];
+    __shared__ int zero_at;
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    const bool act = (r < kb) && (4 * cg < kb);
+    const double2* Am = A + (size_t)blockIdx.x * kb * kb;
+    if (t == 0) zero_at = -1;
+    double2 a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = act ? Am[r * kb + 4 * cg + e] : make_double2(0.0, 0.0);
+    __syncthreads();
+    bool ok = tile_gauss_jordan<double>(a, kb, sRow, candv, candr, rowOf, stepOf, &zero_at);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sM[r][4 * cg + e] = a[e];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int c = 4 * cg + e;
+            Tout[(size_t)blockIdx.x * kb * kb + r * kb + c] = sM[rowOf[r]][stepOf[c]];
+        }
+    }
+    if (t == 0 && !ok) status[blockIdx.x] = 1 + zero_at;
+}
+
+// one wavefront: D = A(16x4) B(4x16) with the operand layout the kernels assume
+__global__ void k_mfma_probe(int prec, const double* A, const double* B, double* D) {
+    const int l = threadIdx.x;
+    if (prec == 0) {
+        v4d c = {0, 0, 0, 0};
+        c = mfma16(A[(l % 16) * 4 + l / 16], B[(l / 16) * 16 + l % 16], c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) D[acc_row<double>(l / 16, e) * 16 + l % 16] = c[e];
+    } else {
+        v4f c = {0, 0, 0, 0};
+        c = mfma16((float)A[(l % 16) * 4 + l / 16], (float)B[(l / 16) * 16 + l % 16], c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) D[acc_row<float>(l / 16, e) * 16 + l % 16] = (double)c[e];
+    }
+}
+
+// ---------------------------------------------------------------- launchers --
+static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+void launch_init_block0(const ChainInfo* tab, int n, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_init_block0<float>, dim3(total), dim3(256), 0, st, tab, n);
+    else hipLaunchKernelGGL(k_init_block0<double>, dim3(total), dim3(256), 0, st, tab, n);
+}
+void launch_panel(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_panel<float>, dim3(total), dim3(256), 0, st, tab, n, t);
+    else hipLaunchKernelGGL(k_panel<double>, dim3(total), dim3(256), 0, st, tab, n, t);
+}
+void launch_update(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_update<float>, dim3(total), dim3(256), 0, st, tab, n, t);
+    else hipLaunchKernelGGL(k_update<double>, dim3(total), dim3(256), 0, st, tab, n, t);
+}
+void launch_sweep(const SweepInfo* tab, int n, int t, int total, bool fp32, bool forward, bool conj_b,
+                  hipStream_t st) {
+    if (fp32) {
+        if (forward) {
+            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), dim3(total), dim3(256), 0, st, tab, n, t);
+            else hipLaunchKernelGGL((k_sweep<float, true, false>), dim3(total), dim3(256), 0, st, tab, n, t);
+        } else hipLaunchKernelGGL((k_sweep<float, false, false>), dim3(total), dim3(256), 0, st, tab, n, t);
+    } else {
+        if (forward) {
+            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), dim3(total), dim3(256), 0, st, tab, n, t);
+            else hipLaunchKernelGGL((k_sweep<double, true, false>), dim3(total), dim3(256), 0, st, tab, n, t);
+        } else hipLaunchKernelGGL((k_sweep<double, false, false>), dim3(total), dim3(256), 0, st, tab, n, t);
+    }
+}
+void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_model, grid1(n), dim3(256), 0, st, m, n, flag);
+}
+void launch_residual(const Coef& cf, int adjoint, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                     double* R, int64_t ldr, float* R32, int S, double* partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual, dim3(nblk, S), dim3(256), 0, st, cf, adjoint, (const double2*)B, ldb,
+                       (const double2*)X, ldx, (double2*)R, ldr, (float2*)R32, S, partial, nblk);
+}
+void launch_norms_finish(const double* partial, int nblk, int S, double* norms, hipStream_t st) {
+    hipLaunchKernelGGL(k_norms_finish, grid1(S, 64), dim3(64), 0, st, partial, nblk, S, norms);
+}
+void launch_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t N, int S, int conj,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_c128_to_c64, dim3(grid1(N).x, S), dim3(256), 0, st, (const double2*)src, lds,
+                       (float2*)dst, ldd, N, conj);
+}
+void launch_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t N, int S, int conj,
+                        int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_c64_to_c128, dim3(grid1(N).x, S), dim3(256), 0, st, (const float2*)src, lds,
+                       (double2*)dst, ldd, N, conj, accumulate);
+}
+void launch_conj_inplace(double* X, int64_t ld, int64_t N, int S, hipStream_t st) {
+    hipLaunchKernelGGL(k_conj, dim3(grid1(N).x, S), dim3(256), 0, st, (double2*)X, ld, N);
+}
+void launch_axpy_c128(const double* D, int64_t ldd, double* X, int64_t ldx, int64_t N, int S, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid1(N).x, S), dim3(256), 0, st, (const double2*)D, ldd, (double2*)X, ldx, N);
+}
+void launch_unit_sources(double* E, int64_t ld, int64_t N, const int* nodes, int S, hipStream_t st) {
+    hipLaunchKernelGGL(k_unit_sources, dim3(grid1(N).x, S), dim3(256), 0, st, (double2*)E, ld, N, nodes);
+}
+void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* rec, int Nr, int S, double* eps,
+                   double* phi_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit, grid1(S, 64), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, rec,
+                       Nr, S, (double2*)eps, phi_part);
+}
+void launch_scatter_adj(const double* eps, const int* rec, int Nr, int S, double* R, int64_t ldr, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_adj, grid1(S, 64), dim3(64), 0, st, (const double2*)eps, rec, Nr, S,
+                       (double2*)R, ldr);
+}
+void launch_grad(const Coef& cf, const double* U, int64_t ldu, const double* L, int64_t ldl, int S, double* g,
+                 hipStream_t st) {
+    hipLaunchKernelGGL(k_grad, grid1((int64_t)cf.nx * cf.nz), dim3(256), 0, st, cf, (const double2*)U, ldu,
+                       (const double2*)L, ldl, S, g);
+}
+void launch_gn_rhs(const Coef& cf, const double* U, int64_t ldu, int S, const double* mt, int n_dir, double* V,
+                   int64_t ldv, hipStream_t st) {
+    hipLaunchKernelGGL(k_gn_rhs, dim3(grid1((int64_t)cf.nx * cf.nz).x, n_dir * S), dim3(256), 0, st, cf,
+                       (const double2*)U, ldu, S, mt, n_dir, (double2*)V, ldv);
+}
+void launch_sample_scatter(const double* V, int64_t ldv, const int* rec, int Nr, int cols, double* RV, int64_t ldr,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_scatter, grid1(cols, 64), dim3(64), 0, st, (const double2*)V, ldv, rec, Nr, cols,
+                       (double2*)RV, ldr);
+}
+void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz, int n_dir,
+               double* hv, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_hv, dim3(grid1(N).x, n_dir), dim3(256), 0, st, cf, (const double2*)U, ldu, S,
+                       (const double2*)Z, ldz, n_dir, hv);
+}
+void launch_gamma(const double* m, int nx, int nz, double alpha, double mu, double* g, double* part, int nblk,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_gamma, dim3(nblk), dim3(256), 0, st, m, nx, nz, alpha, mu, g, part);
+}
+void launch_sum_scalar(const double* part, int n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(64), 0, st, part, n, out);
+}
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+    size_t n32 = (bytes + 3) / 4;
+    if (n32) hipLaunchKernelGGL(k_zero, grid1((int64_t)n32), dim3(256), 0, st, (uint32_t*)p, n32);
+}
+void launch_tile_inverse(int count, int kb, const double* A, double* T, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, (const double2*)A, (double2*)T, status);
+}
+void launch_mfma_probe(int prec, const double* A, const double* B, double* D, hipStream_t st) {
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, prec, A, B, D);
+}
+
+}  // namespace helm

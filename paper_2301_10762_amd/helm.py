@@ -1,0 +1,348 @@
+"""Python binding of libhelm.so: argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels behind the C ABI declared
+in include/helm.h; this module turns torch device tensors into raw pointers
+and the current torch stream into a hipStream_t.  There is no CPU fallback:
+if the library is missing or the GPU is absent the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelm.so")
+
+FP64 = 0
+FP32_IR = 1
+_PREC = {"fp64": FP64, "fp32_ir": FP32_IR, "fp32": FP32_IR, FP64: FP64, FP32_IR: FP32_IR}
+
+OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EDEVICE = 0, -1, -2, -3, -4, -5
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR", ENOCONV: "ENOCONV", EDEVICE: "EDEVICE"}
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("hx", ctypes.c_double), ("hz", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int32), ("max_relres", ctypes.c_double), ("bad_block", ctypes.c_int32),
+                ("bad_row", ctypes.c_int32), ("solves", ctypes.c_int64)]
+
+
+@dataclass
+class Info:
+    ir_iters: int
+    max_relres: float
+    bad_block: int
+    bad_row: int
+    solves: int
+
+    @classmethod
+    def of(cls, i: _Info) -> "Info":
+        return cls(i.ir_iters, i.max_relres, i.bad_block, i.bad_row, i.solves)
+
+
+@dataclass(frozen=True)
+class Grid:
+    """n_x x n_z nodes with spacings h_x, h_z; node k = j*n_x + i, j = 0 on top."""
+    nx: int
+    nz: int
+    hx: float
+    hz: float
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.nz
+
+    def c(self) -> _Grid:
+        return _Grid(self.nx, self.nz, self.hx, self.hz)
+
+    @classmethod
+    def of(cls, w) -> "Grid":
+        return cls(int(w.nx), int(w.nz), float(w.hx), float(w.hz))
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def lib():
+    """Load libhelm.so (built in-tree by paper_2301_10762_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2301_10762_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    G = ctypes.POINTER(_Grid)
+    I = ctypes.POINTER(_Info)
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.helm_factor.argtypes = [G, _vp, f64, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+    L.helm_factor_batch.argtypes = [i32, G, ctypes.POINTER(_vp), ctypes.POINTER(f64), ctypes.c_int, _vp,
+                                    ctypes.POINTER(_vp)]
+    L.helm_factor_bytes.argtypes = [G, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.helm_factor_destroy.argtypes = [_vp]
+    L.helm_factor_destroy.restype = None
+    L.helm_solve.argtypes = [_vp, _vp, _vp, i32, i64, f64, _vp, I]
+    L.helm_adjoint_solve.argtypes = [_vp, _vp, _vp, i32, i64, f64, _vp, I]
+    L.helm_solve_batch.argtypes = [i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.c_int, f64, _vp, I]
+    L.helm_misfit_grad.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
+                                   ctypes.POINTER(i32), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp, I]
+    L.helm_gn_hvp.argtypes = [G, _vp, i32, ctypes.POINTER(f64), i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+                              i32, _vp, f64, f64, ctypes.c_int, f64, _vp, _vp, I]
+    L.helm_residual.argtypes = [G, _vp, f64, ctypes.c_int, _vp, _vp, _vp, i32, i64, _vp, _vp]
+    L.helm_tile_inverse.argtypes = [i32, i32, _vp, _vp, _vp]
+    L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
+    L.helm_counter.argtypes = [ctypes.c_int]
+    L.helm_counter.restype = ctypes.c_int64
+    L.helm_last_error.restype = ctypes.c_char_p
+    for name in ("helm_factor", "helm_factor_batch", "helm_factor_bytes", "helm_solve", "helm_adjoint_solve",
+                 "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
+                 "helm_mfma_probe"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise HelmError(rc, lib().helm_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libhelm needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t) -> _vp:
+    return _vp(t.data_ptr())
+
+
+def _dev_f64(x, n=None):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+def _dev_c128(x):
+    torch = _torch()
+    t = torch.as_tensor(x, device="cuda")
+    if t.dtype != torch.complex128:
+        t = t.to(torch.complex128)
+    return t.contiguous()
+
+
+def _i32(seq):
+    a = np.ascontiguousarray(np.asarray(seq, dtype=np.int32))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def counters() -> dict:
+    L = lib()
+    return {"launches": int(L.helm_counter(0)), "solves": int(L.helm_counter(1))}
+
+
+def factor_bytes(grid: Grid, precision="fp64") -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().helm_factor_bytes(ctypes.byref(grid.c()), _PREC[precision], ctypes.byref(out)))
+    return int(out.value)
+
+
+class Factor:
+    """Device factorisation of A(m, w); owns HBM until close()."""
+
+    def __init__(self, handle: int, grid: Grid, omega: float, precision: int):
+        self._h = _vp(handle)
+        self.grid = grid
+        self.omega = float(omega)
+        self.precision = precision
+
+    @property
+    def handle(self) -> _vp:
+        if not self._h:
+            raise RuntimeError("factor already destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().helm_factor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, B, tol: float = 0.0, stream=None):
+        return solve(self, B, tol, stream)
+
+    def adjoint_solve(self, R, tol: float = 0.0, stream=None):
+        return adjoint_solve(self, R, tol, stream)
+
+
+def factor(grid: Grid, m, omega: float, precision="fp64", stream=None) -> Factor:
+    """Factor A(m, w) on the GPU (block-tridiagonal LU, one block per grid row)."""
+    md = _dev_f64(m, grid.N)
+    h = _vp()
+    _check(lib().helm_factor(ctypes.byref(grid.c()), _ptr(md), float(omega), _PREC[precision], _stream(stream),
+                             ctypes.byref(h)))
+    return Factor(h.value, grid, omega, _PREC[precision])
+
+
+def factor_batch(grids, ms, omegas, precision="fp64", stream=None) -> list:
+    """Factor several systems with their block chains sharing kernel launches."""
+    n = len(omegas)
+    grids = list(grids) if not isinstance(grids, Grid) else [grids] * n
+    mds = [_dev_f64(m, g.N) for m, g in zip(ms, grids)]
+    garr = (_Grid * n)(*[g.c() for g in grids])
+    marr = (_vp * n)(*[md.data_ptr() for md in mds])
+    warr = (ctypes.c_double * n)(*[float(w) for w in omegas])
+    outs = (_vp * n)()
+    _check(lib().helm_factor_batch(n, garr, marr, warr, _PREC[precision], _stream(stream), outs))
+    return [Factor(outs[c], grids[c], omegas[c], _PREC[precision]) for c in range(n)]
+
+
+def _rhs(F: Factor, B):
+    B = _dev_c128(B)
+    if B.dim() == 1:
+        B = B.unsqueeze(0)
+    if B.shape[-1] != F.grid.N:
+        raise ValueError("right-hand sides must be [S][nx*nz]")
+    return B
+
+
+def solve(F: Factor, B, tol: float = 0.0, stream=None):
+    """X = A^{-1} B (rows of B are right-hand sides).  Returns (X, Info)."""
+    torch = _torch()
+    B = _rhs(F, B)
+    X = torch.empty_like(B)
+    info = _Info()
+    _check(lib().helm_solve(F.handle, _ptr(B), _ptr(X), B.shape[0], F.grid.N, float(tol), _stream(stream),
+                            ctypes.byref(info)))
+    return X, Info.of(info)
+
+
+def adjoint_solve(F: Factor, R, tol: float = 0.0, stream=None):
+    """L = A^{-*} R, the conjugate-transpose solve with the same factors."""
+    torch = _torch()
+    R = _rhs(F, R)
+    L = torch.empty_like(R)
+    info = _Info()
+    _check(lib().helm_adjoint_solve(F.handle, _ptr(R), _ptr(L), R.shape[0], F.grid.N, float(tol), _stream(stream),
+                                    ctypes.byref(info)))
+    return L, Info.of(info)
+
+
+def solve_batch(Fs, Bs, adjoint: bool = False, tol: float = 0.0, stream=None, out=None):
+    """Solve with several factors at once; sweeps share kernel launches."""
+    torch = _torch()
+    n = len(Fs)
+    Bs = [_rhs(F, B) for F, B in zip(Fs, Bs)]
+    Xs = out if out is not None else [torch.empty_like(B) for B in Bs]
+    harr = (_vp * n)(*[F.handle.value for F in Fs])
+    barr = (_vp * n)(*[B.data_ptr() for B in Bs])
+    xarr = (_vp * n)(*[X.data_ptr() for X in Xs])
+    sarr = (ctypes.c_int32 * n)(*[B.shape[0] for B in Bs])
+    larr = (ctypes.c_int64 * n)(*[F.grid.N for F in Fs])
+    infos = (_Info * n)()
+    _check(lib().helm_solve_batch(n, harr, barr, xarr, sarr, larr, int(adjoint), float(tol), _stream(stream), infos))
+    return Xs, [Info.of(infos[c]) for c in range(n)]
+
+
+def misfit_grad(grid: Grid, m, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: float = 0.0,
+                precision="fp64", tol: float = 0.0, stream=None, grad_out=None):
+    """phi and grad phi (adjoint-state, Thm A.1).  d_obs: complex [n_omega][S][Nr]."""
+    torch = _torch()
+    md = _dev_f64(m, grid.N)
+    n_omega = len(omegas)
+    src, psrc = _i32(sources)
+    rec, prec = _i32(receivers)
+    dd = _dev_c128(d_obs)
+    if tuple(dd.shape) != (n_omega, len(src), len(rec)):
+        raise ValueError("d_obs must be [n_omega][S][Nr]")
+    warr = (ctypes.c_double * n_omega)(*[float(w) for w in omegas])
+    g = grad_out if grad_out is not None else torch.empty(grid.N, dtype=torch.float64, device="cuda")
+    phi = ctypes.c_double(0.0)
+    info = _Info()
+    _check(lib().helm_misfit_grad(ctypes.byref(grid.c()), _ptr(md), n_omega, warr, _ptr(dd), len(src), psrc,
+                                  len(rec), prec, float(alpha), float(mu), _PREC[precision], float(tol),
+                                  _stream(stream), ctypes.byref(phi), _ptr(g), ctypes.byref(info)))
+    return float(phi.value), g, Info.of(info)
+
+
+def gn_hvp(grid: Grid, m, omegas, sources, receivers, directions, alpha: float = 0.0, mu: float = 0.0,
+           precision="fp64", tol: float = 0.0, stream=None):
+    """(H^(1) + Gamma) mt for each direction (rows of `directions`)."""
+    torch = _torch()
+    md = _dev_f64(m, grid.N)
+    mt = _dev_f64(directions)
+    mt = mt.reshape(-1, grid.N).contiguous()
+    n_omega = len(omegas)
+    src, psrc = _i32(sources)
+    rec, prec = _i32(receivers)
+    warr = (ctypes.c_double * n_omega)(*[float(w) for w in omegas])
+    hv = torch.empty_like(mt)
+    info = _Info()
+    _check(lib().helm_gn_hvp(ctypes.byref(grid.c()), _ptr(md), n_omega, warr, len(src), psrc, len(rec), prec,
+                             mt.shape[0], _ptr(mt), float(alpha), float(mu), _PREC[precision], float(tol),
+                             _stream(stream), _ptr(hv), ctypes.byref(info)))
+    return hv, Info.of(info)
+
+
+def residual(grid: Grid, m, omega: float, B, X, adjoint: bool = False, stream=None):
+    """(r = B - A X, per-column [||r||^2, ||B||^2]) in FP64 on the GPU."""
+    torch = _torch()
+    md = _dev_f64(m, grid.N)
+    B = _dev_c128(B).reshape(-1, grid.N).contiguous()
+    X = _dev_c128(X).reshape(-1, grid.N).contiguous()
+    r = torch.empty_like(B)
+    norms = torch.empty(B.shape[0], 2, dtype=torch.float64, device="cuda")
+    _check(lib().helm_residual(ctypes.byref(grid.c()), _ptr(md), float(omega), int(adjoint), _ptr(B), _ptr(X),
+                               _ptr(r), B.shape[0], grid.N, _ptr(norms), _stream(stream)))
+    return r, norms
+
+
+def tile_inverse(A):
+    """Inverse of each kb x kb complex128 tile (kb = 16 or 32) by the panel's Gauss-Jordan."""
+    torch = _torch()
+    A = _dev_c128(A)
+    count, kb = A.shape[0], A.shape[1]
+    T = torch.empty_like(A)
+    _check(lib().helm_tile_inverse(count, kb, _ptr(A), _ptr(T), _stream()))
+    return T
+
+
+def mfma_probe(prec: int, A, B):
+    torch = _torch()
+    A = _dev_f64(A, 64)
+    B = _dev_f64(B, 64)
+    D = torch.zeros(256, dtype=torch.float64, device="cuda")
+    _check(lib().helm_mfma_probe(int(prec), _ptr(A), _ptr(B), _ptr(D), _stream()))
+    return D.reshape(16, 16)

@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every function include/helm.h declares
+(no compute: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helm.h")
+LIB = os.path.join(ROOT, "paper_2301_10762_amd", "libhelm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(helm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("helm_factor", "helm_solve", "helm_adjoint_solve", "helm_misfit_grad", "helm_gn_hvp",
+                     "helm_factor_destroy", "helm_factor_bytes", "helm_last_error"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_host_side_argument_checks_without_gpu():
+    """Entry points reject bad grids before touching the device."""
+    from paper_2301_10762_amd import helm
+    L = helm.lib()
+    g = helm._Grid(1, 5, 0.1, 0.1)
+    out = ctypes.c_size_t(0)
+    assert L.helm_factor_bytes(ctypes.byref(g), 0, ctypes.byref(out)) == helm.EINVAL
+    assert b"nx >= 2" in L.helm_last_error()
+    g = helm._Grid(401, 401, 0.025, 0.025)
+    assert L.helm_factor_bytes(ctypes.byref(g), 0, ctypes.byref(out)) == 0
+    # 401 -> 416 padded block, 401 blocks of complex128, plus the model copy
+    assert out.value == 416 * 416 * 401 * 16 + 401 * 401 * 8
+    assert L.helm_factor_bytes(ctypes.byref(g), 1, ctypes.byref(out)) == 0
+    assert out.value == 416 * 416 * 401 * 8 + 401 * 401 * 8
+    assert L.helm_factor_bytes(ctypes.byref(g), 7, ctypes.byref(out)) == helm.EINVAL
