@@ -1,0 +1,111 @@
+// Device-side helpers shared by the HIP kernels of libhelm: complex
+// arithmetic, the matrix-core wrappers, and on-the-fly assembly of the
+// five-point operator A(m, w) of App. A.1 (arXiv 2301.10762).
+#pragma once
+#include "helm_internal.h"
+
+namespace helm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct CT;
+template <> struct CT<double> { using c = double2; using v4 = v4d; };
+template <> struct CT<float> { using c = float2; using v4 = v4f; };
+
+template <typename C> __device__ __forceinline__ C mk(double re, double im) { C r; r.x = re; r.y = im; return r; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cscale(C a, double s) { return mk<C>(a.x * s, a.y * s); }
+template <typename C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
+template <typename C> __device__ __forceinline__ C cinv(C a) {
+    // 1/a with the larger component factored out (Smith's scaling)
+    if (fabs((double)a.x) >= fabs((double)a.y)) {
+        double r = (double)a.y / (double)a.x, den = (double)a.x + (double)a.y * r;
+        return mk<C>(1.0 / den, -r / den);
+    } else {
+        double r = (double)a.x / (double)a.y, den = (double)a.x * r + (double)a.y;
+        return mk<C>(r / den, -1.0 / den);
+    }
+}
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 result held in accumulator element e by lane group g
+// (lanes 16g .. 16g+15 hold columns 0..15): the FP64 instruction interleaves
+// the rows (g + 4e), the FP32 one keeps them contiguous (4g + e).
+template <typename T> __device__ __forceinline__ int acc_row(int g, int e);
+template <> __device__ __forceinline__ int acc_row<double>(int g, int e) { return g + 4 * e; }
+template <> __device__ __forceinline__ int acc_row<float>(int g, int e) { return 4 * g + e; }
+
+// (cr + i ci) += (ar + i ai)(br + i bi) for one 16x16x4 block
+template <typename T, typename V>
+__device__ __forceinline__ void cmfma(V& cr, V& ci, T ar, T ai, T br, T bi) {
+    cr = mfma16(ar, br, cr);
+    cr = mfma16(-ai, bi, cr);
+    ci = mfma16(ar, bi, ci);
+    ci = mfma16(ai, br, ci);
+}
+
+// ---------------------------------------------------------------- assembly --
+__device__ __forceinline__ double half_at_ends(int idx, int n) { return (idx == 0 || idx == n - 1) ? 0.5 : 1.0; }
+__device__ __forceinline__ double x_coupling(const Coef& c, int j) { return (c.hz / c.hx) * half_at_ends(j, c.nz); }
+__device__ __forceinline__ double z_coupling(const Coef& c, int i) { return (c.hx / c.hz) * half_at_ends(i, c.nx); }
+
+// A(m, w) at node (i, j), diagonal entry
+__device__ __forceinline__ double2 diag_entry(const Coef& c, int i, int j) {
+    double cx = x_coupling(c, j), cz = z_coupling(c, i);
+    double s = 0.0;
+    if (i > 0) s += cx;
+    if (i < c.nx - 1) s += cx;
+    if (j > 0) s += cz;
+    if (j < c.nz - 1) s += cz;
+    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
+    double bnd = 0.0;
+    if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
+    if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
+    double mk_ = c.m[(size_t)j * c.nx + i];
+    return make_double2(s - c.omega * c.omega * mass * mk_, -c.omega * bnd * sqrt(mk_));
+}
+
+// entry (r, q) of the padded diagonal block A_j (identity in the padding)
+__device__ __forceinline__ double2 block_entry(const Coef& c, int j, int r, int q) {
+    if (r >= c.nx || q >= c.nx) return make_double2(r == q ? 1.0 : 0.0, 0.0);
+    if (r == q) return diag_entry(c, r, j);
+    if (r == q + 1 || q == r + 1) return make_double2(-x_coupling(c, j), 0.0);
+    return make_double2(0.0, 0.0);
+}
+
+// coupling E_ii between rows j and j+1 (zero in the padding)
+__device__ __forceinline__ double row_coupling(const Coef& c, int i) { return i < c.nx ? -z_coupling(c, i) : 0.0; }
+
+// chain owning workgroup `bid`, given each chain's first workgroup
+template <typename Info, typename F>
+__device__ __forceinline__ int find_chain(const Info* tab, int n, int bid, F first) {
+    int c = 0;
+    while (c + 1 < n && bid >= first(tab[c + 1])) ++c;
+    return c;
+}
+
+// the panel step a chain performs at global step t: block j, panel p
+// (columns k0 .. k0+kb-1 of the block)
+struct PanelStep {
+    int j, p, k0, kb, last_panel;
+};
+__device__ __forceinline__ PanelStep panel_step(const ChainInfo& c, int t) {
+    PanelStep s;
+    s.j = t / c.npan;
+    s.p = t - s.j * c.npan;
+    s.k0 = s.p * KB;
+    s.kb = min(KB, c.np - s.k0);
+    s.last_panel = s.p == c.npan - 1;
+    return s;
+}
+
+}  // namespace helm

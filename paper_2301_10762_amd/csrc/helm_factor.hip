@@ -1,0 +1,535 @@
+// Block factorisation kernels of libhelm (gfx950).
+//
+// For each system the Schur complements of the block-tridiagonal operator,
+//     D_0 = A_0,   D_{j+1} = A_{j+1} - E D_j^{-1} E,
+// are inverted in place by block Gauss-Jordan on panels of KB = 32 columns.
+// Panel K of block j, with T = (X_KK)^{-1} the inverse of its diagonal tile
+// (pivoting inside the tile only), maps the working block X to
+//     Y = X' + W V,   W = [-X_{:,K} T ; T - I],   V = [X_{K,:} with V_KK = I],
+// X' = X with the K columns cleared except X'_KK = I.  After the last panel Y
+// is D_j^{-1}; the same launch also writes D_{j+1} for the next block.
+//
+// One launch per panel step serves every chain of the batch.  Its
+// workgroups are the 64 x 64 output tiles of Y (each forms its rows of W
+// from X and T itself, so X and Y live in different buffers and no copy of
+// V is needed) plus one workgroup per chain that builds the diagonal tile
+// the NEXT step needs,
+//     Z = X_{K'K'} - X_{K'K} T X_{KK'}            (next panel K' of block j), or
+//     Z = A_{j+1}[K'K'] - E (Y restricted) E       (first panel of block j+1),
+// and inverts it, so the sequential pivoting of the next step runs
+// concurrently with this step's matrix-core update.
+#include "helm_device.h"
+
+namespace helm {
+
+// --------------------------------------------------- diagonal-tile inverse --
+// Gauss-Jordan inversion of a kb x kb tile (kb = 16 or 32) by 256 threads:
+// thread t holds row r = t/8 (wave w = t/64 holds rows 8w..8w+7) and columns
+// 4(t%8) .. 4(t%8)+3.  Partial pivoting over the unused rows of the tile.
+// Each wave nominates its best candidate row for the next column (key =
+// magnitude bits with the row index in the low bits, reduced with DPP) and
+// publishes it with the row's values; one barrier per pivot.  Rows are not
+// moved: the pivot of column p sits in row rowOf[p], and the inverse is
+// T[i][c] = M[rowOf[i]][stepOf[c]].
+
+template <typename T>
+struct GJScratch {
+    uint32_t key[2][4];
+    typename CT<T>::c row[2][4][32];
+    int rowOf[32];
+    int stepOf[32];
+};
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row half-mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+    const uint32_t a = __builtin_amdgcn_readlane((int)v, 0), b = __builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = __builtin_amdgcn_readlane((int)v, 32), d = __builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+// value held by lane (l & ~7) | src within each group of 32 lanes
+template <int SRC>
+__device__ __forceinline__ int swz_row(int v) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x18 | (SRC << 5));
+}
+template <int SRC>
+__device__ __forceinline__ double swz_row(double v) {
+    const int lo = swz_row<SRC>(__double2loint(v)), hi = swz_row<SRC>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int SRC>
+__device__ __forceinline__ float swz_row(float v) {
+    return __int_as_float(swz_row<SRC>(__float_as_int(v)));
+}
+template <typename T>
+__device__ __forceinline__ typename CT<T>::c swz_row_c(typename CT<T>::c v, int src) {
+    using C = typename CT<T>::c;
+    C r;
+    switch (src) {
+#define HELM_SWZ(k) case k: r.x = swz_row<k>(v.x); r.y = swz_row<k>(v.y); break;
+        HELM_SWZ(0) HELM_SWZ(1) HELM_SWZ(2) HELM_SWZ(3) HELM_SWZ(4) HELM_SWZ(5) HELM_SWZ(6)
+        default: r.x = swz_row<7>(v.x); r.y = swz_row<7>(v.y); break;
+#undef HELM_SWZ
+    }
+    return r;
+}
+
+// 1 / p for complex p, reciprocal of |p|^2 refined by Newton steps
+__device__ __forceinline__ double2 crcp(double2 p) {
+    const double n = p.x * p.x + p.y * p.y;
+    double y = __builtin_amdgcn_rcp(n);
+    y = y * (2.0 - n * y);
+    y = y * (2.0 - n * y);
+    return make_double2(p.x * y, -p.y * y);
+}
+__device__ __forceinline__ float2 crcp(float2 p) {
+    const float n = p.x * p.x + p.y * p.y;
+    float y = __builtin_amdgcn_rcpf(n);
+    y = y * (2.0f - n * y);
+    return make_float2(p.x * y, -p.y * y);
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t pivot_key(typename CT<T>::c v, int r, bool cand) {
+    if (!cand) return 0u;
+    const float mag = (float)(v.x * v.x + v.y * v.y);
+    return (__float_as_uint(mag) & ~0x3Fu) | 0x20u | (uint32_t)(31 - r);
+}
+
+// Inverts the tile held in a[] (layout above); on return a[] holds M and
+// sh.rowOf / sh.stepOf the pivot order (valid after a barrier).  Returns the
+// first pivot step whose candidates were all zero, or -1.
+template <typename T, int KBT>
+__device__ __forceinline__ int gj_invert(typename CT<T>::c (&a)[4], GJScratch<T>& sh) {
+    using C = typename CT<T>::c;
+    constexpr int NW = KBT / 8;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < KBT) && (4 * cg < KBT);
+    uint32_t used = 0u;
+    int zero = -1;
+    {
+        const uint32_t k = pivot_key<T>(a[0], r, act && cg == 0);
+        const uint32_t wk = wave_max_u32(k);
+        if (w < NW) {
+            if (act && wk != 0u && r == 31 - (int)(wk & 31u)) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sh.row[0][w][4 * cg + e] = a[e];
+            }
+            if (l == 0) sh.key[0][w] = wk;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < KBT; ++p) {
+        const int par = p & 1;
+        const int pc = p >> 2, pe = p & 3;
+        __syncthreads();
+        uint32_t best = sh.key[par][0];
+        int wb = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const uint32_t kq = sh.key[par][q];
+            if (kq > best) { best = kq; wb = q; }
+        }
+        const int rp = 31 - (int)(best & 31u);
+        const bool good = (best >> 6) != 0u;
+        if (!good && zero < 0) zero = p;
+        const C piv = sh.row[par][wb][p];
+        C pr[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pr[e] = sh.row[par][wb][4 * cg + e];
+        const C f = swz_row_c<T>(a[pe], pc);
+        const C dv = good ? crcp(piv) : mk<C>(0.0, 0.0);
+        if (act) {
+            if (r == rp) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[e] = (4 * cg + e == p) ? dv : cmul(pr[e], dv);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (4 * cg + e == p) {
+                        a[e] = mk<C>(-(f.x * dv.x - f.y * dv.y), -(f.x * dv.y + f.y * dv.x));
+                    } else {
+                        const C s = cmul(pr[e], dv);
+                        a[e] = mk<C>(a[e].x - (f.x * s.x - f.y * s.y), a[e].y - (f.x * s.y + f.y * s.x));
+                    }
+                }
+            }
+        }
+        used |= 1u << rp;
+        if (t == 0) { sh.rowOf[p] = rp; sh.stepOf[rp] = p; }
+        if (p + 1 < KBT) {
+            const int pc1 = (p + 1) >> 2, pe1 = (p + 1) & 3;
+            const uint32_t k = pivot_key<T>(a[pe1], r, act && cg == pc1 && !((used >> r) & 1u));
+            const uint32_t wk = wave_max_u32(k);
+            if (w < NW) {
+                if (act && wk != 0u && r == 31 - (int)(wk & 31u)) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sh.row[par ^ 1][w][4 * cg + e] = a[e];
+                }
+                if (l == 0) sh.key[par ^ 1][w] = wk;
+            }
+        }
+    }
+    return zero;
+}
+
+// Invert the kb x kb tile in a[] and store its inverse transposed
+// (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer.
+// Returns the first zero-pivot step or -1.
+template <typename T>
+__device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, GJScratch<T>& sh,
+                                typename CT<T>::c (*M)[33], typename CT<T>::c* Tt) {
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    const bool act = (r < kb) && (4 * cg < kb);
+    int zero = (kb == 32) ? gj_invert<T, 32>(a, sh) : gj_invert<T, 16>(a, sh);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) M[r][4 * cg + e] = a[e];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * cg + e;
+            Tt[c * KB + r] = M[sh.rowOf[r]][sh.stepOf[c]];
+        }
+    }
+    return zero;
+}
+
+__device__ __forceinline__ void report_zero_pivot(int* status, int block, int row) {
+    if (atomicCAS(&status[0], 0, 1) == 0) {
+        status[1] = block;
+        status[2] = row;
+    }
+}
+
+// ----------------------------------------------------------------- launches --
+// LDS of a step workgroup: update tiles use sW, sV (64 x 33 each); the
+// next-tile workgroup four 32 x 33 blocks and the pivoting scratch
+constexpr size_t SM_UPDATE = 2 * 64 * 33 * sizeof(double2);
+constexpr size_t SM_NEXT = 4 * 32 * 33 * sizeof(double2) + sizeof(GJScratch<double>);
+constexpr size_t SM_BYTES_D = SM_UPDATE > SM_NEXT ? SM_UPDATE : SM_NEXT;
+
+__host__ __device__ int init_blocks(int np) { return (int)(((int64_t)np * np + 255) / 256) + 1; }
+__host__ __device__ int step_blocks(int np) {
+    const int tx = (np + TILE - 1) / TILE;
+    return tx * tx + 1;
+}
+int factor_init_blocks(int np) { return init_blocks(np); }
+int factor_step_blocks(int np) { return step_blocks(np); }
+
+// D_0 = A_0 into block 0, and T_0 = (first diagonal tile of A_0)^{-1}
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n) {
+    using C = typename CT<T>::c;
+    __shared__ C M[32][33];
+    __shared__ GJScratch<T> sh;
+    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
+    const ChainInfo& d = tab[ci];
+    const int local = blockIdx.x - d.itile0;
+    const int np = d.np;
+    const int nfill = init_blocks(np) - 1;
+    if (local < nfill) {
+        const int64_t e = (int64_t)local * 256 + threadIdx.x;
+        if (e < (int64_t)np * np) {
+            const int r = (int)(e / np), q = (int)(e % np);
+            const double2 v = block_entry(d.cf, 0, r, q);
+            ((C*)d.G)[e] = mk<C>(v.x, v.y);
+        }
+        return;
+    }
+    const int kb = min(KB, np);
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    C a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = 4 * cg + e;
+        const double2 v = (r < kb && c < kb) ? block_entry(d.cf, 0, r, c) : make_double2(0.0, 0.0);
+        a[e] = mk<C>(v.x, v.y);
+    }
+    const int zero = invert_and_store<T>(a, kb, sh, M, (C*)d.Tb);
+    if (zero >= 0 && t == 0) report_zero_pivot(d.status, 0, zero);
+}
+
+// workgroup that prepares the next step's inverted diagonal tile
+template <typename T>
+__device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& ps, const typename CT<T>::c* X,
+                          const typename CT<T>::c* Tcur, typename CT<T>::c* Tnext, char* smem) {
+    using C = typename CT<T>::c;
+    const int np = d.np, kb = ps.kb, k0 = ps.k0;
+    int jn, kn0, kbn;
+    if (!ps.last_panel) {
+        jn = ps.j;
+        kn0 = k0 + kb;
+    } else {
+        if (ps.j + 1 >= d.cf.nz) return;
+        jn = ps.j + 1;
+        kn0 = 0;
+    }
+    kbn = min(KB, np - kn0);
+    C (*sXa)[33] = (C(*)[33])smem;                      // X_{K'K}    kbn x kb
+    C (*sT)[33] = (C(*)[33])(smem + 1 * 32 * 33 * sizeof(C));   // T   kb x kb
+    C (*sXb)[33] = (C(*)[33])(smem + 2 * 32 * 33 * sizeof(C));  // X_{KK'}    kb x kbn
+    C (*sP)[33] = (C(*)[33])(smem + 3 * 32 * 33 * sizeof(C));   // X_{K'K} T  kbn x kb
+    GJScratch<T>& sh = *(GJScratch<T>*)(smem + 4 * 32 * 33 * sizeof(C));
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    const bool single = ps.last_panel && d.npan == 1;   // next tile is Y = T itself
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = t + 256 * i;
+        const int rr = idx >> 5, cc = idx & 31;
+        sT[rr][cc] = (rr < kb && cc < kb) ? Tcur[cc * KB + rr] : mk<C>(0.0, 0.0);
+        if (!single) {
+            sXa[rr][cc] = (rr < kbn && cc < kb) ? X[(size_t)(kn0 + rr) * np + k0 + cc] : mk<C>(0.0, 0.0);
+            sXb[rr][cc] = (rr < kb && cc < kbn) ? X[(size_t)(k0 + rr) * np + kn0 + cc] : mk<C>(0.0, 0.0);
+        }
+    }
+    C a[4];
+    const bool act = (r < kbn) && (4 * cg < kbn);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        a[e] = (act && !single) ? X[(size_t)(kn0 + r) * np + kn0 + 4 * cg + e] : mk<C>(0.0, 0.0);
+    __syncthreads();
+    if (single) {
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[e] = sT[r][4 * cg + e];
+        }
+    } else {
+        // P = X_{K'K} T
+        if (r < kbn && 4 * cg < kb) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 4 * cg + e;
+                T sr = 0, si = 0;
+                for (int k = 0; k < kb; ++k) {
+                    const C x = sXa[r][k], y = sT[k][c];
+                    sr += x.x * y.x - x.y * y.y;
+                    si += x.x * y.y + x.y * y.x;
+                }
+                sP[r][c] = mk<C>(sr, si);
+            }
+        }
+        __syncthreads();
+        // Z = X_{K'K'} - P X_{KK'}
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 4 * cg + e;
+                T sr = 0, si = 0;
+                for (int k = 0; k < kb; ++k) {
+                    const C x = sP[r][k], y = sXb[k][c];
+                    sr += x.x * y.x - x.y * y.y;
+                    si += x.x * y.y + x.y * y.x;
+                }
+                a[e] = mk<C>(a[e].x - sr, a[e].y - si);
+            }
+        }
+    }
+    if (ps.last_panel && act) {
+        // Schur complement of the next block: A_{j+1} - E G_j E on this tile
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * cg + e;
+            const double2 a1 = block_entry(d.cf, jn, r, c);
+            const double s = row_coupling(d.cf, r) * row_coupling(d.cf, c);
+            a[e] = mk<C>(a1.x - s * (double)a[e].x, a1.y - s * (double)a[e].y);
+        }
+    }
+    __syncthreads();   // sXa is reused as the inversion buffer
+    const int zero = invert_and_store<T>(a, kbn, sh, sXa, Tnext);
+    if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
+}
+
+// update of one 64 x 64 tile of Y
+template <typename T>
+__device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep& ps, int ti, const typename CT<T>::c* X,
+                            typename CT<T>::c* Y, const typename CT<T>::c* Tcur, char* smem) {
+    using C = typename CT<T>::c;
+    using V = typename CT<T>::v4;
+    const int np = d.np, kb = ps.kb, k0 = ps.k0;
+    const int tiles_x = (np + TILE - 1) / TILE;
+    const int I0 = (ti / tiles_x) * TILE, J0 = (ti % tiles_x) * TILE;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int lr = l & 15, lg = l >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    C (*sW)[33] = (C(*)[33])smem;                      // W rows I0..I0+63, k < kb
+    C (*sV)[33] = (C(*)[33])(smem + 64 * 33 * sizeof(C));  // V^T: sV[c][k], c = J0..J0+63
+
+    int R[2], Cc[2];
+    bool vr[2], vc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        R[q] = I0 + 32 * wr + 16 * q;
+        Cc[q] = J0 + 32 * wc + 16 * q;
+        vr[q] = R[q] < np;
+        vc[q] = Cc[q] < np;
+    }
+    // 1. this tile of X' (loads issued first)
+    V accr[2][2], acci[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { accr[bi][bj][e] = 0; acci[bi][bj][e] = 0; }
+            if (vr[bi] && vc[bj]) {
+                const int col = Cc[bj] + lr;
+                const bool inK = col >= k0 && col < k0 + kb;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = R[bi] + acc_row<T>(lg, e);
+                    const C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : X[(size_t)row * np + col];
+                    accr[bi][bj][e] = v.x;
+                    acci[bi][bj][e] = v.y;
+                }
+            }
+        }
+    // 2. V_J into LDS (transposed), V_KK = I
+    for (int i = t; i < kb * TILE; i += 256) {
+        const int k = i >> 6, cc = i & 63, col = J0 + cc;
+        C v = mk<C>(0.0, 0.0);
+        if (col < np) v = (col >= k0 && col < k0 + kb) ? mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0)
+                                                       : X[(size_t)(k0 + k) * np + col];
+        sV[cc][k] = v;
+    }
+    // 3. W_I = -X_{I,K} T (matrix cores; wave w makes rows I0+16w .. +15), T - I on rows of K
+    {
+        const int row0 = I0 + 16 * w;
+        if (row0 < np) {
+            for (int cb = 0; cb < kb / 16; ++cb) {
+                V wr_, wi_;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) { wr_[e] = 0; wi_[e] = 0; }
+                for (int kk = 0; kk < kb; kk += 16) {
+                    C av[4], bv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        av[q] = X[(size_t)(row0 + lr) * np + k0 + kk + 4 * lg + q];
+                        bv[q] = Tcur[(cb * 16 + lr) * KB + kk + 4 * lg + q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cmfma<T, V>(wr_, wi_, av[q].x, av[q].y, bv[q].x, bv[q].y);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rl = 16 * w + acc_row<T>(lg, e), row = I0 + rl, c = cb * 16 + lr;
+                    C v;
+                    if (row >= k0 && row < k0 + kb) {
+                        v = Tcur[c * KB + (row - k0)];
+                        if (row - k0 == c) v.x -= (T)1;
+                    } else {
+                        v = mk<C>(-wr_[e], -wi_[e]);
+                    }
+                    sW[rl][c] = v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // 4. Y_IJ = X'_IJ + W_I V_J
+    for (int kk = 0; kk < kb; kk += 16) {
+        C av[2][4], bv[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                av[q][s] = sW[32 * wr + 16 * q + lr][kk + 4 * lg + s];
+                bv[q][s] = sV[32 * wc + 16 * q + lr][kk + 4 * lg + s];
+            }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    if (vr[bi] && vc[bj])
+                        cmfma<T, V>(accr[bi][bj], acci[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
+                                    bv[bj][s].y);
+    }
+    // 5. store; after the last panel also D_{j+1} = A_{j+1} - E Y E
+    const bool schur = ps.last_panel && ps.j + 1 < d.cf.nz;
+    C* An = (C*)d.G + (size_t)(ps.j + 1) * np * np;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            if (!(vr[bi] && vc[bj])) continue;
+            const int col = Cc[bj] + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = R[bi] + acc_row<T>(lg, e);
+                const C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
+                Y[(size_t)row * np + col] = g;
+                if (schur) {
+                    const double2 a1 = block_entry(d.cf, ps.j + 1, row, col);
+                    const double s = row_coupling(d.cf, row) * row_coupling(d.cf, col);
+                    An[(size_t)row * np + col] = mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
+                }
+            }
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor_step(const ChainInfo* tab, int n, int tstep) {
+    using C = typename CT<T>::c;
+    __shared__ __attribute__((aligned(16))) char smem[SM_BYTES_D];
+    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
+    const ChainInfo& d = tab[ci];
+    if (tstep >= d.T) return;
+    const PanelStep ps = panel_step(d, tstep);
+    const int np = d.np;
+    const size_t n2 = (size_t)np * np;
+    C* G = (C*)d.G;
+    const C* X = ps.p == 0 ? G + (size_t)ps.j * n2 : (const C*)((ps.p - 1) & 1 ? d.P1 : d.P0);
+    C* Y = ps.last_panel ? G + (size_t)ps.j * n2 : (C*)(ps.p & 1 ? d.P1 : d.P0);
+    const C* Tcur = (const C*)d.Tb + (size_t)(tstep & 1) * KB * KB;
+    C* Tnext = (C*)d.Tb + (size_t)((tstep + 1) & 1) * KB * KB;
+    const int ti = blockIdx.x - d.utile0;
+    if (ti == step_blocks(np) - 1) {
+        next_tile<T>(d, ps, X, Tcur, Tnext, smem);
+    } else {
+        update_tile<T>(d, ps, ti, X, Y, Tcur, smem);
+    }
+}
+
+// standalone tile inverses (the building block above, for tests)
+__global__ __launch_bounds__(256) void k_tile_inverse(int kb, const double2* A, double2* Tout, int* status) {
+    __shared__ double2 M[32][33];
+    __shared__ GJScratch<double> sh;
+    __shared__ double2 Tt[KB * KB];
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    const double2* Am = A + (size_t)blockIdx.x * kb * kb;
+    double2 a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = 4 * cg + e;
+        a[e] = (r < kb && c < kb) ? Am[r * kb + c] : make_double2(0.0, 0.0);
+    }
+    const int zero = invert_and_store<double>(a, kb, sh, M, Tt);
+    __syncthreads();
+    for (int i = t; i < kb * kb; i += 256) {
+        const int rr = i / kb, c = i % kb;
+        Tout[(size_t)blockIdx.x * kb * kb + i] = Tt[c * KB + rr];
+    }
+    if (t == 0 && zero >= 0) status[blockIdx.x] = 1 + zero;
+}
+
+void launch_factor_init(const ChainInfo* tab, int n, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_factor_init<float>, dim3(total), dim3(256), 0, st, tab, n);
+    else hipLaunchKernelGGL(k_factor_init<double>, dim3(total), dim3(256), 0, st, tab, n);
+}
+void launch_factor_step(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t);
+    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t);
+}
+void launch_tile_inverse(int count, int kb, const double* A, double* T, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, (const double2*)A, (double2*)T, status);
+}
+
+}  // namespace helm

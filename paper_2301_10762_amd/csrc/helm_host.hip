@@ -115,6 +115,53 @@ struct PinnedRing {
 };
 PinnedRing g_ring;
 
+// Optional live timing of the dominant kernels with HIP events: every
+// `stride`-th launch of a kind is bracketed by two events on its stream.
+struct KernelTimer {
+    std::mutex mu;
+    int enabled = 0, stride = 1;
+    int64_t seen[3] = {0, 0, 0};
+    struct Pair {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pair> pending;
+    double total_ms[3] = {0, 0, 0};
+    int64_t count[3] = {0, 0, 0};
+    bool begin(int kind, hipStream_t st, Pair* p) {
+        if (!enabled) return false;
+        std::lock_guard<std::mutex> lk(mu);
+        if ((seen[kind]++ % stride) != 0) return false;
+        p->kind = kind;
+        if (hipEventCreate(&p->a) != hipSuccess) return false;
+        if (hipEventCreate(&p->b) != hipSuccess) {
+            (void)hipEventDestroy(p->a);
+            return false;
+        }
+        (void)hipEventRecord(p->a, st);
+        return true;
+    }
+    void end(Pair& p, hipStream_t st) {
+        (void)hipEventRecord(p.b, st);
+        std::lock_guard<std::mutex> lk(mu);
+        pending.push_back(p);
+    }
+    void drain() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                total_ms[p.kind] += ms;
+                count[p.kind] += 1;
+            }
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        pending.clear();
+    }
+};
+KernelTimer g_timer;
+
 Coef coef_of(const helm_factor_s* f) {
     Coef c;
     c.m = f->m;
@@ -143,15 +190,16 @@ int check_model(const double* m, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------ factorisation --
-// Factor a group of at most MAXB chains of one precision in lockstep.
+// Factor a group of at most MAXB chains of one precision in lockstep: one
+// initial launch, then one launch per panel step.
 int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
     const size_t es = elem_bytes(fs[0]->prec);
     Scratch sc(st);
     std::vector<ChainInfo> tab(n);
-    int ptot = 0, utot = 0, itot = 0, Tmax = 0;
+    int utot = 0, itot = 0, Tmax = 0;
     size_t buf = 0;
-    for (int c = 0; c < n; ++c) buf += 2 * (size_t)fs[c]->np * KB * es + 64;
+    for (int c = 0; c < n; ++c) buf += (2 * (size_t)fs[c]->np * fs[c]->np + 2 * (size_t)KB * KB) * es + 256;
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
@@ -159,38 +207,46 @@ int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
     if ((rc = sc.get(&status, sizeof(int) * 4 * n))) return rc;
     launch_zero(status, sizeof(int) * 4 * n, st);
     size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void* p = arena + off;
+        off = (off + bytes + 255) / 256 * 256;
+        return p;
+    };
     for (int c = 0; c < n; ++c) {
         helm_factor_s* f = fs[c];
         ChainInfo& ci = tab[c];
+        const size_t n2 = (size_t)f->np * f->np;
         ci.G = f->G;
-        ci.W = arena + off;
-        off += (size_t)f->np * KB * es;
-        ci.Vt = arena + off;
-        off += (size_t)f->np * KB * es;
-        off = (off + 63) / 64 * 64;
+        ci.P0 = take(n2 * es);
+        ci.P1 = take(n2 * es);
+        ci.Tb = take(2 * (size_t)KB * KB * es);
         ci.status = status + 4 * c;
         ci.cf = coef_of(f);
         ci.np = f->np;
         ci.npan = (f->np + KB - 1) / KB;
         ci.T = ci.npan * f->g.nz;
-        ci.ptile0 = ptot;
-        ptot += (f->np + PR - 1) / PR;
-        const int tx = (f->np + TILE - 1) / TILE;
         ci.utile0 = utot;
-        utot += tx * tx;
+        utot += factor_step_blocks(f->np);
         ci.itile0 = itot;
-        itot += (int)(((int64_t)f->np * f->np + 255) / 256);
+        itot += factor_init_blocks(f->np);
         Tmax = std::max(Tmax, ci.T);
     }
     ChainInfo* dtab;
     if ((rc = sc.get(&dtab, sizeof(ChainInfo) * n))) return rc;
     if ((rc = g_ring.upload(dtab, tab.data(), sizeof(ChainInfo) * n, st))) return rc;
-    launch_init_block0(dtab, n, itot, fp32, st);
-    for (int t = 0; t < Tmax; ++t) {
-        launch_panel(dtab, n, t, ptot, fp32, st);
-        launch_update(dtab, n, t, utot, fp32, st);
+    {
+        KernelTimer::Pair pi;
+        const bool ti = g_timer.begin(1, st, &pi);
+        launch_factor_init(dtab, n, itot, fp32, st);
+        if (ti) g_timer.end(pi, st);
     }
-    g_launches += 2 + 2 * (int64_t)Tmax;
+    for (int t = 0; t < Tmax; ++t) {
+        KernelTimer::Pair pu;
+        const bool tu = g_timer.begin(0, st, &pu);
+        launch_factor_step(dtab, n, t, utot, fp32, st);
+        if (tu) g_timer.end(pu, st);
+    }
+    g_launches += 2 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
     std::vector<int> hs(4 * n);
     HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * 4 * n, hipMemcpyDeviceToHost, st));
@@ -294,8 +350,18 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     int rc = sc.get(&dtab, sizeof(SweepInfo) * n);
     if (rc) return rc;
     if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * n, st))) return rc;
-    for (int t = 0; t < steps; ++t) launch_sweep(dtab, n, t, tot, fp32, true, conj_b, st);
-    for (int t = 0; t + 1 < steps; ++t) launch_sweep(dtab, n, t, tot, fp32, false, false, st);
+    for (int t = 0; t < steps; ++t) {
+        KernelTimer::Pair p;
+        const bool tm = g_timer.begin(2, st, &p);
+        launch_sweep(dtab, n, t, tot, fp32, true, conj_b, st);
+        if (tm) g_timer.end(p, st);
+    }
+    for (int t = 0; t + 1 < steps; ++t) {
+        KernelTimer::Pair p;
+        const bool tm = g_timer.begin(2, st, &p);
+        launch_sweep(dtab, n, t, tot, fp32, false, false, st);
+        if (tm) g_timer.end(p, st);
+    }
     g_launches += 2 * (int64_t)steps - 1;
     HIPCHECK(hipGetLastError());
     return HELM_OK;
@@ -524,6 +590,27 @@ extern "C" {
 const char* helm_last_error(void) { return g_err.c_str(); }
 
 int64_t helm_counter(int which) { return which == 0 ? g_launches.load() : g_solves.load(); }
+
+void helm_kernel_timing(int enable, int stride) {
+    g_timer.drain();
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.enabled = enable;
+    g_timer.stride = stride > 0 ? stride : 1;
+    for (int k = 0; k < 3; ++k) {
+        g_timer.seen[k] = 0;
+        g_timer.total_ms[k] = 0.0;
+        g_timer.count[k] = 0;
+    }
+}
+
+int helm_kernel_time(int kind, double* total_ms, int64_t* count) {
+    if (kind < 0 || kind > 2 || !total_ms || !count) return fail(HELM_EINVAL, "bad kernel kind");
+    g_timer.drain();
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    *total_ms = g_timer.total_ms[kind];
+    *count = g_timer.count[kind];
+    return HELM_OK;
+}
 
 int helm_factor_bytes(const helm_grid* grid, int precision, size_t* bytes) {
     int rc = check_grid(grid);

@@ -8,7 +8,6 @@ namespace helm {
 
 constexpr int MAXB = 16;   // chains (independent systems) per batched launch
 constexpr int TILE = 64;   // output tile of the rank-kb update (64 x 64)
-constexpr int PR = 32;     // rows of the panel product W handled per workgroup
 constexpr int KB = 32;     // panel width (columns eliminated per Gauss-Jordan step)
 
 // Everything needed to assemble A(m, w) on the fly (App. A.1).
@@ -19,17 +18,19 @@ struct Coef {
 };
 
 // One chain (one system) of a batched factorisation.  The table lives in
-// device memory; a launch for global step t makes every chain with t < T do
-// its panel step (j, p) = (t / npan, t % npan).
+// device memory; the launch for global step t makes every chain with t < T
+// do panel p = t % npan of block j = t / npan.
 struct ChainInfo {
-    void* G;        // nz blocks of np x np row-major complex; block j holds D_j -> D_j^{-1}
-    void* W;        // np x KB row-major panel multipliers
-    void* Vt;       // np x KB row-major: Vt[c][t] = (row k0+t of the working block)[c]
+    void* G;        // nz blocks of np x np row-major complex; block j ends as D_j^{-1}
+    void* P0;       // ping-pong working blocks (np x np) between panel steps
+    void* P1;
+    void* Tb;       // two KB x KB slots holding the inverted diagonal tile,
+                    // transposed (Tt[c][k] = T[k][c]); step t reads slot t&1
     int* status;    // [0] failure flag, [1] block, [2] row
     Coef cf;
     int np, npan, T;        // padded size, panels per block, steps (nz * npan)
-    int ptile0, utile0;     // first workgroup of this chain in panel / update launches
-    int itile0;             // first workgroup in the block-0 assembly launch
+    int utile0;             // first workgroup of this chain in a step launch
+    int itile0;             // first workgroup in the initial launch
 };
 
 // One chain of a batched block sweep.
@@ -44,9 +45,11 @@ struct SweepInfo {
 };
 
 // kernel launchers (helm_kernels.hip); `fp32` selects the complex64 variants
-void launch_init_block0(const ChainInfo* tab, int n, int total_blocks, bool fp32, hipStream_t st);
-void launch_panel(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
-void launch_update(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
+// workgroups per chain of the factorisation launches
+int factor_init_blocks(int np);
+int factor_step_blocks(int np);
+void launch_factor_init(const ChainInfo* tab, int n, int total_blocks, bool fp32, hipStream_t st);
+void launch_factor_step(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
 // forward: step t is block j = t; backward: step t is block j = nz - 2 - t
 void launch_sweep(const SweepInfo* tab, int n, int t, int total_blocks, bool fp32, bool forward,
                   bool conj_b, hipStream_t st);

@@ -25,399 +25,9 @@
 // k index owned by lane group l/16; each lane loads four consecutive k of
 // its row/column (64 contiguous bytes) and feeds them to four successive
 // instructions, so every operand load is a contiguous vector load.
-#include "helm_internal.h"
+#include "helm_device.h"
 
 namespace helm {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T> struct CT;
-template <> struct CT<double> { using c = double2; using v4 = v4d; };
-template <> struct CT<float> { using c = float2; using v4 = v4f; };
-
-template <typename C> __device__ __forceinline__ C mk(double re, double im) { C r; r.x = re; r.y = im; return r; }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
-template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
-template <typename C> __device__ __forceinline__ C cscale(C a, double s) { return mk<C>(a.x * s, a.y * s); }
-template <typename C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
-template <typename C> __device__ __forceinline__ C cinv(C a) {
-    // 1/a with the larger component factored out (Smith's scaling)
-    if (fabs((double)a.x) >= fabs((double)a.y)) {
-        double r = (double)a.y / (double)a.x, den = (double)a.x + (double)a.y * r;
-        return mk<C>(1.0 / den, -r / den);
-    } else {
-        double r = (double)a.x / (double)a.y, den = (double)a.x * r + (double)a.y;
-        return mk<C>(r / den, -1.0 / den);
-    }
-}
-
-__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Row of the 16x16 result held in accumulator element e by lane group g
-// (lanes 16g .. 16g+15 hold columns 0..15): the FP64 instruction interleaves
-// the rows (g + 4e), the FP32 one keeps them contiguous (4g + e).
-template <typename T> __device__ __forceinline__ int acc_row(int g, int e);
-template <> __device__ __forceinline__ int acc_row<double>(int g, int e) { return g + 4 * e; }
-template <> __device__ __forceinline__ int acc_row<float>(int g, int e) { return 4 * g + e; }
-
-// (cr + i ci) += (ar + i ai)(br + i bi) for one 16x16x4 block
-template <typename T, typename V>
-__device__ __forceinline__ void cmfma(V& cr, V& ci, T ar, T ai, T br, T bi) {
-    cr = mfma16(ar, br, cr);
-    cr = mfma16(-ai, bi, cr);
-    ci = mfma16(ar, bi, ci);
-    ci = mfma16(ai, br, ci);
-}
-
-// ---------------------------------------------------------------- assembly --
-__device__ __forceinline__ double half_at_ends(int idx, int n) { return (idx == 0 || idx == n - 1) ? 0.5 : 1.0; }
-__device__ __forceinline__ double x_coupling(const Coef& c, int j) { return (c.hz / c.hx) * half_at_ends(j, c.nz); }
-__device__ __forceinline__ double z_coupling(const Coef& c, int i) { return (c.hx / c.hz) * half_at_ends(i, c.nx); }
-
-// A(m, w) at node (i, j), diagonal entry
-__device__ __forceinline__ double2 diag_entry(const Coef& c, int i, int j) {
-    double cx = x_coupling(c, j), cz = z_coupling(c, i);
-    double s = 0.0;
-    if (i > 0) s += cx;
-    if (i < c.nx - 1) s += cx;
-    if (j > 0) s += cz;
-    if (j < c.nz - 1) s += cz;
-    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
-    double bnd = 0.0;
-    if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
-    if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
-    double mk_ = c.m[(size_t)j * c.nx + i];
-    return make_double2(s - c.omega * c.omega * mass * mk_, -c.omega * bnd * sqrt(mk_));
-}
-
-// entry (r, q) of the padded diagonal block A_j (identity in the padding)
-__device__ __forceinline__ double2 block_entry(const Coef& c, int j, int r, int q) {
-    if (r >= c.nx || q >= c.nx) return make_double2(r == q ? 1.0 : 0.0, 0.0);
-    if (r == q) return diag_entry(c, r, j);
-    if (r == q + 1 || q == r + 1) return make_double2(-x_coupling(c, j), 0.0);
-    return make_double2(0.0, 0.0);
-}
-
-// coupling E_ii between rows j and j+1 (zero in the padding)
-__device__ __forceinline__ double row_coupling(const Coef& c, int i) { return i < c.nx ? -z_coupling(c, i) : 0.0; }
-
-// chain owning workgroup `bid`, given each chain's first workgroup
-template <typename Info, typename F>
-__device__ __forceinline__ int find_chain(const Info* tab, int n, int bid, F first) {
-    int c = 0;
-    while (c + 1 < n && bid >= first(tab[c + 1])) ++c;
-    return c;
-}
-
-// the panel step a chain performs at global step t
-struct PanelStep {
-    int j, k0, kb, last;
-};
-__device__ __forceinline__ PanelStep panel_step(const ChainInfo& c, int t) {
-    PanelStep s;
-    s.j = t / c.npan;
-    const int p = t - s.j * c.npan;
-    s.k0 = p * KB;
-    s.kb = min(KB, c.np - s.k0);
-    s.last = (p == c.npan - 1) && (s.j + 1 < c.cf.nz);
-    return s;
-}
-
-// --------------------------------------------------------- block 0 init --
-template <typename T>
-__global__ __launch_bounds__(256) void k_init_block0(const ChainInfo* tab, int n) {
-    using C = typename CT<T>::c;
-    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
-    const ChainInfo& d = tab[ci];
-    int64_t e = (int64_t)(blockIdx.x - d.itile0) * 256 + threadIdx.x;
-    int64_t n2 = (int64_t)d.np * d.np;
-    if (e >= n2) return;
-    int r = (int)(e / d.np), q = (int)(e % d.np);
-    double2 v = block_entry(d.cf, 0, r, q);
-    ((C*)d.G)[e] = mk<C>(v.x, v.y);
-}
-
-// ------------------------------------------- diagonal-tile Gauss-Jordan --
-// In-place Gauss-Jordan inversion of a kb x kb tile (kb in {16, 32}) held
-// in registers by 256 threads: thread t owns row r = t/8 and columns
-// 4*(t%8) .. +3.  Partial pivoting over the not-yet-used rows of the tile,
-// without moving rows: the pivot of column p is taken in row rowOf[p], and
-// the inverse is recovered as T[i][c] = M[rowOf[i]][stepOf[c]].
-// Returns false (uniformly) if some pivot column was exactly zero.
-template <typename T>
-__device__ bool tile_gauss_jordan(typename CT<T>::c (&a)[4], int kb,
-                                  typename CT<T>::c* sRow, T* candv, int* candr,
-                                  int* rowOf, int* stepOf, int* zero_at) {
-    using C = typename CT<T>::c;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int r = t >> 3, cg = t & 7;
-    const bool act = (r < kb) && (4 * cg < kb);
-    bool used = false;
-    bool ok = true;
-    for (int p = 0; p < kb; ++p) {
-        const int pc = p >> 2, pe = p & 3;
-        C apk = a[0];
-#pragma unroll
-        for (int e = 1; e < 4; ++e) if (e == pe) apk = a[e];
-        T v = (act && cg == pc && !used) ? (T)(apk.x * apk.x + apk.y * apk.y) : (T)-1;
-        int vr = r;
-#pragma unroll
-        for (int off = 8; off < 64; off <<= 1) {
-            T ov = __shfl_xor(v, off);
-            int orr = __shfl_xor(vr, off);
-            if (ov > v || (ov == v && orr < vr)) { v = ov; vr = orr; }
-        }
-        if (lane == pc) { candv[w] = v; candr[w] = vr; }
-        __syncthreads();
-        T bv = candv[0];
-        int br = candr[0];
-        for (int q = 1; q < (kb >> 3); ++q) {
-            T cv = candv[q];
-            int cr = candr[q];
-            if (cv > bv || (cv == bv && cr < br)) { bv = cv; br = cr; }
-        }
-        const int rp = br;
-        const bool good = bv > (T)0;
-        if (!good) ok = false;
-        if (t == 0) { rowOf[p] = rp; stepOf[rp] = p; if (!good && *zero_at < 0) *zero_at = p; }
-        // value of column p in this thread's row, from the lane holding it
-        const int src = (lane & ~7) | pc;
-        C f;
-        f.x = __shfl(apk.x, src);
-        f.y = __shfl(apk.y, src);
-        if (act && r == rp) {
-            C dv = good ? cinv(f) : mk<C>(0.0, 0.0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int c = 4 * cg + e;
-                a[e] = (c == p) ? dv : cmul(a[e], dv);
-                sRow[c] = a[e];
-            }
-            used = true;
-        }
-        __syncthreads();
-        if (act && r != rp) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int c = 4 * cg + e;
-                C pr = sRow[c];
-                a[e] = (c == p) ? mk<C>(-(f.x * pr.x - f.y * pr.y), -(f.x * pr.y + f.y * pr.x))
-                                : csub(a[e], cmul(f, pr));
-            }
-        }
-    }
-    return ok;
-}
-
-// Panel step: T = (A_KK)^{-1}; W rows [32 rb, 32 rb + 32) and the matching
-// columns of Vt.  Every workgroup of a chain inverts the tile itself.
-template <typename T>
-__global__ __launch_bounds__(256) void k_panel(const ChainInfo* tab, int n, int tstep) {
-    using C = typename CT<T>::c;
-    __shared__ C sM[32][33];
-    __shared__ C sT[32][33];
-    __shared__ C sA[32][33];
-    __shared__ C sRow[32];
-    __shared__ T candv[4];
-    __shared__ int candr[4];
-    __shared__ int rowOf[32], stepOf[32];
-    __shared__ int zero_at;
-
-    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.ptile0; });
-    const ChainInfo& d = tab[ci];
-    if (tstep >= d.T) return;
-    const PanelStep ps = panel_step(d, tstep);
-    const int rb = blockIdx.x - d.ptile0;
-    const int np = d.np, kb = ps.kb, k0 = ps.k0;
-    const C* A = (const C*)d.G + (size_t)ps.j * np * np;
-    const int t = threadIdx.x;
-    const int r = t >> 3, cg = t & 7;
-    const bool act = (r < kb) && (4 * cg < kb);
-    if (t == 0) zero_at = -1;
-
-    C a[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        a[e] = act ? A[(size_t)(k0 + r) * np + k0 + 4 * cg + e] : mk<C>(0.0, 0.0);
-    // stage the rows of A whose multipliers this workgroup produces
-    const int r0 = rb * PR;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        int idx = t + 256 * e;
-        int rr = idx >> 5, tt = idx & 31;
-        C v = mk<C>(0.0, 0.0);
-        if (r0 + rr < np && tt < kb) v = A[(size_t)(r0 + rr) * np + k0 + tt];
-        sA[rr][tt] = v;
-    }
-    __syncthreads();
-
-    bool ok = tile_gauss_jordan<T>(a, kb, sRow, candv, candr, rowOf, stepOf, &zero_at);
-    if (act) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sM[r][4 * cg + e] = a[e];
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int c = 4 * cg + e;
-            sT[r][c] = sM[rowOf[r]][stepOf[c]];
-        }
-    }
-    __syncthreads();
-    if (!ok && rb == 0 && t == 0) {
-        if (atomicCAS(&d.status[0], 0, 1) == 0) {
-            d.status[1] = ps.j;
-            d.status[2] = k0 + zero_at;
-        }
-    }
-
-    // W = [-A_{:,K} T ; T - I] for rows r0 .. r0+31
-    {
-        const int row = r0 + r;
-        if (row < np && 4 * cg < kb) {
-            C* W = (C*)d.W;
-            const bool inK = row >= k0 && row < k0 + kb;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = 4 * cg + e;
-                C v;
-                if (inK) {
-                    v = sT[row - k0][c];
-                    if (row - k0 == c) v.x -= (T)1;
-                } else {
-                    T sr = 0, si = 0;
-                    for (int tt = 0; tt < kb; ++tt) {
-                        C x = sA[r][tt], y = sT[tt][c];
-                        sr += x.x * y.x - x.y * y.y;
-                        si += x.x * y.y + x.y * y.x;
-                    }
-                    v = mk<C>(-sr, -si);
-                }
-                W[(size_t)row * kb + c] = v;
-            }
-        }
-    }
-    // Vt[c][t] = A[k0 + t][c] for columns c in [r0, r0 + 32), identity on K
-    {
-        const int cc = t & 31, tg = t >> 5;
-        const int col = r0 + cc;
-        if (col < np && 4 * tg < kb) {
-            C* Vt = (C*)d.Vt;
-            const bool inK = col >= k0 && col < k0 + kb;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int tt = 4 * tg + e;
-                C v = inK ? mk<C>(tt == col - k0 ? 1.0 : 0.0, 0.0) : A[(size_t)(k0 + tt) * np + col];
-                Vt[(size_t)col * kb + tt] = v;
-            }
-        }
-    }
-}
-
-// Rank-kb update A <- A' + W V on 64 x 64 tiles; on the last panel of a
-// block also writes D_{j+1} = A_{j+1} - E G_j E into the next slot.
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(const ChainInfo* tab, int n, int tstep) {
-    using C = typename CT<T>::c;
-    using V = typename CT<T>::v4;
-    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
-    const ChainInfo& d = tab[ci];
-    if (tstep >= d.T) return;
-    const PanelStep ps = panel_step(d, tstep);
-    const int np = d.np, kb = ps.kb, k0 = ps.k0;
-    const int tiles_x = (np + TILE - 1) / TILE;
-    const int ti = blockIdx.x - d.utile0;
-    const int ty = ti / tiles_x, tx = ti % tiles_x;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const int wr = w >> 1, wc = w & 1;
-    C* A = (C*)d.G + (size_t)ps.j * np * np;
-    const C* W = (const C*)d.W;
-    const C* Vt = (const C*)d.Vt;
-
-    int R[2], Cc[2];
-    bool vr[2], vc[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        R[q] = ty * TILE + 32 * wr + 16 * q;
-        Cc[q] = tx * TILE + 32 * wc + 16 * q;
-        vr[q] = R[q] < np;
-        vc[q] = Cc[q] < np;
-    }
-    V accr[2][2], acci[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) { accr[bi][bj][e] = 0; acci[bi][bj][e] = 0; }
-            if (vr[bi] && vc[bj]) {
-                const int col = Cc[bj] + lr;
-                const bool inK = col >= k0 && col < k0 + kb;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = R[bi] + acc_row<T>(lg, e);
-                    C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : A[(size_t)row * np + col];
-                    accr[bi][bj][e] = v.x;
-                    acci[bi][bj][e] = v.y;
-                }
-            }
-        }
-
-    for (int kk = 0; kk < kb; kk += 16) {
-        C av[2][4], bv[2][4];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                av[q][s] = vr[q] ? W[(size_t)(R[q] + lr) * kb + kk + 4 * lg + s] : mk<C>(0.0, 0.0);
-                bv[q][s] = vc[q] ? Vt[(size_t)(Cc[q] + lr) * kb + kk + 4 * lg + s] : mk<C>(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    if (vr[bi] && vc[bj])
-                        cmfma<T, V>(accr[bi][bj], acci[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
-                                    bv[bj][s].y);
-    }
-
-    C* An = A + (size_t)np * np;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            if (!(vr[bi] && vc[bj])) continue;
-            const int col = Cc[bj] + lr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = R[bi] + acc_row<T>(lg, e);
-                C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
-                A[(size_t)row * np + col] = g;
-                if (ps.last) {
-                    double2 a1 = block_entry(d.cf, ps.j + 1, row, col);
-                    double s = row_coupling(d.cf, row) * row_coupling(d.cf, col);
-                    An[(size_t)row * np + col] = mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
-                }
-            }
-        }
-}
-
-// One block step of the forward (X_j = G_j (B_j - E X_{j-1})) or backward
-// (X_j -= G_j E X_{j+1}) sweep, for a 16 x 16 tile of (rows, right-hand
-// sides); the four waves split the contraction dimension and are summed in
-// a fixed order.
 template <typename T, bool FWD, bool CONJB>
 __global__ __launch_bounds__(256) void k_sweep(const SweepInfo* tab, int n, int tstep) {
     using C = typename CT<T>::c;
@@ -728,38 +338,6 @@ __global__ void k_sum_scalar(const double* part, int n, double* out) {
     }
 }
 
-// standalone tile inverses (the panel's building block, for tests)
-__global__ __launch_bounds__(256) void k_tile_inverse(int kb, const double2* A, double2* Tout, int* status) {
-    __shared__ double2 sM[32][33];
-    __shared__ double2 sRow[32];
-    __shared__ double candv[4];
-    __shared__ int candr[4];
-    __shared__ int rowOf[32], stepOf[32];
-    __shared__ int zero_at;
-    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
-    const bool act = (r < kb) && (4 * cg < kb);
-    const double2* Am = A + (size_t)blockIdx.x * kb * kb;
-    if (t == 0) zero_at = -1;
-    double2 a[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = act ? Am[r * kb + 4 * cg + e] : make_double2(0.0, 0.0);
-    __syncthreads();
-    bool ok = tile_gauss_jordan<double>(a, kb, sRow, candv, candr, rowOf, stepOf, &zero_at);
-    if (act) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sM[r][4 * cg + e] = a[e];
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int c = 4 * cg + e;
-            Tout[(size_t)blockIdx.x * kb * kb + r * kb + c] = sM[rowOf[r]][stepOf[c]];
-        }
-    }
-    if (t == 0 && !ok) status[blockIdx.x] = 1 + zero_at;
-}
-
 // one wavefront: D = A(16x4) B(4x16) with the operand layout the kernels assume
 __global__ void k_mfma_probe(int prec, const double* A, const double* B, double* D) {
     const int l = threadIdx.x;
@@ -779,18 +357,6 @@ __global__ void k_mfma_probe(int prec, const double* A, const double* B, double*
 // ---------------------------------------------------------------- launchers --
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-void launch_init_block0(const ChainInfo* tab, int n, int total, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_init_block0<float>, dim3(total), dim3(256), 0, st, tab, n);
-    else hipLaunchKernelGGL(k_init_block0<double>, dim3(total), dim3(256), 0, st, tab, n);
-}
-void launch_panel(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_panel<float>, dim3(total), dim3(256), 0, st, tab, n, t);
-    else hipLaunchKernelGGL(k_panel<double>, dim3(total), dim3(256), 0, st, tab, n, t);
-}
-void launch_update(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_update<float>, dim3(total), dim3(256), 0, st, tab, n, t);
-    else hipLaunchKernelGGL(k_update<double>, dim3(total), dim3(256), 0, st, tab, n, t);
-}
 void launch_sweep(const SweepInfo* tab, int n, int t, int total, bool fp32, bool forward, bool conj_b,
                   hipStream_t st) {
     if (fp32) {
@@ -874,9 +440,6 @@ void launch_sum_scalar(const double* part, int n, double* out, hipStream_t st) {
 void launch_zero(void* p, size_t bytes, hipStream_t st) {
     size_t n32 = (bytes + 3) / 4;
     if (n32) hipLaunchKernelGGL(k_zero, grid1((int64_t)n32), dim3(256), 0, st, (uint32_t*)p, n32);
-}
-void launch_tile_inverse(int count, int kb, const double* A, double* T, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, (const double2*)A, (double2*)T, status);
 }
 void launch_mfma_probe(int prec, const double* A, const double* B, double* D, hipStream_t st) {
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, prec, A, B, D);

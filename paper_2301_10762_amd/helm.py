@@ -109,6 +109,10 @@ def lib():
     L.helm_residual.argtypes = [G, _vp, f64, ctypes.c_int, _vp, _vp, _vp, i32, i64, _vp, _vp]
     L.helm_tile_inverse.argtypes = [i32, i32, _vp, _vp, _vp]
     L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
+    L.helm_kernel_timing.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.helm_kernel_timing.restype = None
+    L.helm_kernel_time.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.helm_kernel_time.restype = ctypes.c_int
     L.helm_counter.argtypes = [ctypes.c_int]
     L.helm_counter.restype = ctypes.c_int64
     L.helm_last_error.restype = ctypes.c_char_p
@@ -166,6 +170,22 @@ def _i32(seq):
 def counters() -> dict:
     L = lib()
     return {"launches": int(L.helm_counter(0)), "solves": int(L.helm_counter(1))}
+
+
+KERNEL_KINDS = {"update": 0, "panel": 1, "sweep": 2}
+
+
+def kernel_timing(enable: bool, stride: int = 1):
+    """Bracket every `stride`-th launch of the hot kernels with HIP events."""
+    lib().helm_kernel_timing(int(enable), int(stride))
+
+
+def kernel_time(kind: str):
+    """(total ms, timed launches) of a kernel kind since kernel_timing(True)."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().helm_kernel_time(KERNEL_KINDS[kind], ctypes.byref(ms), ctypes.byref(cnt)))
+    return float(ms.value), int(cnt.value)
 
 
 def factor_bytes(grid: Grid, precision="fp64") -> int:
