@@ -72,7 +72,9 @@ enum {
  * factor.  precision: HELM_FP64 (complex128 blocks) or HELM_FP32_IR
  * (complex64 blocks; solves are refined in FP64 to `tol`).  On success *out
  * owns ~nz*np^2*(16 or 8) bytes of HBM, np = nx rounded up to 16.
- * Returns HELM_ESINGULAR with no factor if a tile pivot is exactly zero.
+ * Diagonal tiles use diagonal pivots unless one falls below 1e-2 x max|tile|,
+ * in which case the factor is recomputed with partial pivoting inside the
+ * tiles.  Returns HELM_ESINGULAR with no factor if a pivot is exactly zero.
  * Synchronises `stream`.                                                   */
 int helm_factor(const helm_grid* grid, const double* m_dev, double omega, int precision,
                 void* stream, helm_factor_t* out);
@@ -150,10 +152,18 @@ int helm_residual(const helm_grid* grid, const double* m_dev, double omega, int 
                   const double* B_dev, const double* X_dev, double* r_dev, int32_t S, int64_t ld,
                   double* norms_dev, void* stream);
 
-/* Diagonal-tile Gauss-Jordan inverse (pivoting inside the tile) of `count`
- * kb x kb complex128 matrices (kb in {16, 32}, row-major, contiguous): the
- * building block of the block factorisation, exposed to test it alone.     */
-int helm_tile_inverse(int32_t count, int32_t kb, const double* A_dev, double* T_dev, void* stream);
+/* Diagonal-tile Gauss-Jordan inverse of `count` kb x kb complex128 matrices
+ * (kb in {16, 32}, row-major, contiguous): the building block of the block
+ * factorisation, exposed to test it alone.  pivot = 1: partial pivoting
+ * inside the tile; pivot = 0: diagonal pivots, HELM_ESINGULAR if one is
+ * below 1e-2 times the largest entry magnitude of the tile.                */
+int helm_tile_inverse(int32_t count, int32_t kb, int pivot, const double* A_dev, double* T_dev, void* stream);
+
+/* Diagonal tiles are inverted with diagonal pivots by default; a factor
+ * whose tile meets a pivot below 1e-2 x max|tile| is refactored with partial
+ * pivoting inside the tiles.  always != 0 selects partial pivoting from the
+ * start for every later factorisation (process-wide).                      */
+void helm_set_tile_pivoting(int always);
 
 /* Lane-layout check of the matrix-core instruction used by the kernels:
  * D = A(16x4) * B(4x16) in FP64 (prec 0) or FP32 (prec 1) on one wavefront. */

@@ -85,11 +85,14 @@ __device__ __forceinline__ double2 block_entry(const Coef& c, int j, int r, int 
 // coupling E_ii between rows j and j+1 (zero in the padding)
 __device__ __forceinline__ double row_coupling(const Coef& c, int i) { return i < c.nx ? -z_coupling(c, i) : 0.0; }
 
-// chain owning workgroup `bid`, given each chain's first workgroup
+// Chain owning work item `bid`, given each chain's first item.  Tables are
+// allocated with MAXB entries (unused ones start at INT_MAX), so the scan has
+// no data-dependent loads: all entries are fetched at once.
 template <typename Info, typename F>
 __device__ __forceinline__ int find_chain(const Info* tab, int n, int bid, F first) {
     int c = 0;
-    while (c + 1 < n && bid >= first(tab[c + 1])) ++c;
+#pragma unroll
+    for (int q = 1; q < MAXB; ++q) c = (bid >= first(tab[q])) ? q : c;
     return c;
 }
 

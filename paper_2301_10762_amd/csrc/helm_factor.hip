@@ -177,14 +177,133 @@ __device__ __forceinline__ int gj_invert(typename CT<T>::c (&a)[4], GJScratch<T>
     return zero;
 }
 
-// Invert the kb x kb tile in a[] and store its inverse transposed
-// (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer.
-// Returns the first zero-pivot step or -1.
+// Unpivoted Gauss-Jordan in uniform form on the 256-thread layout above
+// (thread: row r = t/8, columns 4(t%8)..+3).  Step p, with d = 1 / a_pp and
+// f = (column p) - e_p scaled to f' = f d: every entry outside column p takes
+// a_ij -= f'_i a_pj, and column p becomes e_p - f', which leaves the inverse
+// in place with no special case for the pivot row.  Row p is published with
+// its pivot entry zeroed, so the general update leaves column p untouched
+// and only the threads holding it overwrite it.  During step p the threads
+// holding column p+1 and row p+1 publish them (and one of them 1 / a_{p+1,p+1})
+// for the next step: one barrier and one LDS round trip per pivot.  The pivot
+// loop runs over column groups of four with the four steps of a group
+// unrolled, so element indices and buffer parities are compile-time and the
+// loop body is a few hundred instructions.  A pivot with
+// |a_pp|^2 < tau2 * max|tile|^2 is reported (return true).
 template <typename T>
-__device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, GJScratch<T>& sh,
-                                typename CT<T>::c (*M)[33], typename CT<T>::c* Tt) {
+struct RowScratch {
+    typename CT<T>::c row[2][32];
+    typename CT<T>::c col[2][32];
+    typename CT<T>::c dinv[2];
+    float amax[4];
+    int small;
+};
+
+// Step p = 4 pc + PE of gj_rows.
+template <typename T, int KBT, int PE>
+__device__ __forceinline__ void gj_rows_step(typename CT<T>::c (&a)[4], RowScratch<T>& sh, int pc, int r, int rr,
+                                             int cg, bool act, float thr, bool& small) {
+    using C = typename CT<T>::c;
+    constexpr int PAR = PE & 1, PE1 = (PE + 1) & 3;
+    const int p = 4 * pc + PE;
+    C rw[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rw[e] = sh.row[PAR][4 * cg + e];
+    const C d = sh.dinv[PAR];
+    C f = sh.col[PAR][rr];
+    if (r == p) f.x -= (T)1;
+    const C fs = cmul(f, d);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        a[e].x = fma(-fs.x, rw[e].x, fma(fs.y, rw[e].y, a[e].x));
+        a[e].y = fma(-fs.x, rw[e].y, fma(-fs.y, rw[e].x, a[e].y));
+    }
+    if (cg == pc) a[PE] = mk<C>((r == p ? (T)1 : (T)0) - fs.x, -fs.y);
+    const int p1 = p + 1, pc1 = p1 >> 2;
+    if (p1 < KBT && act) {
+        if (cg == pc1) sh.col[PAR ^ 1][r] = a[PE1];
+        if (r == p1) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                sh.row[PAR ^ 1][4 * cg + e] = (cg == pc1 && e == PE1) ? mk<C>(0.0, 0.0) : a[e];
+            if (cg == pc1) {
+                sh.dinv[PAR ^ 1] = crcp(a[PE1]);
+                if (!((float)(a[PE1].x * a[PE1].x + a[PE1].y * a[PE1].y) >= thr)) small = true;
+            }
+        }
+    }
+}
+
+template <typename T, int KBT>
+__device__ __forceinline__ bool gj_rows(typename CT<T>::c (&a)[4], RowScratch<T>& sh, float tau2) {
+    using C = typename CT<T>::c;
+    constexpr int NW = KBT / 8;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < KBT) && (4 * cg < KBT);
+    const int rr = r < KBT ? r : 0;
+    {
+        float m2 = 0.0f;
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, (float)(a[e].x * a[e].x + a[e].y * a[e].y));
+        }
+        const uint32_t wm = wave_max_u32(__float_as_uint(m2));
+        if (l == 0) sh.amax[w] = (w < NW) ? __uint_as_float(wm) : 0.0f;
+        if (t == 0) sh.small = 0;
+        // step 0's operands
+        if (act && r == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sh.row[0][4 * cg + e] = (cg == 0 && e == 0) ? mk<C>(0.0, 0.0) : a[e];
+            if (cg == 0) sh.dinv[0] = crcp(a[0]);
+        }
+        if (act && cg == 0) sh.col[0][r] = a[0];
+    }
+    __syncthreads();
+    float thr = sh.amax[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) thr = fmaxf(thr, sh.amax[q]);
+    thr *= tau2;
+    bool small = act && r == 0 && cg == 0 && !((float)(a[0].x * a[0].x + a[0].y * a[0].y) >= thr);
+#pragma unroll 1
+    for (int pc = 0; pc < KBT / 4; ++pc) {
+        if (pc > 0) __syncthreads();
+        gj_rows_step<T, KBT, 0>(a, sh, pc, r, rr, cg, act, thr, small);
+        __syncthreads();
+        gj_rows_step<T, KBT, 1>(a, sh, pc, r, rr, cg, act, thr, small);
+        __syncthreads();
+        gj_rows_step<T, KBT, 2>(a, sh, pc, r, rr, cg, act, thr, small);
+        __syncthreads();
+        gj_rows_step<T, KBT, 3>(a, sh, pc, r, rr, cg, act, thr, small);
+    }
+    if (small) sh.small = 1;
+    __syncthreads();
+    return sh.small != 0;
+}
+
+// Pivot tolerance of the unpivoted path: |a_pp|^2 >= TAU2 * max|a|^2.
+constexpr float TAU2 = 1e-4f;
+
+// Invert the kb x kb tile in a[] and store its inverse transposed
+// (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
+// (pivoted path).  Returns the first zero-pivot step (pivoted path) or -1;
+// *small is set when the unpivoted path met a pivot below the tolerance.
+template <typename T>
+__device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, int pivot, GJScratch<T>& sh,
+                                                typename CT<T>::c (*M)[33], typename CT<T>::c* Tt, bool* small) {
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
     const bool act = (r < kb) && (4 * cg < kb);
+    if (!pivot) {
+        // diagonal pivots
+        RowScratch<T>& rs = *(RowScratch<T>*)&sh;
+        *small = (kb == 32) ? gj_rows<T, 32>(a, rs, TAU2) : gj_rows<T, 16>(a, rs, TAU2);
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Tt[(4 * cg + e) * KB + r] = a[e];
+        }
+        return -1;
+    }
+    *small = false;
     int zero = (kb == 32) ? gj_invert<T, 32>(a, sh) : gj_invert<T, 16>(a, sh);
     if (act) {
 #pragma unroll
@@ -252,8 +371,10 @@ __global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n
         const double2 v = (r < kb && c < kb) ? block_entry(d.cf, 0, r, c) : make_double2(0.0, 0.0);
         a[e] = mk<C>(v.x, v.y);
     }
-    const int zero = invert_and_store<T>(a, kb, sh, M, (C*)d.Tb);
+    bool small;
+    const int zero = invert_and_store<T>(a, kb, d.pivot, sh, M, (C*)d.Tb, &small);
     if (zero >= 0 && t == 0) report_zero_pivot(d.status, 0, zero);
+    if (small && t == 0) d.status[3] = 1;
 }
 
 // workgroup that prepares the next step's inverted diagonal tile
@@ -342,8 +463,10 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
         }
     }
     __syncthreads();   // sXa is reused as the inversion buffer
-    const int zero = invert_and_store<T>(a, kbn, sh, sXa, Tnext);
+    bool small;
+    const int zero = invert_and_store<T>(a, kbn, d.pivot, sh, sXa, Tnext, &small);
     if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
+    if (small && t == 0) d.status[3] = 1;
 }
 
 // update of one 64 x 64 tile of Y
@@ -499,7 +622,7 @@ __global__ __launch_bounds__(256) void k_factor_step(const ChainInfo* tab, int n
 }
 
 // standalone tile inverses (the building block above, for tests)
-__global__ __launch_bounds__(256) void k_tile_inverse(int kb, const double2* A, double2* Tout, int* status) {
+__global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const double2* A, double2* Tout, int* status) {
     __shared__ double2 M[32][33];
     __shared__ GJScratch<double> sh;
     __shared__ double2 Tt[KB * KB];
@@ -511,13 +634,15 @@ __global__ __launch_bounds__(256) void k_tile_inverse(int kb, const double2* A, 
         const int c = 4 * cg + e;
         a[e] = (r < kb && c < kb) ? Am[r * kb + c] : make_double2(0.0, 0.0);
     }
-    const int zero = invert_and_store<double>(a, kb, sh, M, Tt);
+    bool small;
+    const int zero = invert_and_store<double>(a, kb, pivot, sh, M, Tt, &small);
     __syncthreads();
     for (int i = t; i < kb * kb; i += 256) {
         const int rr = i / kb, c = i % kb;
         Tout[(size_t)blockIdx.x * kb * kb + i] = Tt[c * KB + rr];
     }
     if (t == 0 && zero >= 0) status[blockIdx.x] = 1 + zero;
+    if (t == 0 && small) status[blockIdx.x] = -1;
 }
 
 void launch_factor_init(const ChainInfo* tab, int n, int total, bool fp32, hipStream_t st) {
@@ -528,8 +653,9 @@ void launch_factor_step(const ChainInfo* tab, int n, int t, int total, bool fp32
     if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t);
     else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t);
 }
-void launch_tile_inverse(int count, int kb, const double* A, double* T, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, (const double2*)A, (double2*)T, status);
+void launch_tile_inverse(int count, int kb, int pivot, const double* A, double* T, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, pivot, (const double2*)A, (double2*)T,
+                       status);
 }
 
 }  // namespace helm

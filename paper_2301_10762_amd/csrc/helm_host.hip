@@ -7,6 +7,7 @@
 #include <atomic>
 #include <mutex>
 #include <cmath>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -161,6 +162,7 @@ struct KernelTimer {
     }
 };
 KernelTimer g_timer;
+int g_force_pivot = 0;   // 1: always invert diagonal tiles with partial pivoting
 
 Coef coef_of(const helm_factor_s* f) {
     Coef c;
@@ -191,12 +193,17 @@ int check_model(const double* m, int64_t n, hipStream_t st) {
 
 // ------------------------------------------------------------ factorisation --
 // Factor a group of at most MAXB chains of one precision in lockstep: one
-// initial launch, then one launch per panel step.
-int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
+// initial launch, then one launch per panel step.  With pivot == 0 the
+// diagonal tiles are inverted with diagonal pivots; *needs_pivot reports a
+// chain that met a pivot below the tolerance (the caller refactors it).
+int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, bool* needs_pivot) {
+    *needs_pivot = false;
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
     const size_t es = elem_bytes(fs[0]->prec);
     Scratch sc(st);
-    std::vector<ChainInfo> tab(n);
+    std::vector<ChainInfo> tab(MAXB);
+    std::memset(tab.data(), 0, sizeof(ChainInfo) * MAXB);
+    for (int c = n; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
     int utot = 0, itot = 0, Tmax = 0;
     size_t buf = 0;
     for (int c = 0; c < n; ++c) buf += (2 * (size_t)fs[c]->np * fs[c]->np + 2 * (size_t)KB * KB) * es + 256;
@@ -225,6 +232,7 @@ int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
         ci.np = f->np;
         ci.npan = (f->np + KB - 1) / KB;
         ci.T = ci.npan * f->g.nz;
+        ci.pivot = pivot;
         ci.utile0 = utot;
         utot += factor_step_blocks(f->np);
         ci.itile0 = itot;
@@ -232,8 +240,8 @@ int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
         Tmax = std::max(Tmax, ci.T);
     }
     ChainInfo* dtab;
-    if ((rc = sc.get(&dtab, sizeof(ChainInfo) * n))) return rc;
-    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(ChainInfo) * n, st))) return rc;
+    if ((rc = sc.get(&dtab, sizeof(ChainInfo) * MAXB))) return rc;
+    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(ChainInfo) * MAXB, st))) return rc;
     {
         KernelTimer::Pair pi;
         const bool ti = g_timer.begin(1, st, &pi);
@@ -255,6 +263,8 @@ int factor_group(helm_factor_s* const* fs, int n, hipStream_t st) {
         if (hs[4 * c])
             return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: chain " + std::to_string(c) + ", block " +
                                             std::to_string(hs[4 * c + 1]) + ", row " + std::to_string(hs[4 * c + 2]));
+    for (int c = 0; c < n; ++c)
+        if (hs[4 * c + 3]) *needs_pivot = true;
     return HELM_OK;
 }
 
@@ -306,7 +316,10 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
         }
     }
     for (int c0 = 0; c0 < count; c0 += MAXB) {
-        int rc = factor_group(fs.data() + c0, std::min(MAXB, count - c0), st);
+        const int k = std::min(MAXB, count - c0);
+        bool needs = false;
+        int rc = factor_group(fs.data() + c0, k, g_force_pivot, st, &needs);
+        if (rc == HELM_OK && needs) rc = factor_group(fs.data() + c0, k, 1, st, &needs);
         if (rc) {
             cleanup();
             return rc;
@@ -324,15 +337,29 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
 int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const int64_t* ldy, void* const* Xs,
                 const int64_t* ldx, const int* Ss, bool conj_b, hipStream_t st) {
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
+    const size_t es = elem_bytes(fs[0]->prec);
     Scratch sc(st);
-    std::vector<SweepInfo> tab(n);
-    int tot = 0, steps = 0;
+    std::vector<SweepInfo> tab(MAXB);
+    std::memset(tab.data(), 0, sizeof(SweepInfo) * MAXB);
+    for (int c = n; c < MAXB; ++c) tab[c].tile0 = tab[c].itile0 = INT32_MAX;
+    int groups = 0, st_max = 0, itot = 0, steps = 0;
+    size_t buf = 0;
+    for (int c = 0; c < n; ++c) buf += 2 * ((size_t)fs[c]->np * Ss[c] * es + 256);
+    char* arena;
+    int rc = sc.get(&arena, buf);
+    if (rc) return rc;
+    size_t off = 0;
     for (int c = 0; c < n; ++c) {
         const helm_factor_s* f = fs[c];
         SweepInfo& si = tab[c];
+        const size_t yb = (size_t)f->np * Ss[c] * es;
         si.G = f->G;
         si.B = Ys[c];
         si.X = Xs[c];
+        si.Y0 = arena + off;
+        off = (off + yb + 255) / 256 * 256;
+        si.Y1 = arena + off;
+        off = (off + yb + 255) / 256 * 256;
         si.ldb = ldy[c];
         si.ldx = ldx[c];
         si.S = Ss[c];
@@ -340,29 +367,32 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
         si.nz = f->g.nz;
         si.np = f->np;
         si.cz = f->g.hx / f->g.hz;
-        si.tiles_s = (Ss[c] + 15) / 16;
-        si.tile0 = tot;
-        tot += (f->np / 16) * si.tiles_s;
+        si.tiles_s = sweep_col_tiles(Ss[c]);
+        si.tile0 = groups;
+        groups += sweep_row_tiles(f->np);
+        st_max = std::max(st_max, si.tiles_s);
+        si.itile0 = itot;
+        itot += (int)(((int64_t)f->np * Ss[c] + 255) / 256);
         steps = std::max(steps, f->g.nz);
         g_solves += Ss[c];
     }
     SweepInfo* dtab;
-    int rc = sc.get(&dtab, sizeof(SweepInfo) * n);
-    if (rc) return rc;
-    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * n, st))) return rc;
+    if ((rc = sc.get(&dtab, sizeof(SweepInfo) * MAXB))) return rc;
+    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * MAXB, st))) return rc;
+    launch_sweep_init(dtab, n, itot, fp32, conj_b, st);
     for (int t = 0; t < steps; ++t) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        launch_sweep(dtab, n, t, tot, fp32, true, conj_b, st);
+        launch_sweep(dtab, n, t, groups, st_max, fp32, true, conj_b, st);
         if (tm) g_timer.end(p, st);
     }
     for (int t = 0; t + 1 < steps; ++t) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        launch_sweep(dtab, n, t, tot, fp32, false, false, st);
+        launch_sweep(dtab, n, t, groups, st_max, fp32, false, false, st);
         if (tm) g_timer.end(p, st);
     }
-    g_launches += 2 * (int64_t)steps - 1;
+    g_launches += 2 * (int64_t)steps;
     HIPCHECK(hipGetLastError());
     return HELM_OK;
 }
@@ -590,6 +620,8 @@ extern "C" {
 const char* helm_last_error(void) { return g_err.c_str(); }
 
 int64_t helm_counter(int which) { return which == 0 ? g_launches.load() : g_solves.load(); }
+
+void helm_set_tile_pivoting(int always) { g_force_pivot = always ? 1 : 0; }
 
 void helm_kernel_timing(int enable, int stride) {
     g_timer.drain();
@@ -866,7 +898,7 @@ int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega, con
     return HELM_OK;
 }
 
-int helm_tile_inverse(int32_t count, int32_t kb, const double* A_dev, double* T_dev, void* stream) {
+int helm_tile_inverse(int32_t count, int32_t kb, int pivot, const double* A_dev, double* T_dev, void* stream) {
     if (count <= 0 || (kb != 16 && kb != 32) || !A_dev || !T_dev) return fail(HELM_EINVAL, "bad tile arguments");
     hipStream_t st = S_(stream);
     Scratch sc(st);
@@ -874,13 +906,15 @@ int helm_tile_inverse(int32_t count, int32_t kb, const double* A_dev, double* T_
     int rc = sc.get(&status, sizeof(int) * count);
     if (rc) return rc;
     launch_zero(status, sizeof(int) * count, st);
-    launch_tile_inverse(count, kb, A_dev, T_dev, status, st);
+    launch_tile_inverse(count, kb, pivot ? 1 : 0, A_dev, T_dev, status, st);
     g_launches += 2;
     std::vector<int> h(count);
     HIPCHECK(hipMemcpyAsync(h.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    for (int c = 0; c < count; ++c)
-        if (h[c]) return fail(HELM_ESINGULAR, "zero pivot in tile " + std::to_string(c));
+    for (int c = 0; c < count; ++c) {
+        if (h[c] > 0) return fail(HELM_ESINGULAR, "zero pivot in tile " + std::to_string(c));
+        if (h[c] < 0) return fail(HELM_ESINGULAR, "pivot below tolerance in tile " + std::to_string(c));
+    }
     return HELM_OK;
 }
 

@@ -26,33 +26,44 @@ struct ChainInfo {
     void* P1;
     void* Tb;       // two KB x KB slots holding the inverted diagonal tile,
                     // transposed (Tt[c][k] = T[k][c]); step t reads slot t&1
-    int* status;    // [0] failure flag, [1] block, [2] row
+    int* status;    // [0] zero-pivot flag, [1] block, [2] row, [3] small-pivot flag
     Coef cf;
     int np, npan, T;        // padded size, panels per block, steps (nz * npan)
+    int pivot;              // 0: diagonal pivots (flagged if small), 1: partial pivoting in tiles
     int utile0;             // first workgroup of this chain in a step launch
     int itile0;             // first workgroup in the initial launch
 };
 
-// One chain of a batched block sweep.
+// One chain of a batched block sweep.  The coupling vectors y_j = b_j -
+// E w_{j-1} (forward) and z_j = E x_{j+1} (backward) are produced by the
+// workgroups that compute the rows they depend on and kept in two ping-pong
+// buffers of np x S (column-major, leading dimension np, zero below nx).
 struct SweepInfo {
     const void* G;  // factor blocks
-    const void* B;  // right-hand sides (forward sweep), column-major
-    void* X;        // solution being built, column-major
+    const void* B;  // right-hand sides, column-major (ldb)
+    void* X;        // solution being built, column-major (ldx)
+    void* Y0;       // coupling vectors, ping-pong
+    void* Y1;
     int64_t ldb, ldx;
     int S, nx, nz, np;
     double cz;      // hx / hz: the z-edge coupling is -cz (halved at i = 0, nx-1)
-    int tile0, tiles_s;
+    int tile0, tiles_s;     // first row tile (of 16 rows) of this chain, its column tiles
+    int itile0;             // first workgroup of the initial launch
 };
 
-// kernel launchers (helm_kernels.hip); `fp32` selects the complex64 variants
 // workgroups per chain of the factorisation launches
 int factor_init_blocks(int np);
 int factor_step_blocks(int np);
 void launch_factor_init(const ChainInfo* tab, int n, int total_blocks, bool fp32, hipStream_t st);
 void launch_factor_step(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
-// forward: step t is block j = t; backward: step t is block j = nz - 2 - t
-void launch_sweep(const SweepInfo* tab, int n, int t, int total_blocks, bool fp32, bool forward,
-                  bool conj_b, hipStream_t st);
+// y_0 = b_0 (conjugated for adjoint solves) into Y0 of every chain
+void launch_sweep_init(const SweepInfo* tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
+// forward: step t is block j = t; backward: step t is block j = nz - 2 - t.
+// `groups` row tiles (16 rows) over all chains, `st` column tiles (16 columns).
+void launch_sweep(const SweepInfo* tab, int n, int t, int groups, int st, bool fp32, bool forward,
+                  bool conj_b, hipStream_t st_);
+int sweep_row_tiles(int np);
+int sweep_col_tiles(int S);
 void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st);
 void launch_residual(const Coef& cf, int adjoint, const double* B, int64_t ldb, const double* X,
                      int64_t ldx, double* R, int64_t ldr, float* R32, int S, double* partial,
@@ -82,7 +93,7 @@ void launch_gamma(const double* m, int nx, int nz, double alpha, double mu, doub
                   int nblk, hipStream_t st);
 void launch_sum_scalar(const double* part, int n, double* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
-void launch_tile_inverse(int count, int kb, const double* A, double* T, int* status, hipStream_t st);
+void launch_tile_inverse(int count, int kb, int pivot, const double* A, double* T, int* status, hipStream_t st);
 void launch_mfma_probe(int prec, const double* A, const double* B, double* D, hipStream_t st);
 
 }  // namespace helm

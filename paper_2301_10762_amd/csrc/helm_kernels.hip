@@ -28,79 +28,6 @@
 #include "helm_device.h"
 
 namespace helm {
-template <typename T, bool FWD, bool CONJB>
-__global__ __launch_bounds__(256) void k_sweep(const SweepInfo* tab, int n, int tstep) {
-    using C = typename CT<T>::c;
-    using V = typename CT<T>::v4;
-    __shared__ T red[4][2][4][64];
-    const int ci = find_chain(tab, n, blockIdx.x, [](const SweepInfo& c) { return c.tile0; });
-    const SweepInfo& d = tab[ci];
-    const int j = FWD ? tstep : d.nz - 2 - tstep;
-    if (j < 0 || j >= d.nz) return;
-    const int ti = blockIdx.x - d.tile0;
-    const int i0 = 16 * (ti / d.tiles_s), s0 = 16 * (ti % d.tiles_s);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const int np = d.np, nx = d.nx;
-    const C* G = (const C*)d.G + (size_t)j * np * np;
-    const C* Bm = (const C*)d.B;
-    C* X = (C*)d.X;
-    const int s = s0 + lr;
-    const bool scol = s < d.S;
-    const C* Xprev = FWD ? X + (size_t)s * d.ldx + (size_t)(j - 1) * nx : X + (size_t)s * d.ldx + (size_t)(j + 1) * nx;
-    const C* Bcol = FWD ? Bm + (size_t)s * d.ldb + (size_t)j * nx : nullptr;
-
-    V cr, cim;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) { cr[e] = 0; cim[e] = 0; }
-    const int nch = np / 16;
-    for (int ch = w; ch < nch; ch += 4) {
-        const int kb0 = 16 * ch + 4 * lg;
-        C av[4], bv[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) av[q] = G[(size_t)(i0 + lr) * np + kb0 + q];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = kb0 + q;
-            C y = mk<C>(0.0, 0.0);
-            if (scol && k < nx) {
-                const T e = (T)(k == 0 || k == nx - 1 ? -0.5 * d.cz : -d.cz);
-                if (FWD) {
-                    y = Bcol[k];
-                    if (CONJB) y.y = -y.y;
-                    if (j > 0) { C xp = Xprev[k]; y.x -= e * xp.x; y.y -= e * xp.y; }
-                } else {
-                    C xp = Xprev[k];
-                    y = mk<C>(e * xp.x, e * xp.y);
-                }
-            }
-            bv[q] = y;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cmfma<T, V>(cr, cim, av[q].x, av[q].y, bv[q].x, bv[q].y);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) { red[w][0][e][l] = cr[e]; red[w][1][e][l] = cim[e]; }
-    __syncthreads();
-    if (w == 0 && scol) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = i0 + acc_row<T>(lg, e);
-            if (i >= nx) continue;
-            T sr = red[0][0][e][l], si = red[0][1][e][l];
-#pragma unroll
-            for (int q = 1; q < 4; ++q) { sr += red[q][0][e][l]; si += red[q][1][e][l]; }
-            C* out = X + (size_t)s * d.ldx + (size_t)j * nx + i;
-            if (FWD) {
-                *out = mk<C>(sr, si);
-            } else {
-                C o = *out;
-                *out = mk<C>(o.x - sr, o.y - si);
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------ elementwise / FP64 --
 __global__ void k_check_model(const double* m, int64_t n, int* flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -357,20 +284,6 @@ __global__ void k_mfma_probe(int prec, const double* A, const double* B, double*
 // ---------------------------------------------------------------- launchers --
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-void launch_sweep(const SweepInfo* tab, int n, int t, int total, bool fp32, bool forward, bool conj_b,
-                  hipStream_t st) {
-    if (fp32) {
-        if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), dim3(total), dim3(256), 0, st, tab, n, t);
-            else hipLaunchKernelGGL((k_sweep<float, true, false>), dim3(total), dim3(256), 0, st, tab, n, t);
-        } else hipLaunchKernelGGL((k_sweep<float, false, false>), dim3(total), dim3(256), 0, st, tab, n, t);
-    } else {
-        if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), dim3(total), dim3(256), 0, st, tab, n, t);
-            else hipLaunchKernelGGL((k_sweep<double, true, false>), dim3(total), dim3(256), 0, st, tab, n, t);
-        } else hipLaunchKernelGGL((k_sweep<double, false, false>), dim3(total), dim3(256), 0, st, tab, n, t);
-    }
-}
 void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_check_model, grid1(n), dim3(256), 0, st, m, n, flag);
 }

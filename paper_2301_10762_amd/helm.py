@@ -107,7 +107,9 @@ def lib():
     L.helm_gn_hvp.argtypes = [G, _vp, i32, ctypes.POINTER(f64), i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
                               i32, _vp, f64, f64, ctypes.c_int, f64, _vp, _vp, I]
     L.helm_residual.argtypes = [G, _vp, f64, ctypes.c_int, _vp, _vp, _vp, i32, i64, _vp, _vp]
-    L.helm_tile_inverse.argtypes = [i32, i32, _vp, _vp, _vp]
+    L.helm_tile_inverse.argtypes = [i32, i32, ctypes.c_int, _vp, _vp, _vp]
+    L.helm_set_tile_pivoting.argtypes = [ctypes.c_int]
+    L.helm_set_tile_pivoting.restype = None
     L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
     L.helm_kernel_timing.argtypes = [ctypes.c_int, ctypes.c_int]
     L.helm_kernel_timing.restype = None
@@ -349,14 +351,19 @@ def residual(grid: Grid, m, omega: float, B, X, adjoint: bool = False, stream=No
     return r, norms
 
 
-def tile_inverse(A):
-    """Inverse of each kb x kb complex128 tile (kb = 16 or 32) by the panel's Gauss-Jordan."""
+def tile_inverse(A, pivot: bool = True):
+    """Inverse of each kb x kb complex128 tile (kb = 16 or 32) by the factorisation's Gauss-Jordan."""
     torch = _torch()
     A = _dev_c128(A)
     count, kb = A.shape[0], A.shape[1]
     T = torch.empty_like(A)
-    _check(lib().helm_tile_inverse(count, kb, _ptr(A), _ptr(T), _stream()))
+    _check(lib().helm_tile_inverse(count, kb, int(pivot), _ptr(A), _ptr(T), _stream()))
     return T
+
+
+def set_tile_pivoting(always: bool):
+    """Always invert diagonal tiles with partial pivoting (process-wide)."""
+    lib().helm_set_tile_pivoting(int(always))
 
 
 def mfma_probe(prec: int, A, B):

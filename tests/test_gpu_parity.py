@@ -53,10 +53,42 @@ def test_tile_inverse_pivots_inside_tile(helm, kb):
     A = rng.standard_normal((6, kb, kb)) + 1j * rng.standard_normal((6, kb, kb))
     A[:, 0, 0] = 1e-12          # forces a row exchange at the first step
     A[1, :, 3] *= 1e-6          # badly scaled column
-    T = helm.tile_inverse(A).cpu().numpy()
+    T = helm.tile_inverse(A, pivot=True).cpu().numpy()
     for c in range(A.shape[0]):
         ref = np.linalg.inv(A[c])
         assert rel(T[c], ref) < 1e-10, c
+
+
+@pytest.mark.parametrize("kb", [16, 32])
+def test_tile_inverse_diagonal_pivots(helm, kb):
+    """The fast path: diagonal pivots, flagged when one is below tolerance."""
+    rng = np.random.default_rng(100 + kb)
+    A = rng.standard_normal((4, kb, kb)) + 1j * rng.standard_normal((4, kb, kb))
+    A += 4.0 * np.eye(kb)[None]
+    T = helm.tile_inverse(A, pivot=False).cpu().numpy()
+    for c in range(A.shape[0]):
+        assert rel(T[c], np.linalg.inv(A[c])) < 1e-12, c
+    A[2, 0, 0] = 1e-3        # first pivot far below 1e-2 * max|tile|
+    with pytest.raises(helm.HelmError) as e:
+        helm.tile_inverse(A, pivot=False)
+    assert e.value.code == helm.ESINGULAR
+    T = helm.tile_inverse(A, pivot=True).cpu().numpy()
+    assert rel(T[2], np.linalg.inv(A[2])) < 1e-10
+
+
+def test_forced_tile_pivoting_matches(helm):
+    """Factors built with partial pivoting in every tile solve to the same answer."""
+    g, m, omega = _case(40, 23, 0.025, 0.025, seed=3)
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((5, g.N)) + 1j * rng.standard_normal((5, g.N))
+    Xo = oracle.Factor(g, m, omega).solve(B)
+    G = helm.Grid(g.nx, g.nz, g.hx, g.hz)
+    helm.set_tile_pivoting(True)
+    try:
+        X, info = helm.factor(G, m, omega).solve(B, tol=1e-10)
+    finally:
+        helm.set_tile_pivoting(False)
+    assert rel(X.cpu().numpy(), Xo) < 1e-10 and info.max_relres <= 1e-10
 
 
 def test_tile_inverse_reports_singular(helm):
@@ -65,7 +97,7 @@ def test_tile_inverse_reports_singular(helm):
     A[1] = np.eye(16)
     A[1, 5, 5] = 0.0
     with pytest.raises(helm.HelmError) as e:
-        helm.tile_inverse(A)
+        helm.tile_inverse(A, pivot=True)
     assert e.value.code == helm.ESINGULAR
 
 
