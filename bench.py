@@ -28,8 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Helmholtz RHS solves/s at 401^2 (rel. residual<=1e-10) vs FP64 plain; p50/p99 ms"
 TOL = 1e-10
 PEAK = {"fp64": 78.6, "fp32_ir": 157.3}           # dense matrix-core TFLOP/s (MI355X)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_update_c3_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2301_10762_amd", "csrc", "helm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_step_c3_traffic.txt")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2301_10762_amd", "csrc", f)
+               for f in ("helm_factor.hip", "helm_device.h", "helm_internal.h")]
 
 
 def parse():
@@ -39,7 +40,6 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     p.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 comparison (0 = skip)")
-    p.add_argument("--timing-stride", type=int, default=16, help="HIP-event sample stride of the hot kernels")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
@@ -56,8 +56,32 @@ def percentile(xs, q):
 
 
 def src_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """Digest of the sources the factorisation-step kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def read_traffic(prec):
+    """HBM bytes per k_factor_step launch from the committed counter summary
+    (lines "key: value"), or None when it is missing, was taken for another
+    precision, or the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#", "|", "`")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != src_sha() or kv.get("precision") != prec:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -109,7 +133,7 @@ def main():
             step(precision)
         torch.cuda.synchronize()
         if timing:
-            helm.kernel_timing(True, args.timing_stride)
+            helm.kernel_timing(True)
         lat, infos = [], None
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -121,7 +145,7 @@ def main():
         total = time.perf_counter() - t0
         kt = {}
         if timing:
-            for kind in ("update", "panel", "sweep"):
+            for kind in ("factor_step", "factor_init", "sweep"):
                 kt[kind] = helm.kernel_time(kind)
             helm.kernel_timing(False)
         return total, lat, infos, kt
@@ -132,28 +156,23 @@ def main():
     value = solves / total
     ms_per_step = total / args.steps * 1e3
 
-    # roofline of the dominant kernel: the matrix-core rank-32 block update.
-    # Algorithmic work: the block factorisation's canonical count
-    # 8 * (4/3) * n_z * n_x^3 flops per frequency, spread evenly over its
-    # n_z * ceil(np/32) update launches; one launch serves all five chains.
+    # roofline of the dominant kernel, k_factor_step (one Gauss-Jordan panel
+    # step of every chain: rank-32 block update on the matrix cores plus the
+    # next diagonal tile).  Algorithmic work: the block factorisation's
+    # canonical count 8 * (4/3) * n_z * n_x^3 flops per frequency, spread
+    # evenly over its n_z * ceil(np/32) step launches; one launch serves all
+    # five frequencies.
     nx, nz = w.nx, w.nz
     np_ = (nx + 15) // 16 * 16
     npan = (np_ + 31) // 32
     flops_per_launch = n_omega * 8.0 * (4.0 / 3.0) * nx ** 3 / npan
-    upd_ms, upd_n = kt.get("update", (0.0, 0))
+    upd_ms, upd_n = kt.get("factor_step", (0.0, 0))
     avg_upd_s = upd_ms / upd_n * 1e-3 if upd_n else float("nan")
     achieved = flops_per_launch / avg_upd_s / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tf = json.load(open(TRAFFIC_FILE))
-            if tf.get("kernel_source_sha256") == src_sha() and tf.get("precision") == prec:
-                traffic = tf.get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = read_traffic(prec)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
-                "kernel": "k_update (rank-32 block Gauss-Jordan update, 5 chains per launch)",
+                "kernel": "k_factor_step (Gauss-Jordan panel step, 5 chains per launch)",
                 "avg_launch_us": round(avg_upd_s * 1e6, 2), "timed_launches": upd_n,
                 "flops_per_launch": flops_per_launch}
     kernels = {}

@@ -169,13 +169,15 @@ void helm_set_tile_pivoting(int always);
  * D = A(16x4) * B(4x16) in FP64 (prec 0) or FP32 (prec 1) on one wavefront. */
 int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* D_dev, void* stream);
 
-/* Live timing of the hot kernels with HIP events.  helm_kernel_timing(1, k)
- * brackets every k-th launch of each kind with two events on its stream (and
- * resets the totals); helm_kernel_time reports, per kind, the summed elapsed
- * milliseconds and the number of timed launches (waits for them).  Kind 0
- * is the factorisation step (block update + next diagonal tile), kind 1 the
- * initial assembly launch, kind 2 a sweep step.                           */
-void helm_kernel_timing(int enable, int stride);
+/* Live timing of the hot kernels with HIP events.  helm_kernel_timing(1)
+ * resets the totals and brackets every run of back-to-back launches of one
+ * kind (all panel steps of a factorisation group; one forward or backward
+ * sweep) with two events on its stream; helm_kernel_time reports, per kind,
+ * the summed elapsed milliseconds and the number of launches inside the
+ * timed runs (it waits for them), so total / count is the average launch
+ * duration.  Kind 0 is the factorisation step (block update + next diagonal
+ * tile), kind 1 the initial assembly launch, kind 2 a sweep step.          */
+void helm_kernel_timing(int enable);
 int helm_kernel_time(int kind, double* total_ms, int64_t* count);
 
 /* Number of kernel launches and right-hand-side solves issued since load. */

@@ -116,14 +116,17 @@ struct PinnedRing {
 };
 PinnedRing g_ring;
 
-// Optional live timing of the dominant kernels with HIP events: every
-// `stride`-th launch of a kind is bracketed by two events on its stream.
+// Optional live timing of the dominant kernels with HIP events: each run of
+// back-to-back launches of one kind on a stream (the panel steps of a
+// factorisation group, the steps of one forward or one backward sweep) is
+// bracketed by two events on that stream; the elapsed time is booked with
+// the number of launches in the run.
 struct KernelTimer {
     std::mutex mu;
-    int enabled = 0, stride = 1;
-    int64_t seen[3] = {0, 0, 0};
+    int enabled = 0;
     struct Pair {
         int kind;
+        int64_t launches;
         hipEvent_t a, b;
     };
     std::vector<Pair> pending;
@@ -131,8 +134,6 @@ struct KernelTimer {
     int64_t count[3] = {0, 0, 0};
     bool begin(int kind, hipStream_t st, Pair* p) {
         if (!enabled) return false;
-        std::lock_guard<std::mutex> lk(mu);
-        if ((seen[kind]++ % stride) != 0) return false;
         p->kind = kind;
         if (hipEventCreate(&p->a) != hipSuccess) return false;
         if (hipEventCreate(&p->b) != hipSuccess) {
@@ -142,8 +143,9 @@ struct KernelTimer {
         (void)hipEventRecord(p->a, st);
         return true;
     }
-    void end(Pair& p, hipStream_t st) {
+    void end(Pair& p, int64_t launches, hipStream_t st) {
         (void)hipEventRecord(p.b, st);
+        p.launches = launches;
         std::lock_guard<std::mutex> lk(mu);
         pending.push_back(p);
     }
@@ -153,7 +155,7 @@ struct KernelTimer {
             float ms = 0.f;
             if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
                 total_ms[p.kind] += ms;
-                count[p.kind] += 1;
+                count[p.kind] += p.launches;
             }
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
@@ -246,13 +248,13 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
         KernelTimer::Pair pi;
         const bool ti = g_timer.begin(1, st, &pi);
         launch_factor_init(dtab, n, itot, fp32, st);
-        if (ti) g_timer.end(pi, st);
+        if (ti) g_timer.end(pi, 1, st);
     }
-    for (int t = 0; t < Tmax; ++t) {
+    {
         KernelTimer::Pair pu;
         const bool tu = g_timer.begin(0, st, &pu);
-        launch_factor_step(dtab, n, t, utot, fp32, st);
-        if (tu) g_timer.end(pu, st);
+        for (int t = 0; t < Tmax; ++t) launch_factor_step(dtab, n, t, utot, fp32, st);
+        if (tu) g_timer.end(pu, Tmax, st);
     }
     g_launches += 2 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
@@ -380,17 +382,17 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     if ((rc = sc.get(&dtab, sizeof(SweepInfo) * MAXB))) return rc;
     if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * MAXB, st))) return rc;
     launch_sweep_init(dtab, n, itot, fp32, conj_b, st);
-    for (int t = 0; t < steps; ++t) {
+    {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        launch_sweep(dtab, n, t, groups, st_max, fp32, true, conj_b, st);
-        if (tm) g_timer.end(p, st);
+        for (int t = 0; t < steps; ++t) launch_sweep(dtab, n, t, groups, st_max, fp32, true, conj_b, st);
+        if (tm) g_timer.end(p, steps, st);
     }
-    for (int t = 0; t + 1 < steps; ++t) {
+    {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        launch_sweep(dtab, n, t, groups, st_max, fp32, false, false, st);
-        if (tm) g_timer.end(p, st);
+        for (int t = 0; t + 1 < steps; ++t) launch_sweep(dtab, n, t, groups, st_max, fp32, false, false, st);
+        if (tm) g_timer.end(p, steps - 1, st);
     }
     g_launches += 2 * (int64_t)steps;
     HIPCHECK(hipGetLastError());
@@ -623,13 +625,11 @@ int64_t helm_counter(int which) { return which == 0 ? g_launches.load() : g_solv
 
 void helm_set_tile_pivoting(int always) { g_force_pivot = always ? 1 : 0; }
 
-void helm_kernel_timing(int enable, int stride) {
+void helm_kernel_timing(int enable) {
     g_timer.drain();
     std::lock_guard<std::mutex> lk(g_timer.mu);
     g_timer.enabled = enable;
-    g_timer.stride = stride > 0 ? stride : 1;
     for (int k = 0; k < 3; ++k) {
-        g_timer.seen[k] = 0;
         g_timer.total_ms[k] = 0.0;
         g_timer.count[k] = 0;
     }

@@ -111,7 +111,7 @@ def lib():
     L.helm_set_tile_pivoting.argtypes = [ctypes.c_int]
     L.helm_set_tile_pivoting.restype = None
     L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
-    L.helm_kernel_timing.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.helm_kernel_timing.argtypes = [ctypes.c_int]
     L.helm_kernel_timing.restype = None
     L.helm_kernel_time.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.helm_kernel_time.restype = ctypes.c_int
@@ -174,12 +174,12 @@ def counters() -> dict:
     return {"launches": int(L.helm_counter(0)), "solves": int(L.helm_counter(1))}
 
 
-KERNEL_KINDS = {"update": 0, "panel": 1, "sweep": 2}
+KERNEL_KINDS = {"factor_step": 0, "factor_init": 1, "sweep": 2}
 
 
-def kernel_timing(enable: bool, stride: int = 1):
-    """Bracket every `stride`-th launch of the hot kernels with HIP events."""
-    lib().helm_kernel_timing(int(enable), int(stride))
+def kernel_timing(enable: bool):
+    """Bracket every run of back-to-back hot-kernel launches with HIP events."""
+    lib().helm_kernel_timing(int(enable))
 
 
 def kernel_time(kind: str):
