@@ -300,7 +300,8 @@ def solve_batch(Fs, Bs, adjoint: bool = False, tol: float = 0.0, stream=None, ou
 
 def misfit_grad(grid: Grid, m, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: float = 0.0,
                 precision="fp64", tol: float = 0.0, stream=None, grad_out=None):
-    """phi and grad phi (adjoint-state, Thm A.1).  d_obs: complex [n_omega][S][Nr]."""
+    """phi and grad phi by the adjoint-state method (appendix "Gradient of phi",
+    Algorithm 3).  d_obs: complex [n_omega][S][Nr]."""
     torch = _torch()
     md = _dev_f64(m, grid.N)
     n_omega = len(omegas)

@@ -1,0 +1,313 @@
+"""Continuous batching of independent Helmholtz factor + solve requests.
+
+A request is a model m on a grid, one or more frequencies and a block of
+right-hand sides (point sources by default).  The server keeps a FIFO queue;
+each scheduler iteration admits every queued request that fits, in arrival
+order, until the chain limit of one batched launch sequence (16 chains; one
+chain per frequency) or the HBM budget is reached.  Admitted requests are
+factored together (one set of launches for all their chains) and solved
+together, so requests that arrive while a batch runs join the next one.
+This is the paper's observation that the solves for different models are
+independent (Appendix, "Parallelisation"), applied to a request stream.
+
+Memory: a request needs its factors (helm_factor_bytes per frequency) plus
+its solutions and refinement buffers (48 bytes per unknown and right-hand
+side per frequency).  With `resident=True`, factors of requests that name a
+`model_key` stay in HBM after the request completes, and are reused by later
+requests with the same key, frequency and precision.  Resident factors count
+against the budget and are evicted least-recently-used when room is needed.
+A request larger than the whole budget is rejected.
+
+    python -m paper_2301_10762_amd.serving --requests 32 --rate 200
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import math
+import sys
+import time
+
+MAX_CHAINS = 16
+BYTES_PER_UNKNOWN_RHS = 48
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    rid: int
+    grid: object                 # helm.Grid
+    m: object                    # FP64 model, length N (device tensor or array)
+    omegas: list
+    sources: list = None         # node indices of unit point sources ...
+    B: object = None             # ... or an explicit [S][N] complex128 device block
+    arrival: float = 0.0         # seconds, relative to the stream start
+    model_key: object = None     # for resident factors
+
+    @property
+    def S(self) -> int:
+        return len(self.sources) if self.B is None else int(self.B.shape[0])
+
+
+@dataclasses.dataclass
+class ServeResult:
+    rid: int
+    X: list                      # per frequency, [S][N] complex128 device tensors
+    infos: list
+    arrival: float
+    start: float
+    done: float
+    batch: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class HelmBackend:
+    """The device path: helm.factor_batch / helm.solve_batch."""
+
+    def __init__(self, precision="fp32_ir", tol=1e-10, stream=None):
+        from . import helm
+        self.helm = helm
+        self.precision = precision
+        self.tol = tol
+        self.stream = stream
+        self.factorisations = 0
+
+    def factor_bytes(self, grid) -> int:
+        return self.helm.factor_bytes(grid, self.precision)
+
+    def factor(self, grids, ms, omegas):
+        self.factorisations += len(grids)
+        return self.helm.factor_batch(grids, ms, omegas, self.precision, self.stream)
+
+    def rhs(self, req: ServeRequest):
+        if req.B is not None:
+            return req.B
+        import torch
+        B = torch.zeros((len(req.sources), req.grid.N), dtype=torch.complex128, device="cuda")
+        idx = torch.as_tensor(list(req.sources), dtype=torch.int64, device="cuda")
+        B[torch.arange(len(req.sources), device="cuda"), idx] = 1.0
+        return B
+
+    def model(self, req: ServeRequest):
+        import torch
+        if isinstance(req.m, torch.Tensor) and req.m.is_cuda:
+            return req.m
+        return torch.as_tensor(req.m, dtype=torch.float64).reshape(-1).to("cuda")
+
+    def solve(self, Fs, Bs):
+        return self.helm.solve_batch(Fs, Bs, tol=self.tol, stream=self.stream)
+
+    def release(self, F):
+        F.close()
+
+    def sync(self):
+        import torch
+        torch.cuda.synchronize()
+
+
+class Server:
+    def __init__(self, backend, hbm_budget: int, max_chains: int = MAX_CHAINS, resident: bool = False,
+                 clock=time.perf_counter):
+        if max_chains < 1 or max_chains > MAX_CHAINS:
+            raise ValueError(f"max_chains must be in [1, {MAX_CHAINS}]")
+        self.be = backend
+        self.budget = int(hbm_budget)
+        self.max_chains = max_chains
+        self.resident = resident
+        self.clock = clock
+        self.queue = collections.deque()
+        self.cache = collections.OrderedDict()     # (key, omega) -> (factor, bytes)
+        self.cache_bytes = 0
+        self.batches = 0
+        self.rejected = []
+
+    # -- memory accounting --------------------------------------------------
+    def _need(self, req: ServeRequest, reuse) -> int:
+        fb = self.be.factor_bytes(req.grid)
+        n_new = sum(1 for w in req.omegas if (req.model_key, float(w)) not in reuse)
+        return n_new * fb + len(req.omegas) * BYTES_PER_UNKNOWN_RHS * req.grid.N * req.S
+
+    def _evict(self, need: int, keep) -> bool:
+        """Free resident factors (least recently used first, never those in
+        `keep`) until `need` more bytes fit.  Returns whether they fit."""
+        while self.cache_bytes + need > self.budget:
+            victim = next((k for k in self.cache if k not in keep), None)
+            if victim is None:
+                return False
+            F, b = self.cache.pop(victim)
+            self.be.release(F)
+            self.cache_bytes -= b
+        return True
+
+    # -- queue --------------------------------------------------------------
+    def submit(self, req: ServeRequest):
+        if len(req.omegas) > self.max_chains:
+            raise ValueError(f"request {req.rid}: {len(req.omegas)} frequencies exceed {self.max_chains} chains")
+        alone = self._need(req, ())
+        if alone > self.budget:
+            self.rejected.append(req.rid)
+            raise MemoryError(f"request {req.rid} needs {alone} bytes, above the HBM budget {self.budget}")
+        self.queue.append(req)
+
+    def admit(self):
+        """Requests of the next batch, FIFO, within the chain and memory limits."""
+        batch, chains, used = [], 0, 0
+        keep = set()
+        while self.queue:
+            req = self.queue[0]
+            if chains + len(req.omegas) > self.max_chains:
+                break
+            keys = {(req.model_key, float(w)) for w in req.omegas} if req.model_key is not None else set()
+            hit = {k for k in keys if k in self.cache}
+            need = self._need(req, hit)
+            if not self._evict(used + need, keep | hit):
+                break
+            self.queue.popleft()
+            keep |= hit
+            batch.append(req)
+            chains += len(req.omegas)
+            used += need
+        return batch
+
+    def step(self):
+        """Run one batch; returns its results (empty if the queue is empty)."""
+        batch = self.admit()
+        if not batch:
+            return []
+        t0 = self.clock()
+        grids, ms, oms, slots = [], [], [], []
+        Fs = {}                                    # (request index, frequency index) -> factor
+        for r, req in enumerate(batch):
+            m = self.be.model(req)
+            for q, w in enumerate(req.omegas):
+                key = (req.model_key, float(w))
+                if req.model_key is not None and key in self.cache:
+                    self.cache.move_to_end(key)
+                    Fs[(r, q)] = self.cache[key][0]
+                else:
+                    grids.append(req.grid)
+                    ms.append(m)
+                    oms.append(float(w))
+                    slots.append((r, q))
+        if grids:
+            for slot, F in zip(slots, self.be.factor(grids, ms, oms)):
+                Fs[slot] = F
+        order = [(r, q) for r, req in enumerate(batch) for q in range(len(req.omegas))]
+        Bs = {r: self.be.rhs(req) for r, req in enumerate(batch)}
+        X, infos = self.be.solve([Fs[k] for k in order], [Bs[k[0]] for k in order])
+        self.be.sync()
+        t1 = self.clock()
+        out, c = [], 0
+        for r, req in enumerate(batch):
+            k = len(req.omegas)
+            out.append(ServeResult(req.rid, X[c:c + k], infos[c:c + k], req.arrival, t0, t1, self.batches))
+            c += k
+        # keep or free the factors made for this batch
+        for r, q in slots:
+            req = batch[r]
+            F = Fs[(r, q)]
+            key = (req.model_key, float(req.omegas[q]))
+            if self.resident and req.model_key is not None and key not in self.cache:
+                b = self.be.factor_bytes(req.grid)
+                if self._evict(b, set()):
+                    self.cache[key] = (F, b)
+                    self.cache_bytes += b
+                    continue
+            self.be.release(F)
+        self.batches += 1
+        return out
+
+    def close(self):
+        for F, _ in self.cache.values():
+            self.be.release(F)
+        self.cache.clear()
+        self.cache_bytes = 0
+
+
+def run_stream(server: Server, requests, realtime: bool = True):
+    """Feed `requests` (sorted by arrival) to the server as they arrive and
+    run it until all are done.  Returns the results in completion order."""
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    results = []
+    t0 = server.clock()
+    while pending or server.queue:
+        now = server.clock() - t0 if realtime else math.inf
+        while pending and pending[0].arrival <= now:
+            server.submit(pending.popleft())
+        if not server.queue:
+            if pending and realtime:
+                time.sleep(max(0.0, pending[0].arrival - (server.clock() - t0)))
+            continue
+        for res in server.step():
+            res.start -= t0
+            res.done -= t0
+            results.append(res)
+    return results
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def summary(results, requests) -> dict:
+    lat = [r.latency for r in results]
+    span = max(r.done for r in results) - min(q.arrival for q in requests)
+    solves = sum(q.S * len(q.omegas) for q in requests)
+    offered = len(requests) / max(1e-12, max(q.arrival for q in requests))
+    served = len(results) / span
+    return {"requests": len(results), "p50_ms": percentile(lat, 0.5) * 1e3, "p99_ms": percentile(lat, 0.99) * 1e3,
+            "max_ms": max(lat) * 1e3, "solves_per_s": solves / span, "offered_req_per_s": offered,
+            "served_req_per_s": served, "stable": served >= 0.95 * offered,
+            "batches": len({r.batch for r in results})}
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    p.add_argument("--requests", type=int, default=32)
+    p.add_argument("--rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--budget-gb", type=float, default=64.0)
+    p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
+    p.add_argument("--max-chains", type=int, default=MAX_CHAINS)
+    args = p.parse_args(argv)
+
+    import torch
+    from . import helm
+    from . import inputs as I
+
+    stream = I.serving_stream(args.requests, args.rate, args.seed)
+    reqs = []
+    for q in stream:
+        m, omega, src = I.request_inputs(q)
+        g = helm.Grid(q.n, q.n, I.H_KM, I.H_KM)
+        reqs.append(ServeRequest(q.rid, g, torch.as_tensor(m.reshape(-1), device="cuda"), [omega], list(src),
+                                 arrival=q.t_arrival))
+    be = HelmBackend(args.precision, 1e-10)
+    # warm-up: one small request through the whole path
+    warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",
+                        dtype=torch.float64), [1.0], [5])
+    srv = Server(be, int(args.budget_gb * 2**30), args.max_chains)
+    srv.submit(warm)
+    srv.step()
+    torch.cuda.synchronize()
+    res = run_stream(srv, reqs)
+    worst = max(i.max_relres for r in res for i in r.infos)
+    out = summary(res, reqs)
+    out.update({"precision": args.precision, "max_relres": worst, "budget_gb": args.budget_gb,
+                "rate": args.rate, "sizes": sorted({q.n for q in stream})})
+    print(json.dumps(out), flush=True)
+    srv.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

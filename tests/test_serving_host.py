@@ -1,0 +1,173 @@
+"""Scheduler logic of the serving layer, on the CPU with a stand-in backend
+(no device work): FIFO admission, the chain and HBM limits, rejection,
+resident factors and their eviction, and that no factor leaks."""
+import dataclasses
+
+import pytest
+
+from paper_2301_10762_amd import serving as SV
+
+
+@dataclasses.dataclass(frozen=True)
+class G:
+    nx: int
+    nz: int
+
+    @property
+    def N(self):
+        return self.nx * self.nz
+
+
+class FakeFactor:
+    def __init__(self, ident, grid, omega):
+        self.ident, self.grid, self.omega, self.live = ident, grid, omega, True
+
+
+class FakeInfo:
+    max_relres = 0.0
+
+
+class FakeBackend:
+    """factor bytes = 100 per unknown; solutions = the factor identities."""
+
+    def __init__(self):
+        self.made, self.calls = [], []
+
+    def factor_bytes(self, grid):
+        return 100 * grid.N
+
+    def factor(self, grids, ms, omegas):
+        self.calls.append(len(grids))
+        out = [FakeFactor(len(self.made) + c, g, w) for c, (g, w) in enumerate(zip(grids, omegas))]
+        self.made += out
+        return out
+
+    def rhs(self, req):
+        return ("B", req.rid)
+
+    def model(self, req):
+        return req.m
+
+    def solve(self, Fs, Bs):
+        assert all(F.live for F in Fs)
+        return [(F.ident, B) for F, B in zip(Fs, Bs)], [FakeInfo() for _ in Fs]
+
+    def release(self, F):
+        assert F.live
+        F.live = False
+
+    def sync(self):
+        pass
+
+    def live(self):
+        return sum(F.live for F in self.made)
+
+
+def req(rid, n=10, omegas=(1.0,), S=4, key=None, arrival=0.0):
+    return SV.ServeRequest(rid, G(n, n), None, list(omegas), list(range(S)), arrival=arrival, model_key=key)
+
+
+def per_request_bytes(n, S, n_omega=1):
+    return n_omega * (100 * n * n + SV.BYTES_PER_UNKNOWN_RHS * n * n * S)
+
+
+def test_fifo_batches_respect_chain_limit():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16)
+    for r in range(20):
+        srv.submit(req(r))
+    first = srv.step()
+    second = srv.step()
+    assert [x.rid for x in first] == list(range(16))
+    assert [x.rid for x in second] == list(range(16, 20))
+    assert be.calls == [16, 4] and be.live() == 0
+    assert srv.step() == []
+
+
+def test_multi_frequency_requests_count_one_chain_per_frequency():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16)
+    srv.submit(req(0, omegas=(1.0, 2.0, 3.0, 4.0, 5.0)))
+    srv.submit(req(1, omegas=(1.0,) * 10))
+    srv.submit(req(2, omegas=(1.0, 2.0)))
+    b1 = srv.step()
+    assert [x.rid for x in b1] == [0, 1]            # 15 chains; request 2 would make 17
+    assert len(b1[0].X) == 5 and len(b1[1].X) == 10
+    assert [x.rid for x in srv.step()] == [2]
+    with pytest.raises(ValueError):
+        srv.submit(req(3, omegas=(1.0,) * 17))
+
+
+def test_memory_budget_limits_batches_and_rejects_oversize():
+    be = FakeBackend()
+    one = per_request_bytes(10, 4)
+    srv = SV.Server(be, 2 * one + one // 2, max_chains=16)
+    for r in range(5):
+        srv.submit(req(r))
+    sizes = []
+    while True:
+        b = srv.step()
+        if not b:
+            break
+        sizes.append(len(b))
+    assert sizes == [2, 2, 1] and be.live() == 0
+    with pytest.raises(MemoryError):
+        srv.submit(req(9, n=40))
+    assert srv.rejected == [9]
+
+
+def test_head_of_line_request_is_not_overtaken():
+    be = FakeBackend()
+    small, big = per_request_bytes(10, 4), per_request_bytes(20, 4)
+    srv = SV.Server(be, big + small // 2, max_chains=16)
+    srv.submit(req(0, n=10))
+    srv.submit(req(1, n=20))
+    srv.submit(req(2, n=10))
+    assert [x.rid for x in srv.step()] == [0]       # 1 does not fit beside 0; 2 must wait behind 1
+    assert [x.rid for x in srv.step()] == [1]
+    assert [x.rid for x in srv.step()] == [2]
+
+
+def test_resident_factors_are_reused_and_evicted_lru():
+    be = FakeBackend()
+    fb = 100 * 100
+    work = SV.BYTES_PER_UNKNOWN_RHS * 100 * 4
+    srv = SV.Server(be, 2 * fb + work, max_chains=16, resident=True)
+    srv.submit(req(0, key="a"))
+    r0 = srv.step()[0]
+    srv.submit(req(1, key="a"))
+    r1 = srv.step()[0]
+    assert be.calls == [1]                          # second request reused the factor
+    assert r1.X[0][0] == r0.X[0][0]
+    assert srv.cache_bytes == fb and be.live() == 1
+    srv.submit(req(2, key="b"))
+    srv.step()
+    assert set(k[0] for k in srv.cache) == {"a", "b"}
+    srv.submit(req(3, key="c"))                     # needs room: "a" is least recently used
+    srv.step()
+    assert set(k[0] for k in srv.cache) == {"b", "c"}
+    assert be.live() == 2
+    srv.close()
+    assert be.live() == 0 and srv.cache_bytes == 0
+
+
+def test_same_key_twice_in_one_batch_does_not_leak():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16, resident=True)
+    srv.submit(req(0, key="a"))
+    srv.submit(req(1, key="a"))
+    srv.step()
+    assert len(srv.cache) == 1 and be.live() == 1
+    srv.close()
+    assert be.live() == 0
+
+
+def test_run_stream_serves_everything_and_summarises():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=4)
+    reqs = [req(r, arrival=0.001 * r) for r in range(10)]
+    res = SV.run_stream(srv, reqs, realtime=False)
+    assert sorted(x.rid for x in res) == list(range(10))
+    s = SV.summary(res, reqs)
+    assert s["requests"] == 10 and s["batches"] == 3
+    assert s["p50_ms"] <= s["p99_ms"] <= s["max_ms"]
