@@ -342,7 +342,8 @@ __host__ __device__ int step_blocks(int np) {
 int factor_init_blocks(int np) { return init_blocks(np); }
 int factor_step_blocks(int np) { return step_blocks(np); }
 
-// D_0 = A_0 into block 0, and T_0 = (first diagonal tile of A_0)^{-1}
+// D = A_{row0} into the first block of each front, and the inverse of its
+// first diagonal tile
 template <typename T>
 __global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n) {
     using C = typename CT<T>::c;
@@ -357,8 +358,8 @@ __global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n
         const int64_t e = (int64_t)local * 256 + threadIdx.x;
         if (e < (int64_t)np * np) {
             const int r = (int)(e / np), q = (int)(e % np);
-            const double2 v = block_entry(d.cf, 0, r, q);
-            ((C*)d.G)[e] = mk<C>(v.x, v.y);
+            const double2 v = block_entry(d.cf, d.row0, r, q);
+            ((C*)d.G)[(size_t)d.row0 * np * np + e] = mk<C>(v.x, v.y);
         }
         return;
     }
@@ -368,13 +369,20 @@ __global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int c = 4 * cg + e;
-        const double2 v = (r < kb && c < kb) ? block_entry(d.cf, 0, r, c) : make_double2(0.0, 0.0);
+        const double2 v = (r < kb && c < kb) ? block_entry(d.cf, d.row0, r, c) : make_double2(0.0, 0.0);
         a[e] = mk<C>(v.x, v.y);
     }
     bool small;
     const int zero = invert_and_store<T>(a, kb, d.pivot, sh, M, (C*)d.Tb, &small);
-    if (zero >= 0 && t == 0) report_zero_pivot(d.status, 0, zero);
+    if (zero >= 0 && t == 0) report_zero_pivot(d.status, d.row0, zero);
     if (small && t == 0) d.status[3] = 1;
+}
+
+// Source of A for the block after local block jl of a front: the merge
+// block for the top front's last block, else null (assemble from m).
+template <typename C>
+__device__ __forceinline__ const C* next_a_source(const ChainInfo& d, int jl) {
+    return (d.Ain && jl + 1 == d.nblk - 1) ? (const C*)d.Ain : nullptr;
 }
 
 // workgroup that prepares the next step's inverted diagonal tile
@@ -383,14 +391,17 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
                           const typename CT<T>::c* Tcur, typename CT<T>::c* Tnext, char* smem) {
     using C = typename CT<T>::c;
     const int np = d.np, kb = ps.kb, k0 = ps.k0;
+    const int row = d.row0 + d.dir * ps.j;
     int jn, kn0, kbn;
+    const C* Asrc = nullptr;
     if (!ps.last_panel) {
-        jn = ps.j;
+        jn = row;
         kn0 = k0 + kb;
     } else {
-        if (ps.j + 1 >= d.cf.nz) return;
-        jn = ps.j + 1;
+        if (ps.j + 1 >= d.nblk) return;
+        jn = row + d.dir;
         kn0 = 0;
+        Asrc = next_a_source<C>(d, ps.j);
     }
     kbn = min(KB, np - kn0);
     C (*sXa)[33] = (C(*)[33])smem;                      // X_{K'K}    kbn x kb
@@ -457,7 +468,13 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            const double2 a1 = block_entry(d.cf, jn, r, c);
+            double2 a1;
+            if (Asrc) {
+                const C v = Asrc[(size_t)r * np + c];
+                a1 = make_double2(v.x, v.y);
+            } else {
+                a1 = block_entry(d.cf, jn, r, c);
+            }
             const double s = row_coupling(d.cf, r) * row_coupling(d.cf, c);
             a[e] = mk<C>(a1.x - s * (double)a[e].x, a1.y - s * (double)a[e].y);
         }
@@ -575,9 +592,21 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                         cmfma<T, V>(accr[bi][bj], acci[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
                                     bv[bj][s].y);
     }
-    // 5. store; after the last panel also D_{j+1} = A_{j+1} - E Y E
-    const bool schur = ps.last_panel && ps.j + 1 < d.cf.nz;
-    C* An = (C*)d.G + (size_t)(ps.j + 1) * np * np;
+    // 5. store; after the last panel also D_next = A_next - E Y E, into the
+    //    front's next block, or into the merge block after a bottom front's
+    //    last block
+    const int row_b = d.row0 + d.dir * ps.j, rn = row_b + d.dir;
+    C* An = nullptr;
+    const C* Asrc = nullptr;
+    if (ps.last_panel) {
+        if (ps.j + 1 < d.nblk) {
+            An = (C*)d.G + (size_t)rn * np * np;
+            Asrc = next_a_source<C>(d, ps.j);
+        } else if (d.Aout) {
+            An = (C*)d.Aout;
+        }
+    }
+    const bool schur = An != nullptr;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -590,7 +619,13 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                 const C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
                 Y[(size_t)row * np + col] = g;
                 if (schur) {
-                    const double2 a1 = block_entry(d.cf, ps.j + 1, row, col);
+                    double2 a1;
+                    if (Asrc) {
+                        const C v = Asrc[(size_t)row * np + col];
+                        a1 = make_double2(v.x, v.y);
+                    } else {
+                        a1 = block_entry(d.cf, rn, row, col);
+                    }
                     const double s = row_coupling(d.cf, row) * row_coupling(d.cf, col);
                     An[(size_t)row * np + col] = mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
                 }
@@ -609,8 +644,9 @@ __global__ __launch_bounds__(256) void k_factor_step(const ChainInfo* tab, int n
     const int np = d.np;
     const size_t n2 = (size_t)np * np;
     C* G = (C*)d.G;
-    const C* X = ps.p == 0 ? G + (size_t)ps.j * n2 : (const C*)((ps.p - 1) & 1 ? d.P1 : d.P0);
-    C* Y = ps.last_panel ? G + (size_t)ps.j * n2 : (C*)(ps.p & 1 ? d.P1 : d.P0);
+    const int row = d.row0 + d.dir * ps.j;
+    const C* X = ps.p == 0 ? G + (size_t)row * n2 : (const C*)((ps.p - 1) & 1 ? d.P1 : d.P0);
+    C* Y = ps.last_panel ? G + (size_t)row * n2 : (C*)(ps.p & 1 ? d.P1 : d.P0);
     const C* Tcur = (const C*)d.Tb + (size_t)(tstep & 1) * KB * KB;
     C* Tnext = (C*)d.Tb + (size_t)((tstep + 1) & 1) * KB * KB;
     const int ti = blockIdx.x - d.utile0;

@@ -194,10 +194,13 @@ int check_model(const double* m, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------ factorisation --
-// Factor a group of at most MAXB chains of one precision in lockstep: one
-// initial launch, then one launch per panel step.  With pivot == 0 the
-// diagonal tiles are inverted with diagonal pivots; *needs_pivot reports a
-// chain that met a pivot below the tolerance (the caller refactors it).
+// Factor a group of at most MAXB / 2 systems of one precision in lockstep,
+// each as a top and (when nz >= 4) a bottom front: one initial launch, then
+// one launch per panel step.  With pivot == 0 the diagonal tiles are
+// inverted with diagonal pivots; *needs_pivot reports a front that met a
+// pivot below the tolerance (the caller refactors the group).
+constexpr int MAXF = MAXB / 2;   // systems per factorisation or sweep group
+
 int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, bool* needs_pivot) {
     *needs_pivot = false;
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
@@ -205,41 +208,65 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     Scratch sc(st);
     std::vector<ChainInfo> tab(MAXB);
     std::memset(tab.data(), 0, sizeof(ChainInfo) * MAXB);
-    for (int c = n; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
-    int utot = 0, itot = 0, Tmax = 0;
+    for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
+    int utot = 0, itot = 0, Tmax = 0, nf = 0;
     size_t buf = 0;
-    for (int c = 0; c < n; ++c) buf += (2 * (size_t)fs[c]->np * fs[c]->np + 2 * (size_t)KB * KB) * es + 256;
+    for (int c = 0; c < n; ++c) {
+        const size_t n2 = (size_t)fs[c]->np * fs[c]->np;
+        buf += 2 * (2 * n2 + 2 * (size_t)KB * KB) * es + n2 * es + 5 * 256;
+    }
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
     int* status;
-    if ((rc = sc.get(&status, sizeof(int) * 4 * n))) return rc;
-    launch_zero(status, sizeof(int) * 4 * n, st);
+    if ((rc = sc.get(&status, sizeof(int) * 4 * 2 * n))) return rc;
+    launch_zero(status, sizeof(int) * 4 * 2 * n, st);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void* p = arena + off;
         off = (off + bytes + 255) / 256 * 256;
         return p;
     };
+    std::vector<int> owner;
     for (int c = 0; c < n; ++c) {
         helm_factor_s* f = fs[c];
-        ChainInfo& ci = tab[c];
         const size_t n2 = (size_t)f->np * f->np;
-        ci.G = f->G;
-        ci.P0 = take(n2 * es);
-        ci.P1 = take(n2 * es);
-        ci.Tb = take(2 * (size_t)KB * KB * es);
-        ci.status = status + 4 * c;
-        ci.cf = coef_of(f);
-        ci.np = f->np;
-        ci.npan = (f->np + KB - 1) / KB;
-        ci.T = ci.npan * f->g.nz;
-        ci.pivot = pivot;
-        ci.utile0 = utot;
-        utot += factor_step_blocks(f->np);
-        ci.itile0 = itot;
-        itot += factor_init_blocks(f->np);
-        Tmax = std::max(Tmax, ci.T);
+        const int nz = f->g.nz, k = twist_row(nz);
+        const bool bottom = k < nz - 1;
+        void* merge = bottom ? take(n2 * es) : nullptr;
+        for (int side = 0; side < (bottom ? 2 : 1); ++side) {
+            ChainInfo& ci = tab[nf];
+            ci.G = f->G;
+            ci.P0 = take(n2 * es);
+            ci.P1 = take(n2 * es);
+            ci.Tb = take(2 * (size_t)KB * KB * es);
+            ci.status = status + 4 * nf;
+            ci.cf = coef_of(f);
+            ci.np = f->np;
+            ci.npan = (f->np + KB - 1) / KB;
+            if (side == 0) {
+                ci.row0 = 0;
+                ci.dir = 1;
+                ci.nblk = k + 1;
+                ci.Ain = merge;
+                ci.Aout = nullptr;
+            } else {
+                ci.row0 = nz - 1;
+                ci.dir = -1;
+                ci.nblk = nz - 1 - k;
+                ci.Ain = nullptr;
+                ci.Aout = merge;
+            }
+            ci.T = ci.npan * ci.nblk;
+            ci.pivot = pivot;
+            ci.utile0 = utot;
+            utot += factor_step_blocks(f->np);
+            ci.itile0 = itot;
+            itot += factor_init_blocks(f->np);
+            Tmax = std::max(Tmax, ci.T);
+            owner.push_back(c);
+            ++nf;
+        }
     }
     ChainInfo* dtab;
     if ((rc = sc.get(&dtab, sizeof(ChainInfo) * MAXB))) return rc;
@@ -247,25 +274,26 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     {
         KernelTimer::Pair pi;
         const bool ti = g_timer.begin(1, st, &pi);
-        launch_factor_init(dtab, n, itot, fp32, st);
+        launch_factor_init(dtab, nf, itot, fp32, st);
         if (ti) g_timer.end(pi, 1, st);
     }
     {
         KernelTimer::Pair pu;
         const bool tu = g_timer.begin(0, st, &pu);
-        for (int t = 0; t < Tmax; ++t) launch_factor_step(dtab, n, t, utot, fp32, st);
+        for (int t = 0; t < Tmax; ++t) launch_factor_step(dtab, nf, t, utot, fp32, st);
         if (tu) g_timer.end(pu, Tmax, st);
     }
     g_launches += 2 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
-    std::vector<int> hs(4 * n);
-    HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * 4 * n, hipMemcpyDeviceToHost, st));
+    std::vector<int> hs(4 * nf);
+    HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * 4 * nf, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    for (int c = 0; c < n; ++c)
+    for (int c = 0; c < nf; ++c)
         if (hs[4 * c])
-            return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: chain " + std::to_string(c) + ", block " +
-                                            std::to_string(hs[4 * c + 1]) + ", row " + std::to_string(hs[4 * c + 2]));
-    for (int c = 0; c < n; ++c)
+            return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: system " + std::to_string(owner[c]) +
+                                            ", block " + std::to_string(hs[4 * c + 1]) + ", row " +
+                                            std::to_string(hs[4 * c + 2]));
+    for (int c = 0; c < nf; ++c)
         if (hs[4 * c + 3]) *needs_pivot = true;
     return HELM_OK;
 }
@@ -317,8 +345,8 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
             return fail(HELM_EDEVICE, "model copy failed");
         }
     }
-    for (int c0 = 0; c0 < count; c0 += MAXB) {
-        const int k = std::min(MAXB, count - c0);
+    for (int c0 = 0; c0 < count; c0 += MAXF) {
+        const int k = std::min(MAXF, count - c0);
         bool needs = false;
         int rc = factor_group(fs.data() + c0, k, g_force_pivot, st, &needs);
         if (rc == HELM_OK && needs) rc = factor_group(fs.data() + c0, k, 1, st, &needs);
@@ -332,10 +360,11 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
 }
 
 // ----------------------------------------------------------------- sweeps --
-// X = A^{-1} Y for a group of factors of one precision: forward then
-// backward block sweep.  FP64: Y, X complex128; FP32: complex64.  With
-// conj_b the forward sweep reads conj(Y) (the adjoint solve A^{-*} r =
-// conj(A^{-1} conj r); the caller conjugates the result).
+// X = A^{-1} Y for a group of at most MAXF factors of one precision: forward
+// then backward block sweeps, from both ends of each grid.  FP64: Y, X
+// complex128; FP32: complex64.  With conj_b the forward sweep reads conj(Y)
+// (the adjoint solve A^{-*} r = conj(A^{-1} conj r); the caller conjugates
+// the result).
 int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const int64_t* ldy, void* const* Xs,
                 const int64_t* ldx, const int* Ss, bool conj_b, hipStream_t st) {
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
@@ -343,58 +372,85 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     Scratch sc(st);
     std::vector<SweepInfo> tab(MAXB);
     std::memset(tab.data(), 0, sizeof(SweepInfo) * MAXB);
-    for (int c = n; c < MAXB; ++c) tab[c].tile0 = tab[c].itile0 = INT32_MAX;
-    int groups = 0, st_max = 0, itot = 0, steps = 0;
+    for (int c = 0; c < MAXB; ++c) tab[c].tile0 = tab[c].itile0 = INT32_MAX;
+    int groups = 0, st_max = 0, itot = 0, fsteps = 0, bsteps = 0, nf = 0;
     size_t buf = 0;
-    for (int c = 0; c < n; ++c) buf += 2 * ((size_t)fs[c]->np * Ss[c] * es + 256);
+    for (int c = 0; c < n; ++c) buf += 5 * ((size_t)fs[c]->np * Ss[c] * es + 256);
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
     size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void* p = arena + off;
+        off = (off + bytes + 255) / 256 * 256;
+        return p;
+    };
     for (int c = 0; c < n; ++c) {
         const helm_factor_s* f = fs[c];
-        SweepInfo& si = tab[c];
         const size_t yb = (size_t)f->np * Ss[c] * es;
-        si.G = f->G;
-        si.B = Ys[c];
-        si.X = Xs[c];
-        si.Y0 = arena + off;
-        off = (off + yb + 255) / 256 * 256;
-        si.Y1 = arena + off;
-        off = (off + yb + 255) / 256 * 256;
-        si.ldb = ldy[c];
-        si.ldx = ldx[c];
-        si.S = Ss[c];
-        si.nx = f->g.nx;
-        si.nz = f->g.nz;
-        si.np = f->np;
-        si.cz = f->g.hx / f->g.hz;
-        si.tiles_s = sweep_col_tiles(Ss[c]);
-        si.tile0 = groups;
-        groups += sweep_row_tiles(f->np);
-        st_max = std::max(st_max, si.tiles_s);
-        si.itile0 = itot;
-        itot += (int)(((int64_t)f->np * Ss[c] + 255) / 256);
-        steps = std::max(steps, f->g.nz);
+        const int nz = f->g.nz, k = twist_row(nz);
+        const bool bottom = k < nz - 1;
+        const int top = nf;
+        for (int side = 0; side < (bottom ? 2 : 1); ++side) {
+            SweepInfo& si = tab[nf++];
+            si.G = f->G;
+            si.B = Ys[c];
+            si.X = Xs[c];
+            si.Y0 = take(yb);
+            si.Y1 = take(yb);
+            si.ldb = ldy[c];
+            si.ldx = ldx[c];
+            si.S = Ss[c];
+            si.nx = f->g.nx;
+            si.nz = nz;
+            si.np = f->np;
+            si.cz = f->g.hx / f->g.hz;
+            if (side == 0) {        // rows 0..k, then back from k-1 to 0
+                si.row0 = 0;
+                si.dir = 1;
+                si.nfwd = k + 1;
+                si.brow0 = k - 1;
+                si.nbwd = k;
+            } else {                // rows nz-1..k+1, then back from k+1 to nz-1
+                si.row0 = nz - 1;
+                si.dir = -1;
+                si.nfwd = nz - 1 - k;
+                si.brow0 = k + 1;
+                si.nbwd = nz - 1 - k;
+                SweepInfo& t = tab[top];
+                si.Mout = take(yb);
+                t.Bm = si.Mout;
+                // the bottom front's first backward step reads buffer nfwd & 1
+                t.Zp = (si.nfwd & 1) ? si.Y1 : si.Y0;
+            }
+            si.tiles_s = sweep_col_tiles(Ss[c]);
+            si.tile0 = groups;
+            groups += sweep_row_tiles(f->np);
+            st_max = std::max(st_max, si.tiles_s);
+            si.itile0 = itot;
+            itot += (int)(((int64_t)f->np * Ss[c] + 255) / 256);
+            fsteps = std::max(fsteps, si.nfwd);
+            bsteps = std::max(bsteps, si.nbwd);
+        }
         g_solves += Ss[c];
     }
     SweepInfo* dtab;
     if ((rc = sc.get(&dtab, sizeof(SweepInfo) * MAXB))) return rc;
     if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * MAXB, st))) return rc;
-    launch_sweep_init(dtab, n, itot, fp32, conj_b, st);
+    launch_sweep_init(dtab, nf, itot, fp32, conj_b, st);
     {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < steps; ++t) launch_sweep(dtab, n, t, groups, st_max, fp32, true, conj_b, st);
-        if (tm) g_timer.end(p, steps, st);
+        for (int t = 0; t < fsteps; ++t) launch_sweep(dtab, nf, t, groups, st_max, fp32, true, conj_b, st);
+        if (tm) g_timer.end(p, fsteps, st);
     }
-    {
+    if (bsteps > 0) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t + 1 < steps; ++t) launch_sweep(dtab, n, t, groups, st_max, fp32, false, false, st);
-        if (tm) g_timer.end(p, steps - 1, st);
+        for (int t = 0; t < bsteps; ++t) launch_sweep(dtab, nf, t, groups, st_max, fp32, false, false, st);
+        if (tm) g_timer.end(p, bsteps, st);
     }
-    g_launches += 2 * (int64_t)steps;
+    g_launches += 1 + (int64_t)fsteps + bsteps;
     HIPCHECK(hipGetLastError());
     return HELM_OK;
 }
@@ -464,8 +520,8 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
             ldy[c] = ldx[c] = jobs[c].ld;
             Ss[c] = jobs[c].S;
         }
-        for (int c0 = 0; c0 < n; c0 += MAXB) {
-            int k = std::min(MAXB, n - c0);
+        for (int c0 = 0; c0 < n; c0 += MAXF) {
+            int k = std::min(MAXF, n - c0);
             int rc = sweep_group(fs.data() + c0, k, Ys.data() + c0, ldy.data() + c0, Xs.data() + c0, ldx.data() + c0,
                                  Ss.data() + c0, adjoint, st);
             if (rc) return rc;
@@ -550,8 +606,8 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
                 idx.push_back(c);
             }
         if (af.empty()) break;
-        for (size_t c0 = 0; c0 < af.size(); c0 += MAXB) {
-            int k = (int)std::min<size_t>(MAXB, af.size() - c0);
+        for (size_t c0 = 0; c0 < af.size(); c0 += MAXF) {
+            int k = (int)std::min<size_t>(MAXF, af.size() - c0);
             int rc = sweep_group(af.data() + c0, k, ay.data() + c0, al.data() + c0, ax.data() + c0, al.data() + c0,
                                  as.data() + c0, false, st);
             if (rc) return rc;

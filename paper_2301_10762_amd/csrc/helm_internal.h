@@ -17,37 +17,64 @@ struct Coef {
     int nx, nz;
 };
 
-// One chain (one system) of a batched factorisation.  The table lives in
-// device memory; the launch for global step t makes every chain with t < T
-// do panel p = t % npan of block j = t / npan.
+// One front of a batched factorisation.  A system is factored from both
+// ends ("twisted"): a top front runs down rows 0, 1, .., k and a bottom front
+// up rows nz-1, nz-2, .., k+1, each forming D_next = A_next - E G E.  The
+// bottom front finishes earlier and leaves A_k - E G_{k+1} E in a merge
+// block, which the top front uses in place of A_k when it forms D_k, so
+// G_k is the inverse of the full Schur complement at row k.  The table lives
+// in device memory; the launch for global step t makes every front with
+// t < T do panel p = t % npan of its block jl = t / npan (grid row
+// row0 + dir * jl).
 struct ChainInfo {
-    void* G;        // nz blocks of np x np row-major complex; block j ends as D_j^{-1}
+    void* G;        // nz blocks of np x np row-major complex; block j ends as its Schur inverse
     void* P0;       // ping-pong working blocks (np x np) between panel steps
     void* P1;
     void* Tb;       // two KB x KB slots holding the inverted diagonal tile,
                     // transposed (Tt[c][k] = T[k][c]); step t reads slot t&1
     int* status;    // [0] zero-pivot flag, [1] block, [2] row, [3] small-pivot flag
+    void* Aout;     // bottom front: receives A_next - E G E after its last block
+    const void* Ain;   // top front: replaces A of its last block (the merge block)
     Coef cf;
-    int np, npan, T;        // padded size, panels per block, steps (nz * npan)
+    int np, npan, T;        // padded size, panels per block, steps (nblk * npan)
+    int row0, dir, nblk;    // first grid row, +1 (down) or -1 (up), blocks of this front
     int pivot;              // 0: diagonal pivots (flagged if small), 1: partial pivoting in tiles
-    int utile0;             // first workgroup of this chain in a step launch
+    int utile0;             // first workgroup of this front in a step launch
     int itile0;             // first workgroup in the initial launch
 };
 
-// One chain of a batched block sweep.  The coupling vectors y_j = b_j -
-// E w_{j-1} (forward) and z_j = E x_{j+1} (backward) are produced by the
-// workgroups that compute the rows they depend on and kept in two ping-pong
-// buffers of np x S (column-major, leading dimension np, zero below nx).
+// Row k at which the two fronts of an nz-row system meet (the top front ends
+// there), or nz - 1 when there is no bottom front.  The bottom front has
+// nz - 1 - k < k blocks, so it ends at least one launch before the top front
+// needs its merge block.
+__host__ __device__ inline int twist_row(int nz) {
+    const int k = (nz + 1) / 2;
+    return (nz - 1 - k >= 1) ? k : nz - 1;
+}
+
+// One front of a batched block sweep.  Forward: w_j = G_j y_j and the next
+// coupling vector y_{j+dir} = b_{j+dir} - E w_j; backward: x_j = w_j - G_j z_j
+// and z_{j-dir} = E x_j.  Coupling vectors are produced by the workgroups
+// that compute the rows they depend on and kept in two ping-pong buffers of
+// np x S (column-major, leading dimension np, zero below nx).  With a bottom
+// front, its last forward step leaves b_k - E w_{k+1} in `Mout`, which the
+// top front reads in place of b_k; the top front's last forward step gives
+// x_k and starts both backward sweeps with E x_k (its own buffer and `Zp`).
 struct SweepInfo {
     const void* G;  // factor blocks
     const void* B;  // right-hand sides, column-major (ldb)
     void* X;        // solution being built, column-major (ldx)
     void* Y0;       // coupling vectors, ping-pong
     void* Y1;
+    const void* Bm; // top front: b_k replaced by the bottom front's b_k - E w_{k+1}
+    void* Mout;     // bottom front: where that vector goes
+    void* Zp;       // top front: the bottom front's first backward input
     int64_t ldb, ldx;
     int S, nx, nz, np;
     double cz;      // hx / hz: the z-edge coupling is -cz (halved at i = 0, nx-1)
-    int tile0, tiles_s;     // first row tile (of 16 rows) of this chain, its column tiles
+    int row0, dir, nfwd;    // forward: rows row0 + dir * t, t < nfwd
+    int brow0, nbwd;        // backward: rows brow0 - dir * t, t < nbwd
+    int tile0, tiles_s;     // first row tile (of 16 rows) of this front, its column tiles
     int itile0;             // first workgroup of the initial launch
 };
 
@@ -56,10 +83,11 @@ int factor_init_blocks(int np);
 int factor_step_blocks(int np);
 void launch_factor_init(const ChainInfo* tab, int n, int total_blocks, bool fp32, hipStream_t st);
 void launch_factor_step(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
-// y_0 = b_0 (conjugated for adjoint solves) into Y0 of every chain
+// y = b_{row0} (conjugated for adjoint solves) into Y0 of every front
 void launch_sweep_init(const SweepInfo* tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
-// forward: step t is block j = t; backward: step t is block j = nz - 2 - t.
-// `groups` row tiles (16 rows) over all chains, `st` column tiles (16 columns).
+// forward step t: row row0 + dir * t of each front; backward step t: row
+// brow0 - dir * t.  `groups` row tiles (16 rows) over all fronts, `st` column
+// tiles (16 columns).
 void launch_sweep(const SweepInfo* tab, int n, int t, int groups, int st, bool fp32, bool forward,
                   bool conj_b, hipStream_t st_);
 int sweep_row_tiles(int np);

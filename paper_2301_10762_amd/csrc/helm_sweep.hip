@@ -1,8 +1,10 @@
 // Block sweeps of libhelm (gfx950): multi-right-hand-side forward and back
-// substitution with the stored Schur-complement inverses G_j = D_j^{-1},
-//     forward   w_j = G_j y_j,          y_{j+1} = b_{j+1} - E w_j,
-//     backward  x_j = w_j - G_j z_j,    z_{j-1} = E x_j,
-// one launch per block row, every chain of the batch in the same launch.
+// substitution with the stored Schur-complement inverses G_j,
+//     forward   w_j = G_j y_j,          y_{j+dir} = b_{j+dir} - E w_j,
+//     backward  x_j = w_j - G_j z_j,    z_{j-dir} = E x_j,
+// run from both ends of the grid at once (the two fronts of the twisted
+// factorisation meet at row k, where w_k = x_k), one launch per step, every
+// front of the batch in the same launch.
 // A workgroup computes a 16-row x 16-column tile of the block product on
 // the matrix cores (four waves split the contraction and are summed in a
 // fixed order) and, for the same rows, the coupling vector the next step
@@ -24,7 +26,7 @@ __device__ __forceinline__ C conj_if(C v, bool c) {
     return v;
 }
 
-// y_0 = b_0 (rows >= nx zero)
+// y = b_{row0} (rows >= nx zero)
 template <typename T, bool CONJB>
 __global__ __launch_bounds__(256) void k_sweep_init(const SweepInfo* tab, int n) {
     using C = typename CT<T>::c;
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepInfo* tab, int n)
     if (e >= (int64_t)d.np * d.S) return;
     const int s = (int)(e / d.np), k = (int)(e % d.np);
     C v = mk<C>(0.0, 0.0);
-    if (k < d.nx) v = conj_if(((const C*)d.B)[(size_t)s * d.ldb + k], CONJB);
+    if (k < d.nx) v = conj_if(((const C*)d.B)[(size_t)s * d.ldb + (size_t)d.row0 * d.nx + k], CONJB);
     ((C*)d.Y0)[e] = v;
 }
 
@@ -53,16 +55,16 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepInfo* tab, i
     const int ci = find_chain(tab, n, g, [](const SweepInfo& c) { return c.tile0; });
     const SweepInfo& d = tab[ci];
     if (sidx >= d.tiles_s) return;
-    const int j = FWD ? tstep : d.nz - 2 - tstep;
-    if (j < 0 || j >= d.nz) return;
+    if (tstep >= (FWD ? d.nfwd : d.nbwd)) return;
+    const int j = FWD ? d.row0 + d.dir * tstep : d.brow0 - d.dir * tstep;
     const int i0 = 16 * (g - d.tile0), s0 = SW_TILE_S * sidx;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
     const int np = d.np, nx = d.nx;
     const C* G = (const C*)d.G + (size_t)j * np * np + (size_t)(i0 + lr) * np;
-    // launches of one solve alternate the coupling buffers: forward step t is
-    // launch t, backward step t is launch nz + t of this chain
-    const int u = FWD ? tstep : d.nz + tstep;
+    // steps of one front alternate the coupling buffers: forward step t is
+    // step t, backward step t is step nfwd + t of the front
+    const int u = FWD ? tstep : d.nfwd + tstep;
     const C* Yin = (const C*)((u & 1) ? d.Y1 : d.Y0);
     C* Yout = (C*)((u & 1) ? d.Y0 : d.Y1);
     const int s = s0 + lr;
@@ -70,9 +72,14 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepInfo* tab, i
     const C* y = Yin + (size_t)(scol ? s : 0) * np;
 
     // epilogue operands of wave 0 (next block's right-hand side, or this
-    // block's forward result), fetched before the contraction
-    const C* Bm = (const C*)d.B;
+    // block's forward result), fetched before the contraction.  Forward:
+    // `more` - the front continues; else a bottom front hands its vector to
+    // the top front (Mout), and the top front's last step is x_k.
+    const C* Bv = (const C*)d.B;
     C* X = (C*)d.X;
+    const bool more = FWD && tstep + 1 < d.nfwd;
+    const bool merge_in = more && d.Bm && tstep + 2 == d.nfwd;
+    const bool hand_over = FWD && !more && d.Mout;
     C pre[4];
     if (w == 0) {
 #pragma unroll
@@ -81,7 +88,9 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepInfo* tab, i
             pre[e] = mk<C>(0.0, 0.0);
             if (scol && i < nx) {
                 if (FWD) {
-                    if (j + 1 < d.nz) pre[e] = conj_if(Bm[(size_t)s * d.ldb + (size_t)(j + 1) * nx + i], CONJB);
+                    if (merge_in) pre[e] = ((const C*)d.Bm)[(size_t)s * np + i];
+                    else if (more || hand_over)
+                        pre[e] = conj_if(Bv[(size_t)s * d.ldb + (size_t)(j + d.dir) * nx + i], CONJB);
                 } else {
                     pre[e] = X[(size_t)s * d.ldx + (size_t)j * nx + i];
                 }
@@ -130,15 +139,22 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepInfo* tab, i
         const T ei = (T)(i >= nx ? 0.0 : ((i == 0 || i == nx - 1) ? -0.5 * d.cz : -d.cz));
         C nxt = mk<C>(0.0, 0.0);
         if (FWD) {
-            // w_j; the next step's y_{j+1} = b_{j+1} - E w_j, or z_{nz-2} = E w_{nz-1}
+            // w_j; the next step's y_{j+dir} = b_{j+dir} - E w_j; at the end
+            // of a bottom front that vector goes to the top front, and at the
+            // end of a top front (w_j = x_j) both backward sweeps start with E x_j
             if (i < nx) X[(size_t)s * d.ldx + (size_t)j * nx + i] = mk<C>(sr, si);
-            if (j + 1 < d.nz) {
+            if (more || hand_over) {
                 if (i < nx) nxt = mk<C>(pre[e].x - ei * sr, pre[e].y - ei * si);
+                if (hand_over) {
+                    ((C*)d.Mout)[(size_t)s * np + i] = nxt;
+                    continue;
+                }
             } else {
                 nxt = mk<C>(ei * sr, ei * si);
+                if (d.Zp) ((C*)d.Zp)[(size_t)s * np + i] = nxt;
             }
         } else {
-            // x_j = w_j - G_j z_j; the next step's z_{j-1} = E x_j
+            // x_j = w_j - G_j z_j; the next step's z = E x_j
             if (i < nx) {
                 const C xn = mk<C>(pre[e].x - sr, pre[e].y - si);
                 X[(size_t)s * d.ldx + (size_t)j * nx + i] = xn;
