@@ -14,6 +14,35 @@ template <> struct CT<double> { using c = double2; using v4 = v4d; };
 template <> struct CT<float> { using c = float2; using v4 = v4f; };
 
 template <typename C> __device__ __forceinline__ C mk(double re, double im) { C r; r.x = re; r.y = im; return r; }
+
+// Loads and stores through pointers read from the device-side tables.  The
+// compiler cannot tell that such generic pointers address global memory and
+// would emit flat instructions, whose completion is counted together with
+// LDS and scalar traffic (so every wait drains everything); these give
+// global_* instructions.
+#define HELM_GLOBAL __attribute__((address_space(1)))
+typedef double gv2d __attribute__((ext_vector_type(2)));
+typedef float gv2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gld(const double2* p) {
+    const gv2d v = *(const HELM_GLOBAL gv2d*)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gld(const float2* p) {
+    const gv2f v = *(const HELM_GLOBAL gv2f*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(double2* p, double2 v) {
+    gv2d w;
+    w.x = v.x;
+    w.y = v.y;
+    *(HELM_GLOBAL gv2d*)p = w;
+}
+__device__ __forceinline__ void gst(float2* p, float2 v) {
+    gv2f w;
+    w.x = v.x;
+    w.y = v.y;
+    *(HELM_GLOBAL gv2f*)p = w;
+}
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }

@@ -345,12 +345,12 @@ int factor_step_blocks(int np) { return step_blocks(np); }
 // D = A_{row0} into the first block of each front, and the inverse of its
 // first diagonal tile
 template <typename T>
-__global__ __launch_bounds__(256) void k_factor_init(const ChainInfo* tab, int n) {
+__global__ __launch_bounds__(256) void k_factor_init(const ChainTab tab, int n) {
     using C = typename CT<T>::c;
     __shared__ C M[32][33];
     __shared__ GJScratch<T> sh;
-    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
-    const ChainInfo& d = tab[ci];
+    const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
+    const ChainInfo d = tab.c[ci];
     const int local = blockIdx.x - d.itile0;
     const int np = d.np;
     const int nfill = init_blocks(np) - 1;
@@ -617,7 +617,8 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
             for (int e = 0; e < 4; ++e) {
                 const int row = R[bi] + acc_row<T>(lg, e);
                 const C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
-                Y[(size_t)row * np + col] = g;
+                // the finished inverse goes to the sweeps' operand layout
+                gst(Y + (ps.last_panel ? a_tiled(row, col, np) : (size_t)row * np + col), g);
                 if (schur) {
                     double2 a1;
                     if (Asrc) {
@@ -634,11 +635,11 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_factor_step(const ChainInfo* tab, int n, int tstep) {
+__global__ __launch_bounds__(256) void k_factor_step(const ChainTab tab, int n, int tstep) {
     using C = typename CT<T>::c;
     __shared__ __attribute__((aligned(16))) char smem[SM_BYTES_D];
-    const int ci = find_chain(tab, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
-    const ChainInfo& d = tab[ci];
+    const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
+    const ChainInfo d = tab.c[ci];
     if (tstep >= d.T) return;
     const PanelStep ps = panel_step(d, tstep);
     const int np = d.np;
@@ -681,11 +682,11 @@ __global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const d
     if (t == 0 && small) status[blockIdx.x] = -1;
 }
 
-void launch_factor_init(const ChainInfo* tab, int n, int total, bool fp32, hipStream_t st) {
+void launch_factor_init(const ChainTab& tab, int n, int total, bool fp32, hipStream_t st) {
     if (fp32) hipLaunchKernelGGL(k_factor_init<float>, dim3(total), dim3(256), 0, st, tab, n);
     else hipLaunchKernelGGL(k_factor_init<double>, dim3(total), dim3(256), 0, st, tab, n);
 }
-void launch_factor_step(const ChainInfo* tab, int n, int t, int total, bool fp32, hipStream_t st) {
+void launch_factor_step(const ChainTab& tab, int n, int t, int total, bool fp32, hipStream_t st) {
     if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t);
     else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t);
 }

@@ -84,38 +84,6 @@ struct Scratch {
     }
 };
 
-// Pinned host staging for the small per-launch chain tables: a slot is only
-// rewritten after the copy that last used it has completed.
-struct PinnedRing {
-    static constexpr int NSLOT = 64;
-    static constexpr size_t SLOT = 4096;
-    char* host = nullptr;
-    hipEvent_t ev[NSLOT];
-    bool used[NSLOT] = {};
-    int next = 0;
-    std::mutex mu;
-    int upload(void* dev, const void* src, size_t bytes, hipStream_t st) {
-        std::lock_guard<std::mutex> lk(mu);
-        if (bytes > SLOT) return fail(HELM_EINVAL, "chain table too large");
-        if (!host) {
-            if (hipHostMalloc((void**)&host, SLOT * NSLOT, hipHostMallocDefault) != hipSuccess) {
-                host = nullptr;
-                return fail(HELM_ENOMEM, "pinned staging allocation failed");
-            }
-            for (int q = 0; q < NSLOT; ++q) HIPCHECK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
-        }
-        const int q = next;
-        next = (next + 1) % NSLOT;
-        if (used[q]) HIPCHECK(hipEventSynchronize(ev[q]));
-        std::memcpy(host + q * SLOT, src, bytes);
-        HIPCHECK(hipMemcpyAsync(dev, host + q * SLOT, bytes, hipMemcpyHostToDevice, st));
-        HIPCHECK(hipEventRecord(ev[q], st));
-        used[q] = true;
-        return HELM_OK;
-    }
-};
-PinnedRing g_ring;
-
 // Optional live timing of the dominant kernels with HIP events: each run of
 // back-to-back launches of one kind on a stream (the panel steps of a
 // factorisation group, the steps of one forward or one backward sweep) is
@@ -206,8 +174,9 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
     const size_t es = elem_bytes(fs[0]->prec);
     Scratch sc(st);
-    std::vector<ChainInfo> tab(MAXB);
-    std::memset(tab.data(), 0, sizeof(ChainInfo) * MAXB);
+    ChainTab ctab;
+    std::memset(&ctab, 0, sizeof(ctab));
+    ChainInfo* tab = ctab.c;
     for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
     int utot = 0, itot = 0, Tmax = 0, nf = 0;
     size_t buf = 0;
@@ -268,19 +237,16 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             ++nf;
         }
     }
-    ChainInfo* dtab;
-    if ((rc = sc.get(&dtab, sizeof(ChainInfo) * MAXB))) return rc;
-    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(ChainInfo) * MAXB, st))) return rc;
     {
         KernelTimer::Pair pi;
         const bool ti = g_timer.begin(1, st, &pi);
-        launch_factor_init(dtab, nf, itot, fp32, st);
+        launch_factor_init(ctab, nf, itot, fp32, st);
         if (ti) g_timer.end(pi, 1, st);
     }
     {
         KernelTimer::Pair pu;
         const bool tu = g_timer.begin(0, st, &pu);
-        for (int t = 0; t < Tmax; ++t) launch_factor_step(dtab, nf, t, utot, fp32, st);
+        for (int t = 0; t < Tmax; ++t) launch_factor_step(ctab, nf, t, utot, fp32, st);
         if (tu) g_timer.end(pu, Tmax, st);
     }
     g_launches += 2 + (int64_t)Tmax;
@@ -370,12 +336,14 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     const bool fp32 = fs[0]->prec == HELM_FP32_IR;
     const size_t es = elem_bytes(fs[0]->prec);
     Scratch sc(st);
-    std::vector<SweepInfo> tab(MAXB);
-    std::memset(tab.data(), 0, sizeof(SweepInfo) * MAXB);
+    SweepTab stab;
+    std::memset(&stab, 0, sizeof(stab));
+    SweepInfo* tab = stab.c;
     for (int c = 0; c < MAXB; ++c) tab[c].tile0 = tab[c].itile0 = INT32_MAX;
     int groups = 0, st_max = 0, itot = 0, fsteps = 0, bsteps = 0, nf = 0;
     size_t buf = 0;
-    for (int c = 0; c < n; ++c) buf += 5 * ((size_t)fs[c]->np * Ss[c] * es + 256);
+    auto s16 = [](int S) { return (size_t)((S + 15) & ~15); };
+    for (int c = 0; c < n; ++c) buf += 5 * ((size_t)fs[c]->np * s16(Ss[c]) * es + 256);
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
@@ -387,7 +355,7 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     };
     for (int c = 0; c < n; ++c) {
         const helm_factor_s* f = fs[c];
-        const size_t yb = (size_t)f->np * Ss[c] * es;
+        const size_t yb = (size_t)f->np * s16(Ss[c]) * es;
         const int nz = f->g.nz, k = twist_row(nz);
         const bool bottom = k < nz - 1;
         const int top = nf;
@@ -428,26 +396,23 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
             groups += sweep_row_tiles(f->np);
             st_max = std::max(st_max, si.tiles_s);
             si.itile0 = itot;
-            itot += (int)(((int64_t)f->np * Ss[c] + 255) / 256);
+            itot += (int)(((int64_t)f->np * (int64_t)s16(Ss[c]) + 255) / 256);
             fsteps = std::max(fsteps, si.nfwd);
             bsteps = std::max(bsteps, si.nbwd);
         }
         g_solves += Ss[c];
     }
-    SweepInfo* dtab;
-    if ((rc = sc.get(&dtab, sizeof(SweepInfo) * MAXB))) return rc;
-    if ((rc = g_ring.upload(dtab, tab.data(), sizeof(SweepInfo) * MAXB, st))) return rc;
-    launch_sweep_init(dtab, nf, itot, fp32, conj_b, st);
+    launch_sweep_init(stab, nf, itot, fp32, conj_b, st);
     {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < fsteps; ++t) launch_sweep(dtab, nf, t, groups, st_max, fp32, true, conj_b, st);
+        for (int t = 0; t < fsteps; ++t) launch_sweep(stab, nf, t, groups, st_max, fp32, true, conj_b, st);
         if (tm) g_timer.end(p, fsteps, st);
     }
     if (bsteps > 0) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < bsteps; ++t) launch_sweep(dtab, nf, t, groups, st_max, fp32, false, false, st);
+        for (int t = 0; t < bsteps; ++t) launch_sweep(stab, nf, t, groups, st_max, fp32, false, false, st);
         if (tm) g_timer.end(p, bsteps, st);
     }
     g_launches += 1 + (int64_t)fsteps + bsteps;

@@ -22,12 +22,13 @@ struct Coef {
 // up rows nz-1, nz-2, .., k+1, each forming D_next = A_next - E G E.  The
 // bottom front finishes earlier and leaves A_k - E G_{k+1} E in a merge
 // block, which the top front uses in place of A_k when it forms D_k, so
-// G_k is the inverse of the full Schur complement at row k.  The table lives
-// in device memory; the launch for global step t makes every front with
+// G_k is the inverse of the full Schur complement at row k.  The launch for
+// global step t makes every front with
 // t < T do panel p = t % npan of its block jl = t / npan (grid row
 // row0 + dir * jl).
 struct ChainInfo {
-    void* G;        // nz blocks of np x np row-major complex; block j ends as its Schur inverse
+    void* G;        // nz blocks of np x np complex: D_j row-major while block j is
+                    // factored, then its inverse G_j in the A-operand layout (a_tiled)
     void* P0;       // ping-pong working blocks (np x np) between panel steps
     void* P1;
     void* Tb;       // two KB x KB slots holding the inverted diagonal tile,
@@ -43,6 +44,19 @@ struct ChainInfo {
     int itile0;             // first workgroup in the initial launch
 };
 
+// Matrix-core operand layouts of the sweep data.  A factor block G_j (np x np)
+// is stored as 16 x 4 tiles, each the A operand of one 16x16x4 MFMA step in
+// lane order (lane l = 16 g + r holds row 16 I + r, column 4 K + g):
+__host__ __device__ inline size_t a_tiled(int row, int col, int np) {
+    return ((size_t)(row >> 4) * (np >> 2) + (col >> 2)) * 64 + (col & 3) * 16 + (row & 15);
+}
+// and a block of coupling vectors (np rows x S columns, S padded to 16) as
+// 4 x 16 tiles, each the B operand of one step (lane 16 g + r holds row
+// 4 K + g, column 16 T + r):
+__host__ __device__ inline size_t b_tiled(int row, int col, int np) {
+    return ((size_t)(col >> 4) * (np >> 2) + (row >> 2)) * 64 + (row & 3) * 16 + (col & 15);
+}
+
 // Row k at which the two fronts of an nz-row system meet (the top front ends
 // there), or nz - 1 when there is no bottom front.  The bottom front has
 // nz - 1 - k < k blocks, so it ends at least one launch before the top front
@@ -56,7 +70,7 @@ __host__ __device__ inline int twist_row(int nz) {
 // coupling vector y_{j+dir} = b_{j+dir} - E w_j; backward: x_j = w_j - G_j z_j
 // and z_{j-dir} = E x_j.  Coupling vectors are produced by the workgroups
 // that compute the rows they depend on and kept in two ping-pong buffers of
-// np x S (column-major, leading dimension np, zero below nx).  With a bottom
+// np x S16 in the B-operand layout (b_tiled; zero below nx).  With a bottom
 // front, its last forward step leaves b_k - E w_{k+1} in `Mout`, which the
 // top front reads in place of b_k; the top front's last forward step gives
 // x_k and starts both backward sweeps with E x_k (its own buffer and `Zp`).
@@ -78,17 +92,28 @@ struct SweepInfo {
     int itile0;             // first workgroup of the initial launch
 };
 
+// The per-front tables travel as kernel arguments (by value), so a
+// workgroup finds its front and reads its fields without a dependent load
+// through a device pointer.
+struct ChainTab {
+    ChainInfo c[MAXB];
+};
+struct SweepTab {
+    SweepInfo c[MAXB];
+};
+static_assert(sizeof(ChainTab) <= 3072 && sizeof(SweepTab) <= 3072, "kernel argument tables too large");
+
 // workgroups per chain of the factorisation launches
 int factor_init_blocks(int np);
 int factor_step_blocks(int np);
-void launch_factor_init(const ChainInfo* tab, int n, int total_blocks, bool fp32, hipStream_t st);
-void launch_factor_step(const ChainInfo* tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
+void launch_factor_init(const ChainTab& tab, int n, int total_blocks, bool fp32, hipStream_t st);
+void launch_factor_step(const ChainTab& tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
 // y = b_{row0} (conjugated for adjoint solves) into Y0 of every front
-void launch_sweep_init(const SweepInfo* tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
+void launch_sweep_init(const SweepTab& tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
 // forward step t: row row0 + dir * t of each front; backward step t: row
 // brow0 - dir * t.  `groups` row tiles (16 rows) over all fronts, `st` column
 // tiles (16 columns).
-void launch_sweep(const SweepInfo* tab, int n, int t, int groups, int st, bool fp32, bool forward,
+void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp32, bool forward,
                   bool conj_b, hipStream_t st_);
 int sweep_row_tiles(int np);
 int sweep_col_tiles(int S);

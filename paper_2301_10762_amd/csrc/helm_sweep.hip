@@ -13,12 +13,13 @@
 
 namespace helm {
 
-constexpr int SW_TILE_S = 16;
-constexpr int SW_WAVES = 8;
+constexpr int SW_WAVES = 4;
+constexpr int SW_CTG = 1;     // 16-column tiles per workgroup (the waves split them, then K)
+constexpr int SW_DEPTH = 4;   // 16-wide K chunks in flight per wave
 
 int sweep_row_tiles(int np) { return np / 16; }
-int sweep_col_tiles(int S) { return (S + SW_TILE_S - 1) / SW_TILE_S; }
-int sweep_grid(int groups, int st) { return 8 * ((groups + 7) / 8) * st; }
+int sweep_col_tiles(int S) { return ((S + 15) / 16 + SW_CTG - 1) / SW_CTG; }
+int sweep_grid(int groups, int cgroups) { return 8 * ((groups + 7) / 8) * cgroups; }
 
 template <typename C>
 __device__ __forceinline__ C conj_if(C v, bool c) {
@@ -26,146 +27,187 @@ __device__ __forceinline__ C conj_if(C v, bool c) {
     return v;
 }
 
-// y = b_{row0} (rows >= nx zero)
+// y = b_{row0} into Y0 (B-operand layout; rows >= nx and columns >= S zero)
 template <typename T, bool CONJB>
-__global__ __launch_bounds__(256) void k_sweep_init(const SweepInfo* tab, int n) {
+__global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
     using C = typename CT<T>::c;
-    const int ci = find_chain(tab, n, blockIdx.x, [](const SweepInfo& c) { return c.itile0; });
-    const SweepInfo& d = tab[ci];
+    const int ci = find_chain(tab.c, n, blockIdx.x, [](const SweepInfo& c) { return c.itile0; });
+    const SweepInfo d = tab.c[ci];
+    const int s16 = (d.S + 15) & ~15;
     const int64_t e = (int64_t)(blockIdx.x - d.itile0) * 256 + threadIdx.x;
-    if (e >= (int64_t)d.np * d.S) return;
+    if (e >= (int64_t)d.np * s16) return;
     const int s = (int)(e / d.np), k = (int)(e % d.np);
     C v = mk<C>(0.0, 0.0);
-    if (k < d.nx) v = conj_if(((const C*)d.B)[(size_t)s * d.ldb + (size_t)d.row0 * d.nx + k], CONJB);
-    ((C*)d.Y0)[e] = v;
+    if (k < d.nx && s < d.S)
+        v = conj_if(gld((const C*)d.B + (size_t)s * d.ldb + (size_t)d.row0 * d.nx + k), CONJB);
+    gst((C*)d.Y0 + b_tiled(k, s, d.np), v);
 }
 
-// Workgroups are numbered so that the column tiles of one row tile run on
-// the same XCD (consecutive workgroups go to consecutive XCDs): the rows of
-// G_j they share are then read once into that XCD's L2.
+// One workgroup per 16-row tile of a front's block row and group of SW_CTG
+// 16-column tiles of the right-hand sides: the product G_j(rows) Y(columns)
+// on the matrix cores, four real products per complex one in separate
+// accumulators.  The waves share out the column tiles and split the
+// contraction; the parts are summed in a fixed order through LDS.  Each wave
+// streams its operands with SW_DEPTH chunks of 16 in flight, and several
+// workgroups per compute unit hide the rest of the latency.  Workgroups are
+// numbered so that the column tiles of one row tile run on the same XCD
+// (consecutive workgroups go to consecutive XCDs) and share its L2.
 template <typename T, bool FWD, bool CONJB>
-__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepInfo* tab, int n, int tstep, int groups,
-                                                        int st) {
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int n, int tstep, int groups,
+                                                        int cgroups) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     __shared__ T red[SW_WAVES][2][4][64];
     const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
-    const int g = (slot / st) * 8 + xcd, sidx = slot % st;
+    const int g = (slot / cgroups) * 8 + xcd, cgi = slot % cgroups;
     if (g >= groups) return;
-    const int ci = find_chain(tab, n, g, [](const SweepInfo& c) { return c.tile0; });
-    const SweepInfo& d = tab[ci];
-    if (sidx >= d.tiles_s) return;
+    const int ci = find_chain(tab.c, n, g, [](const SweepInfo& c) { return c.tile0; });
+    const SweepInfo d = tab.c[ci];
     if (tstep >= (FWD ? d.nfwd : d.nbwd)) return;
-    const int j = FWD ? d.row0 + d.dir * tstep : d.brow0 - d.dir * tstep;
-    const int i0 = 16 * (g - d.tile0), s0 = SW_TILE_S * sidx;
+    const int nct = (d.S + 15) >> 4, ct0 = SW_CTG * cgi;
+    if (ct0 >= nct) return;
+    const int nctg = min(SW_CTG, nct - ct0);
+    const int P = 4 / nctg;                       // contraction parts per column tile
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
+    const int myct = w % nctg, part = w / nctg;
+    const bool active = part < P;
+    const int j = FWD ? d.row0 + d.dir * tstep : d.brow0 - d.dir * tstep;
+    const int i0 = 16 * (g - d.tile0);
     const int np = d.np, nx = d.nx;
-    const C* G = (const C*)d.G + (size_t)j * np * np + (size_t)(i0 + lr) * np;
+    // operand streams: this row tile of G_j and this column tile of Y, each
+    // 64 consecutive elements per MFMA step (the tiled layouts)
+    const C* Gt = (const C*)d.G + (size_t)j * np * np + (size_t)(i0 >> 4) * (np >> 2) * 64 + l;
     // steps of one front alternate the coupling buffers: forward step t is
     // step t, backward step t is step nfwd + t of the front
     const int u = FWD ? tstep : d.nfwd + tstep;
     const C* Yin = (const C*)((u & 1) ? d.Y1 : d.Y0);
     C* Yout = (C*)((u & 1) ? d.Y0 : d.Y1);
-    const int s = s0 + lr;
+    const int s = 16 * (ct0 + myct) + lr;
     const bool scol = s < d.S;
-    const C* y = Yin + (size_t)(scol ? s : 0) * np;
+    const C* Yt = Yin + (size_t)(ct0 + myct) * (np >> 2) * 64 + l;
 
-    // epilogue operands of wave 0 (next block's right-hand side, or this
-    // block's forward result), fetched before the contraction.  Forward:
-    // `more` - the front continues; else a bottom front hands its vector to
-    // the top front (Mout), and the top front's last step is x_k.
+    // epilogue operands (next block's right-hand side, or this block's
+    // forward result), fetched before the contraction.  Forward: `more` -
+    // the front continues; else a bottom front hands its vector to the top
+    // front (Mout), and the top front's last step is x_k.
     const C* Bv = (const C*)d.B;
     C* X = (C*)d.X;
     const bool more = FWD && tstep + 1 < d.nfwd;
     const bool merge_in = more && d.Bm && tstep + 2 == d.nfwd;
     const bool hand_over = FWD && !more && d.Mout;
+    const bool lead = active && part == 0;
     C pre[4];
-    if (w == 0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = i0 + acc_row<T>(lg, e);
-            pre[e] = mk<C>(0.0, 0.0);
-            if (scol && i < nx) {
-                if (FWD) {
-                    if (merge_in) pre[e] = ((const C*)d.Bm)[(size_t)s * np + i];
-                    else if (more || hand_over)
-                        pre[e] = conj_if(Bv[(size_t)s * d.ldb + (size_t)(j + d.dir) * nx + i], CONJB);
-                } else {
-                    pre[e] = X[(size_t)s * d.ldx + (size_t)j * nx + i];
-                }
+    for (int e = 0; e < 4; ++e) {
+        const int i = i0 + acc_row<T>(lg, e);
+        pre[e] = mk<C>(0.0, 0.0);
+        if (lead && scol && i < nx) {
+            if (FWD) {
+                if (merge_in) pre[e] = gld((const C*)d.Bm + b_tiled(i, s, np));
+                else if (more || hand_over)
+                    pre[e] = conj_if(gld(Bv + (size_t)s * d.ldb + (size_t)(j + d.dir) * nx + i), CONJB);
+            } else {
+                pre[e] = gld(X + (size_t)s * d.ldx + (size_t)j * nx + i);
             }
         }
     }
 
-    V cr, cim;
+    V rr, ii, ri, ir;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { cr[e] = 0; cim[e] = 0; }
-    // this wave's 16-column chunks of the contraction: w, w + W, w + 2W, ...;
-    // two chunks' operands are loaded before they are multiplied.  In MFMA
-    // step q, lane group g carries k = 16 ch + 4 q + g, so each load
-    // instruction reads 64 contiguous bytes per four lanes.
-    const int nch = np / 16;
-    for (int base = w; base < nch; base += 2 * SW_WAVES) {
-        C ga[2][4], ya[2][4];
+    for (int e = 0; e < 4; ++e) { rr[e] = 0; ii[e] = 0; ri[e] = 0; ir[e] = 0; }
+    // this wave's chunks of 16 in the contraction; in MFMA step q lane group
+    // lg carries k = 16 ch + 4 q + lg.  Loads are unconditional (chunk index
+    // clamped, tail chunks zeroed) so the waits count exactly SW_DEPTH
+    // chunks in flight.
+    const int nch = np >> 4;
+    const int c_beg = active ? part * nch / P : 0, c_end = active ? (part + 1) * nch / P : 0;
+    const int cnt = c_end - c_beg;
+    C ga[SW_DEPTH][4], ya[SW_DEPTH][4];
+    auto load = [&](C (&gq)[4], C (&yq)[4], int c) {
+        const int cc = min(c, c_end - 1);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int ch = base + c * SW_WAVES;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = 16 * ch + 4 * q + lg;
-                ga[c][q] = ch < nch ? G[k] : mk<C>(0.0, 0.0);
-                ya[c][q] = (ch < nch && scol) ? y[k] : mk<C>(0.0, 0.0);
-            }
+        for (int q = 0; q < 4; ++q) {
+            const size_t o = (size_t)(4 * cc + q) * 64;
+            gq[q] = gld(Gt + o);
+            yq[q] = gld(Yt + o);
         }
+    };
+    if (cnt > 0) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if (base + c * SW_WAVES < nch) {
+        for (int v = 0; v < SW_DEPTH; ++v) load(ga[v], ya[v], c_beg + v);
+        for (int c0 = c_beg; c0 < c_end; c0 += SW_DEPTH) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) cmfma<T, V>(cr, cim, ga[c][q].x, ga[c][q].y, ya[c][q].x, ya[c][q].y);
+            for (int v = 0; v < SW_DEPTH; ++v) {
+                const bool live = c0 + v < c_end;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T yr = live ? ya[v][q].x : (T)0, yi = live ? ya[v][q].y : (T)0;
+                    rr = mfma16(ga[v][q].x, yr, rr);
+                    ii = mfma16(ga[v][q].y, yi, ii);
+                    ri = mfma16(ga[v][q].x, yi, ri);
+                    ir = mfma16(ga[v][q].y, yr, ir);
+                }
+                load(ga[v], ya[v], c0 + v + SW_DEPTH);
             }
         }
     }
+    T sre[4], sim[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { red[w][0][e][l] = cr[e]; red[w][1][e][l] = cim[e]; }
-    __syncthreads();
-    if (w != 0 || !scol) return;
+    for (int e = 0; e < 4; ++e) {
+        sre[e] = rr[e] - ii[e];
+        sim[e] = ri[e] + ir[e];
+    }
+    if (P > 1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { red[w][0][e][l] = sre[e]; red[w][1][e][l] = sim[e]; }
+        __syncthreads();
+        if (!lead) return;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            sre[e] = red[myct][0][e][l];
+            sim[e] = red[myct][1][e][l];
+            for (int q = 1; q < P; ++q) {
+                sre[e] += red[myct + nctg * q][0][e][l];
+                sim[e] += red[myct + nctg * q][1][e][l];
+            }
+        }
+    }
+    if (!lead || !scol) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int i = i0 + acc_row<T>(lg, e);
-        T sr = red[0][0][e][l], si = red[0][1][e][l];
-#pragma unroll
-        for (int q = 1; q < SW_WAVES; ++q) { sr += red[q][0][e][l]; si += red[q][1][e][l]; }
+        const T sr = sre[e], si = sim[e];
         const T ei = (T)(i >= nx ? 0.0 : ((i == 0 || i == nx - 1) ? -0.5 * d.cz : -d.cz));
         C nxt = mk<C>(0.0, 0.0);
         if (FWD) {
             // w_j; the next step's y_{j+dir} = b_{j+dir} - E w_j; at the end
             // of a bottom front that vector goes to the top front, and at the
             // end of a top front (w_j = x_j) both backward sweeps start with E x_j
-            if (i < nx) X[(size_t)s * d.ldx + (size_t)j * nx + i] = mk<C>(sr, si);
+            if (i < nx) gst(X + (size_t)s * d.ldx + (size_t)j * nx + i, mk<C>(sr, si));
             if (more || hand_over) {
                 if (i < nx) nxt = mk<C>(pre[e].x - ei * sr, pre[e].y - ei * si);
                 if (hand_over) {
-                    ((C*)d.Mout)[(size_t)s * np + i] = nxt;
+                    gst((C*)d.Mout + b_tiled(i, s, np), nxt);
                     continue;
                 }
             } else {
                 nxt = mk<C>(ei * sr, ei * si);
-                if (d.Zp) ((C*)d.Zp)[(size_t)s * np + i] = nxt;
+                if (d.Zp) gst((C*)d.Zp + b_tiled(i, s, np), nxt);
             }
         } else {
             // x_j = w_j - G_j z_j; the next step's z = E x_j
             if (i < nx) {
                 const C xn = mk<C>(pre[e].x - sr, pre[e].y - si);
-                X[(size_t)s * d.ldx + (size_t)j * nx + i] = xn;
+                gst(X + (size_t)s * d.ldx + (size_t)j * nx + i, xn);
                 nxt = mk<C>(ei * xn.x, ei * xn.y);
             }
         }
-        Yout[(size_t)s * np + i] = nxt;
+        gst(Yout + b_tiled(i, s, np), nxt);
     }
 }
 
-void launch_sweep_init(const SweepInfo* tab, int n, int total, bool fp32, bool conj_b, hipStream_t st) {
+void launch_sweep_init(const SweepTab& tab, int n, int total, bool fp32, bool conj_b, hipStream_t st) {
     if (fp32) {
         if (conj_b) hipLaunchKernelGGL((k_sweep_init<float, true>), dim3(total), dim3(256), 0, st, tab, n);
         else hipLaunchKernelGGL((k_sweep_init<float, false>), dim3(total), dim3(256), 0, st, tab, n);
@@ -175,7 +217,7 @@ void launch_sweep_init(const SweepInfo* tab, int n, int total, bool fp32, bool c
     }
 }
 
-void launch_sweep(const SweepInfo* tab, int n, int t, int groups, int st, bool fp32, bool forward, bool conj_b,
+void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp32, bool forward, bool conj_b,
                   hipStream_t st_) {
     const dim3 grid(sweep_grid(groups, st)), block(64 * SW_WAVES);
     if (fp32) {
