@@ -330,9 +330,12 @@ __device__ __forceinline__ void report_zero_pivot(int* status, int block, int ro
 // ----------------------------------------------------------------- launches --
 // LDS of a step workgroup: update tiles use sW, sV (64 x 33 each); the
 // next-tile workgroup four 32 x 33 blocks and the pivoting scratch
-constexpr size_t SM_UPDATE = 2 * 64 * 33 * sizeof(double2);
-constexpr size_t SM_NEXT = 4 * 32 * 33 * sizeof(double2) + sizeof(GJScratch<double>);
-constexpr size_t SM_BYTES_D = SM_UPDATE > SM_NEXT ? SM_UPDATE : SM_NEXT;
+template <typename T>
+constexpr size_t sm_bytes() {
+    using C = typename CT<T>::c;
+    constexpr size_t upd = 2 * 64 * 33 * sizeof(C), nxt = 4 * 32 * 33 * sizeof(C) + sizeof(GJScratch<T>);
+    return upd > nxt ? upd : nxt;
+}
 
 __host__ __device__ int init_blocks(int np) { return (int)(((int64_t)np * np + 255) / 256) + 1; }
 __host__ __device__ int step_blocks(int np) {
@@ -411,57 +414,61 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     GJScratch<T>& sh = *(GJScratch<T>*)(smem + 4 * 32 * 33 * sizeof(C));
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
     const bool single = ps.last_panel && d.npan == 1;   // next tile is Y = T itself
+    const int w = t >> 6, l = t & 63, lr = l & 15, lg = l >> 4;
+    const int wr = w >> 1, wc = w & 1;   // this wave's 16 x 16 output tile of the products
+    // T arrives transposed (Tt[c][k]): read it in order, place it as sT[k][c]
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int idx = t + 256 * i;
-        const int rr = idx >> 5, cc = idx & 31;
-        sT[rr][cc] = (rr < kb && cc < kb) ? Tcur[cc * KB + rr] : mk<C>(0.0, 0.0);
+        const int hi = idx >> 5, lo = idx & 31;
+        sT[lo][hi] = (hi < kb && lo < kb) ? gld(Tcur + idx) : mk<C>(0.0, 0.0);
         if (!single) {
-            sXa[rr][cc] = (rr < kbn && cc < kb) ? X[(size_t)(kn0 + rr) * np + k0 + cc] : mk<C>(0.0, 0.0);
-            sXb[rr][cc] = (rr < kb && cc < kbn) ? X[(size_t)(k0 + rr) * np + kn0 + cc] : mk<C>(0.0, 0.0);
+            sXa[hi][lo] = (hi < kbn && lo < kb) ? gld(X + (size_t)(kn0 + hi) * np + k0 + lo) : mk<C>(0.0, 0.0);
+            sXb[hi][lo] = (hi < kb && lo < kbn) ? gld(X + (size_t)(k0 + hi) * np + kn0 + lo) : mk<C>(0.0, 0.0);
         }
+    }
+    // X_{K'K'} in the accumulator layout of this wave's tile
+    using V = typename CT<T>::v4;
+    V zr, zi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
+        const C v = (!single && rr < kbn && cc < kbn) ? gld(X + (size_t)(kn0 + rr) * np + kn0 + cc) : mk<C>(0.0, 0.0);
+        zr[e] = v.x;
+        zi[e] = v.y;
     }
     C a[4];
     const bool act = (r < kbn) && (4 * cg < kbn);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        a[e] = (act && !single) ? X[(size_t)(kn0 + r) * np + kn0 + 4 * cg + e] : mk<C>(0.0, 0.0);
     __syncthreads();
     if (single) {
-        if (act) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = sT[r][4 * cg + e];
-        }
+        for (int e = 0; e < 4; ++e) a[e] = act ? sT[r][4 * cg + e] : mk<C>(0.0, 0.0);
     } else {
-        // P = X_{K'K} T
-        if (r < kbn && 4 * cg < kb) {
+        // P = X_{K'K} T on the matrix cores (zero padding beyond kb, kbn)
+        V pr, pim;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = 4 * cg + e;
-                T sr = 0, si = 0;
-                for (int k = 0; k < kb; ++k) {
-                    const C x = sXa[r][k], y = sT[k][c];
-                    sr += x.x * y.x - x.y * y.y;
-                    si += x.x * y.y + x.y * y.x;
-                }
-                sP[r][c] = mk<C>(sr, si);
-            }
+        for (int e = 0; e < 4; ++e) { pr[e] = 0; pim[e] = 0; }
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+            const C x = sXa[16 * wr + lr][4 * s8 + lg], y = sT[4 * s8 + lg][16 * wc + lr];
+            cmfma<T, V>(pr, pim, x.x, x.y, y.x, y.y);
         }
+        // -P into sP (accumulator layout -> row-major)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sP[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(-pr[e], -pim[e]);
         __syncthreads();
         // Z = X_{K'K'} - P X_{KK'}
-        if (act) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = 4 * cg + e;
-                T sr = 0, si = 0;
-                for (int k = 0; k < kb; ++k) {
-                    const C x = sP[r][k], y = sXb[k][c];
-                    sr += x.x * y.x - x.y * y.y;
-                    si += x.x * y.y + x.y * y.x;
-                }
-                a[e] = mk<C>(a[e].x - sr, a[e].y - si);
-            }
+        for (int s8 = 0; s8 < 8; ++s8) {
+            const C x = sP[16 * wr + lr][4 * s8 + lg], y = sXb[4 * s8 + lg][16 * wc + lr];
+            cmfma<T, V>(zr, zi, x.x, x.y, y.x, y.y);
         }
+        // to the Gauss-Jordan layout through sXa (no longer read)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sXa[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(zr[e], zi[e]);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = act ? sXa[r][4 * cg + e] : mk<C>(0.0, 0.0);
     }
     if (ps.last_panel && act) {
         // Schur complement of the next block: A_{j+1} - E G_j E on this tile
@@ -510,7 +517,30 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         vr[q] = R[q] < np;
         vc[q] = Cc[q] < np;
     }
-    // 1. this tile of X' (loads issued first)
+    // 1. global loads, all issued up front: X_{I,K} (rows of this tile, panel
+    //    columns) and T for the W product, V_J = X_{K,J} for the update (kept
+    //    in registers until W is done), and this tile of X'
+    C (*sT)[33] = sV;   // T shares the V buffer until W is formed
+    C xik[8], tv[4], vv[8];
+    {
+        const int rr = t >> 2, c8 = 8 * (t & 3), row = I0 + rr;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = c8 + q;
+            xik[q] = (row < np && c < kb) ? gld(X + (size_t)row * np + k0 + c) : mk<C>(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tv[q] = gld(Tcur + t + 256 * q);   // Tt[c][k], idx = 32 c + k
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = t + 256 * q, k = i >> 6, cc = i & 63, col = J0 + cc;
+            C v = mk<C>(0.0, 0.0);
+            if (k < kb && col < np)
+                v = (col >= k0 && col < k0 + kb) ? mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0)
+                                                 : gld(X + (size_t)(k0 + k) * np + col);
+            vv[q] = v;
+        }
+    }
     V accr[2][2], acci[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -524,51 +554,67 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int row = R[bi] + acc_row<T>(lg, e);
-                    const C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : X[(size_t)row * np + col];
+                    const C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : gld(X + (size_t)row * np + col);
                     accr[bi][bj][e] = v.x;
                     acci[bi][bj][e] = v.y;
                 }
             }
         }
-    // 2. V_J into LDS (transposed), V_KK = I
-    for (int i = t; i < kb * TILE; i += 256) {
-        const int k = i >> 6, cc = i & 63, col = J0 + cc;
-        C v = mk<C>(0.0, 0.0);
-        if (col < np) v = (col >= k0 && col < k0 + kb) ? mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0)
-                                                       : X[(size_t)(k0 + k) * np + col];
-        sV[cc][k] = v;
+    // 2. X_{I,K} and T into LDS
+    {
+        const int rr = t >> 2, c8 = 8 * (t & 3);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = xik[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = t + 256 * q, c = i >> 5, k = i & 31;
+            sT[k][c] = (k < kb && c < kb) ? tv[q] : mk<C>(0.0, 0.0);
+        }
     }
+    __syncthreads();
     // 3. W_I = -X_{I,K} T (matrix cores; wave w makes rows I0+16w .. +15), T - I on rows of K
     {
-        const int row0 = I0 + 16 * w;
-        if (row0 < np) {
-            for (int cb = 0; cb < kb / 16; ++cb) {
-                V wr_, wi_;
+        V wre[2], wim[2];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) { wr_[e] = 0; wi_[e] = 0; }
-                for (int kk = 0; kk < kb; kk += 16) {
-                    C av[4], bv[4];
+        for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        av[q] = X[(size_t)(row0 + lr) * np + k0 + kk + 4 * lg + q];
-                        bv[q] = Tcur[(cb * 16 + lr) * KB + kk + 4 * lg + q];
-                    }
+            for (int e = 0; e < 4; ++e) { wre[cb][e] = 0; wim[cb][e] = 0; }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) cmfma<T, V>(wr_, wi_, av[q].x, av[q].y, bv[q].x, bv[q].y);
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int rl = 16 * w + acc_row<T>(lg, e), row = I0 + rl, c = cb * 16 + lr;
-                    C v;
-                    if (row >= k0 && row < k0 + kb) {
-                        v = Tcur[c * KB + (row - k0)];
-                        if (row - k0 == c) v.x -= (T)1;
-                    } else {
-                        v = mk<C>(-wr_[e], -wi_[e]);
-                    }
-                    sW[rl][c] = v;
-                }
+            for (int s8 = 0; s8 < 8; ++s8) {
+                const int k = 4 * s8 + lg;
+                const C av = sW[16 * w + lr][k], bv = sT[k][cb * 16 + lr];
+                cmfma<T, V>(wre[cb], wim[cb], av.x, av.y, bv.x, bv.y);
             }
+        }
+        C tk[2][4];   // rows of K: T - I, read before the buffers are rewritten
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = I0 + 16 * w + acc_row<T>(lg, e), c = cb * 16 + lr;
+                tk[cb][e] = (row >= k0 && row < k0 + kb) ? sT[row - k0][c] : mk<C>(0.0, 0.0);
+            }
+        __syncthreads();   // every wave has read X_{I,K} and T
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rl = 16 * w + acc_row<T>(lg, e), row = I0 + rl, c = cb * 16 + lr;
+                C v;
+                if (row >= k0 && row < k0 + kb) {
+                    v = tk[cb][e];
+                    if (row - k0 == c) v.x -= (T)1;
+                } else {
+                    v = mk<C>(-wre[cb][e], -wim[cb][e]);
+                }
+                sW[rl][c] = v;
+            }
+        }
+        // V_J into LDS, transposed (V_KK = I)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = t + 256 * q, k = i >> 6, cc = i & 63;
+            sV[cc][k] = vv[q];
         }
     }
     __syncthreads();
@@ -637,7 +683,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 template <typename T>
 __global__ __launch_bounds__(256) void k_factor_step(const ChainTab tab, int n, int tstep) {
     using C = typename CT<T>::c;
-    __shared__ __attribute__((aligned(16))) char smem[SM_BYTES_D];
+    __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
     const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
     const ChainInfo d = tab.c[ci];
     if (tstep >= d.T) return;
