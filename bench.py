@@ -156,23 +156,21 @@ def main():
     value = solves / total
     ms_per_step = total / args.steps * 1e3
 
-    # roofline of the dominant kernel, k_factor_step (one Gauss-Jordan panel
-    # step of every chain: rank-32 block update on the matrix cores plus the
-    # next diagonal tile).  Algorithmic work: the block factorisation's
-    # canonical count 8 * (4/3) * n_z * n_x^3 flops per frequency, spread
-    # evenly over its n_z * ceil(np/32) step launches; one launch serves all
-    # five frequencies.
+    # roofline of the dominant kernel: the factorisation (one persistent
+    # launch k_factor_persist per group of systems, or one k_factor_step
+    # launch per panel step).  Algorithmic work: the block factorisation's
+    # canonical count 8 * (4/3) * n_z * n_x^3 flops per frequency; the timed
+    # region factors all five frequencies once per step.
     nx, nz = w.nx, w.nz
-    np_ = (nx + 15) // 16 * 16
-    npan = (np_ + 31) // 32
-    flops_per_launch = n_omega * 8.0 * (4.0 / 3.0) * nx ** 3 / npan
+    factor_flops = args.steps * n_omega * 8.0 * (4.0 / 3.0) * nz * nx ** 3
     upd_ms, upd_n = kt.get("factor_step", (0.0, 0))
+    flops_per_launch = factor_flops / upd_n if upd_n else float("nan")
     avg_upd_s = upd_ms / upd_n * 1e-3 if upd_n else float("nan")
     achieved = flops_per_launch / avg_upd_s / 1e12
     traffic = read_traffic(prec)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
-                "kernel": "k_factor_step (Gauss-Jordan panel step, 5 chains per launch)",
+                "kernel": "factorisation of the five frequencies (k_factor_persist: one launch; else k_factor_step per panel step)",
                 "avg_launch_us": round(avg_upd_s * 1e6, 2), "timed_launches": upd_n,
                 "flops_per_launch": flops_per_launch}
     kernels = {}

@@ -89,6 +89,10 @@ int helm_factor_batch(int32_t count, const helm_grid* grids, const double* const
 /* Bytes of HBM a factor of this grid and precision holds (for admission). */
 int helm_factor_bytes(const helm_grid* grid, int precision, size_t* bytes);
 
+/* Releases a factor.  Its device memory goes back to the device's
+ * stream-ordered pool in the order of the stream the factor was made on, so
+ * work on other streams that uses the factor must be complete before the
+ * call.  NULL is ignored. */
 void helm_factor_destroy(helm_factor_t f);
 
 /* ---- solves ----------------------------------------------------------------
@@ -165,6 +169,17 @@ int helm_tile_inverse(int32_t count, int32_t kb, int pivot, const double* A_dev,
  * start for every later factorisation (process-wide).                      */
 void helm_set_tile_pivoting(int always);
 
+/* Factorisation schedule (process-wide).  persistent = 0 (default): one
+ * launch per panel step.  persistent = 1: one launch per group of systems in
+ * which every workgroup stays resident, keeps its tile in registers and
+ * exchanges panel data with the other workgroups of its front through
+ * memory (device-scope accesses), used when the device can hold all of them
+ * at once (else, or if a workgroup's wait ever times out, the group is
+ * factored with one launch per panel step).  Both give bitwise the same
+ * factors; on MI355X the per-step launches are faster at 401^2 (the
+ * exchanged panels cannot stay in the non-coherent L2). */
+void helm_set_factor_path(int persistent);
+
 /* Lane-layout check of the matrix-core instruction used by the kernels:
  * D = A(16x4) * B(4x16) in FP64 (prec 0) or FP32 (prec 1) on one wavefront. */
 int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* D_dev, void* stream);
@@ -180,8 +195,12 @@ int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* 
 void helm_kernel_timing(int enable);
 int helm_kernel_time(int kind, double* total_ms, int64_t* count);
 
-/* Number of kernel launches and right-hand-side solves issued since load. */
-int64_t helm_counter(int which);   /* 0 = launches, 1 = solves */
+/* Counters since load: 0 = kernel launches, 1 = right-hand-side solves,
+ * 2 = persistent factorisations redone one launch per step because a wait
+ * timed out, 3 = the code of the last such wait (bit 30 set; bit 20: the
+ * next-tile workgroup; bit 16: the merge-block wait; low 16 bits: the step),
+ * -1 for an unknown index. */
+int64_t helm_counter(int which);
 
 const char* helm_last_error(void);
 

@@ -25,12 +25,14 @@ struct helm_factor_s {
     void* G;       // nz * np * np complex (16 B for FP64, 8 B for FP32)
     double* m;     // device copy of the model
     size_t bytes;
+    hipStream_t st;   // the stream it was made on (its memory is freed there)
 };
 
 namespace {
 
 thread_local std::string g_err;
 std::atomic<int64_t> g_launches{0}, g_solves{0};
+std::atomic<int64_t> g_persist_fallbacks{0}, g_persist_last_err{0};
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -65,6 +67,21 @@ int check_grid(const helm_grid* g) {
 
 // stream-ordered scratch memory, released on scope exit (after the work that
 // uses it, in stream order)
+// Device memory of factors and scratch comes from the device's stream-ordered
+// pool, which keeps freed memory for reuse (so repeated factorisations do not
+// pay for fresh gigabyte allocations).
+void keep_pool_memory() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    });
+}
+
 struct Scratch {
     hipStream_t st;
     std::vector<void*> ptrs;
@@ -133,6 +150,7 @@ struct KernelTimer {
 };
 KernelTimer g_timer;
 int g_force_pivot = 0;   // 1: always invert diagonal tiles with partial pivoting
+int g_persist = 0;       // 1: one persistent launch per factorisation when every workgroup fits
 
 Coef coef_of(const helm_factor_s* f) {
     Coef c;
@@ -145,21 +163,23 @@ Coef coef_of(const helm_factor_s* f) {
     return c;
 }
 
-// m_k > 0 and finite for every node (m in R^M_+); synchronises
-int check_model(const double* m, int64_t n, hipStream_t st) {
+// m_k > 0 and finite for every node (m in R^M_+) of each of `count`
+// models; one synchronisation for all
+int check_models(int count, const double* const* ms, const int64_t* ns, hipStream_t st) {
     Scratch sc(st);
     int* flag;
     int rc = sc.get(&flag, sizeof(int));
     if (rc) return rc;
     launch_zero(flag, sizeof(int), st);
-    launch_check_model(m, n, flag, st);
-    g_launches += 2;
+    for (int c = 0; c < count; ++c) launch_check_model(ms[c], ns[c], flag, st);
+    g_launches += 1 + count;
     int h = 0;
     HIPCHECK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     if (h) return fail(HELM_EINVAL, "model must be finite and positive at every node");
     return HELM_OK;
 }
+int check_model(const double* m, int64_t n, hipStream_t st) { return check_models(1, &m, &n, st); }
 
 // ------------------------------------------------------------ factorisation --
 // Factor a group of at most MAXB / 2 systems of one precision in lockstep,
@@ -180,16 +200,22 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
     int utot = 0, itot = 0, Tmax = 0, nf = 0;
     size_t buf = 0;
+    int wgs = 0;
     for (int c = 0; c < n; ++c) {
-        const size_t n2 = (size_t)fs[c]->np * fs[c]->np;
-        buf += 2 * (2 * n2 + 2 * (size_t)KB * KB) * es + n2 * es + 5 * 256;
+        const size_t n2 = (size_t)fs[c]->np * fs[c]->np, npk = (size_t)fs[c]->np * KB;
+        buf += 2 * (2 * n2 + 2 * (size_t)KB * KB + 4 * npk + 2 * (size_t)KB * KB) * es + n2 * es + 14 * 256;
+        wgs += 2 * factor_step_blocks(fs[c]->np);
     }
+    // one persistent launch when every workgroup of the group can be resident
+    const bool persist = g_persist && wgs <= factor_persist_capacity(fp32);
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
     int* status;
-    if ((rc = sc.get(&status, sizeof(int) * 4 * 2 * n))) return rc;
-    launch_zero(status, sizeof(int) * 4 * 2 * n, st);
+    if ((rc = sc.get(&status, sizeof(int) * (4 * 2 * n + 2 * n + 1)))) return rc;
+    launch_zero(status, sizeof(int) * (4 * 2 * n + 2 * n + 1), st);
+    int* ctrs = status + 4 * 2 * n;     // per-front round counters (persistent path)
+    int* err = ctrs + 2 * n;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void* p = arena + off;
@@ -228,6 +254,16 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             }
             ci.T = ci.npan * ci.nblk;
             ci.pivot = pivot;
+            ci.PC = take(2 * (size_t)f->np * KB * es);
+            ci.PR = take(2 * (size_t)f->np * KB * es);
+            ci.DB = take(2 * (size_t)KB * KB * es);
+            ci.ctr = ctrs + nf;
+            if (side == 1) {
+                // the top front waits for the bottom front's last round before its merge block
+                ChainInfo& top = tab[nf - 1];
+                top.peer = ci.ctr;
+                top.peer_target = factor_step_blocks(f->np) * (ci.T + 1);
+            }
             ci.utile0 = utot;
             utot += factor_step_blocks(f->np);
             ci.itile0 = itot;
@@ -237,23 +273,40 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             ++nf;
         }
     }
-    {
-        KernelTimer::Pair pi;
-        const bool ti = g_timer.begin(1, st, &pi);
-        launch_factor_init(ctab, nf, itot, fp32, st);
-        if (ti) g_timer.end(pi, 1, st);
-    }
-    {
+    if (persist) {
+        KernelTimer::Pair pu;
+        const bool tu = g_timer.begin(0, st, &pu);
+        launch_factor_persist(ctab, nf, utot, fp32, err, st);
+        if (tu) g_timer.end(pu, 1, st);
+        g_launches += 1;
+    } else {
+        {
+            KernelTimer::Pair pi;
+            const bool ti = g_timer.begin(1, st, &pi);
+            launch_factor_init(ctab, nf, itot, fp32, st);
+            if (ti) g_timer.end(pi, 1, st);
+        }
         KernelTimer::Pair pu;
         const bool tu = g_timer.begin(0, st, &pu);
         for (int t = 0; t < Tmax; ++t) launch_factor_step(ctab, nf, t, utot, fp32, st);
         if (tu) g_timer.end(pu, Tmax, st);
+        g_launches += 1 + (int64_t)Tmax;
     }
-    g_launches += 2 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
-    std::vector<int> hs(4 * nf);
-    HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * 4 * nf, hipMemcpyDeviceToHost, st));
+    std::vector<int> hs(4 * 2 * n + 2 * n + 1);   // statuses (room for 2 fronts per system), counters, error word
+    HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
+    if (persist && hs[4 * 2 * n + 2 * n]) {
+        // a wait timed out (some workgroup never became resident): redo the
+        // group with one launch per step
+        g_persist_fallbacks += 1;
+        g_persist_last_err = hs[4 * 2 * n + 2 * n];
+        const int keep = g_persist;
+        g_persist = 0;
+        const int rc2 = factor_group(fs, n, pivot, st, needs_pivot);
+        g_persist = keep;
+        return rc2;
+    }
     for (int c = 0; c < nf; ++c)
         if (hs[4 * c])
             return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: system " + std::to_string(owner[c]) +
@@ -266,8 +319,8 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
 
 void destroy(helm_factor_s* f) {
     if (!f) return;
-    if (f->G) (void)hipFree(f->G);
-    if (f->m) (void)hipFree(f->m);
+    if (f->G) (void)hipFreeAsync(f->G, f->st);
+    if (f->m) (void)hipFreeAsync(f->m, f->st);
     delete f;
 }
 
@@ -275,13 +328,16 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
                 hipStream_t st, helm_factor_t* outs) {
     if (count <= 0 || !grids || !m_devs || !omegas || !outs) return fail(HELM_EINVAL, "bad batch arguments");
     if (prec != HELM_FP64 && prec != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
+    std::vector<int64_t> ns(count);
     for (int c = 0; c < count; ++c) {
         int rc = check_grid(&grids[c]);
         if (rc) return rc;
         if (!m_devs[c]) return fail(HELM_EINVAL, "model pointer is NULL");
         if (!std::isfinite(omegas[c]) || omegas[c] < 0.0) return fail(HELM_EINVAL, "omega must be finite and >= 0");
-        if ((rc = check_model(m_devs[c], N_of(grids[c]), st))) return rc;
+        ns[c] = N_of(grids[c]);
     }
+    if (int rc = check_models(count, m_devs, ns.data(), st)) return rc;
+    keep_pool_memory();
     std::vector<helm_factor_s*> fs(count, nullptr);
     auto cleanup = [&]() {
         for (auto* f : fs) destroy(f);
@@ -294,13 +350,14 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
         f->prec = prec;
         f->omega = omegas[c];
         f->bytes = factor_bytes_of(grids[c], prec);
+        f->st = st;
         size_t gb = (size_t)f->np * f->np * (size_t)grids[c].nz * elem_bytes(prec);
-        if (hipMalloc(&f->G, gb) != hipSuccess) {
+        if (hipMallocAsync(&f->G, gb, st) != hipSuccess) {
             f->G = nullptr;
             cleanup();
             return fail(HELM_ENOMEM, "factor allocation of " + std::to_string(gb) + " bytes failed");
         }
-        if (hipMalloc((void**)&f->m, sizeof(double) * N_of(grids[c])) != hipSuccess) {
+        if (hipMallocAsync((void**)&f->m, sizeof(double) * N_of(grids[c]), st) != hipSuccess) {
             f->m = nullptr;
             cleanup();
             return fail(HELM_ENOMEM, "model copy allocation failed");
@@ -642,9 +699,19 @@ extern "C" {
 
 const char* helm_last_error(void) { return g_err.c_str(); }
 
-int64_t helm_counter(int which) { return which == 0 ? g_launches.load() : g_solves.load(); }
+int64_t helm_counter(int which) {
+    switch (which) {
+        case 0: return g_launches.load();
+        case 1: return g_solves.load();
+        case 2: return g_persist_fallbacks.load();
+        case 3: return g_persist_last_err.load();
+        default: return -1;
+    }
+}
 
 void helm_set_tile_pivoting(int always) { g_force_pivot = always ? 1 : 0; }
+
+void helm_set_factor_path(int persistent) { g_persist = persistent ? 1 : 0; }
 
 void helm_kernel_timing(int enable) {
     g_timer.drain();

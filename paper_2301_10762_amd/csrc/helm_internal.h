@@ -36,6 +36,13 @@ struct ChainInfo {
     int* status;    // [0] zero-pivot flag, [1] block, [2] row, [3] small-pivot flag
     void* Aout;     // bottom front: receives A_next - E G E after its last block
     const void* Ain;   // top front: replaces A of its last block (the merge block)
+    // persistent path: the exchange between the front's workgroups
+    void* PC;       // panel columns, 2 x (np x 32)
+    void* PR;       // panel rows, 2 x (32 x np)
+    void* DB;       // next diagonal blocks, 2 x (32 x 32)
+    int* ctr;       // rounds completed by the front's workgroups
+    const int* peer;   // top front: the bottom front's counter (merge block ready at peer_target)
+    int peer_target;
     Coef cf;
     int np, npan, T;        // padded size, panels per block, steps (nblk * npan)
     int row0, dir, nblk;    // first grid row, +1 (down) or -1 (up), blocks of this front
@@ -101,13 +108,17 @@ struct ChainTab {
 struct SweepTab {
     SweepInfo c[MAXB];
 };
-static_assert(sizeof(ChainTab) <= 3072 && sizeof(SweepTab) <= 3072, "kernel argument tables too large");
+static_assert(sizeof(ChainTab) <= 4000 && sizeof(SweepTab) <= 4000, "kernel argument tables too large");
 
 // workgroups per chain of the factorisation launches
 int factor_init_blocks(int np);
 int factor_step_blocks(int np);
 void launch_factor_init(const ChainTab& tab, int n, int total_blocks, bool fp32, hipStream_t st);
 void launch_factor_step(const ChainTab& tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
+// the whole factorisation in one launch (every workgroup resident; see
+// factor_persist_capacity); *err is set if a workgroup's wait timed out
+void launch_factor_persist(const ChainTab& tab, int n, int total_blocks, bool fp32, int* err, hipStream_t st);
+int factor_persist_capacity(bool fp32);   // resident workgroups of the persistent kernel, 0 if unknown
 // y = b_{row0} (conjugated for adjoint solves) into Y0 of every front
 void launch_sweep_init(const SweepTab& tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
 // forward step t: row row0 + dir * t of each front; backward step t: row

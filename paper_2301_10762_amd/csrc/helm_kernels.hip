@@ -83,13 +83,30 @@ __global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const do
     }
 }
 
-__global__ void k_norms_finish(const double* partial, int nblk, int S, double* norms) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+// per column s: the sums of the per-block partials, one workgroup per
+// column, strided partial sums then a fixed-order tree in LDS
+__global__ __launch_bounds__(256) void k_norms_finish(const double* partial, int nblk, int S, double* norms) {
+    __shared__ double sa[256], sc[256];
+    const int s = blockIdx.x, t = threadIdx.x;
     double a = 0.0, c = 0.0;
-    for (int q = 0; q < nblk; ++q) { a += partial[((size_t)s * nblk + q) * 2]; c += partial[((size_t)s * nblk + q) * 2 + 1]; }
-    norms[2 * s] = a;
-    norms[2 * s + 1] = c;
+    for (int q = t; q < nblk; q += 256) {
+        a += partial[((size_t)s * nblk + q) * 2];
+        c += partial[((size_t)s * nblk + q) * 2 + 1];
+    }
+    sa[t] = a;
+    sc[t] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] += sa[t + h];
+            sc[t] += sc[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        norms[2 * s] = sa[0];
+        norms[2 * s + 1] = sc[0];
+    }
 }
 
 __global__ void k_c128_to_c64(const double2* src, int64_t lds, float2* dst, int64_t ldd, int64_t N, int conj) {
@@ -293,7 +310,7 @@ void launch_residual(const Coef& cf, int adjoint, const double* B, int64_t ldb, 
                        (const double2*)X, ldx, (double2*)R, ldr, (float2*)R32, S, partial, nblk);
 }
 void launch_norms_finish(const double* partial, int nblk, int S, double* norms, hipStream_t st) {
-    hipLaunchKernelGGL(k_norms_finish, grid1(S, 64), dim3(64), 0, st, partial, nblk, S, norms);
+    hipLaunchKernelGGL(k_norms_finish, dim3(S), dim3(256), 0, st, partial, nblk, S, norms);
 }
 void launch_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t N, int S, int conj,
                         hipStream_t st) {
