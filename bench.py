@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     p.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 comparison (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
     return p.parse_args()
@@ -187,6 +189,59 @@ def main():
                 "p50_ms": round(percentile(lat64, 0.5), 3), "p99_ms": round(percentile(lat64, 0.99), 3),
                 "max_relres": max(i.max_relres for i in inf64), "speedup_of_headline": round(value / v64, 3)}
 
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        # factor-only time of the five systems (headline precision)
+        tf = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Fs = helm.factor_batch([G] * n_omega, [m_dev] * n_omega, w.omegas, prec)
+            torch.cuda.synchronize()
+            tf.append(time.perf_counter() - t0)
+            for F in Fs:
+                F.close()
+        extras["factor_ms"] = round(min(tf) * 1e3, 3)
+        # forward + adjoint: phi and grad phi at the same workload (200
+        # receivers on the surface); the observations are this library's own
+        # forward data at the true model (an input for timing, not a check)
+        rec = w.receivers
+        Fs = helm.factor_batch([G] * n_omega, [torch.as_tensor(w.m_true, device="cuda")] * n_omega, w.omegas,
+                               "fp64")
+        Xt, _ = helm.solve_batch(Fs, [E] * n_omega, tol=TOL)
+        for F in Fs:
+            F.close()
+        ridx = torch.as_tensor(np.asarray(rec, dtype=np.int64), device="cuda")
+        d_obs = torch.stack([x[:, ridx] for x in Xt]).contiguous()
+        del Xt
+        helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            phi, grad, ginfo = helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / reps
+        extras["misfit_grad"] = {"ms": round(tg * 1e3, 3), "solves_per_s": round(2 * n_omega * S / tg, 2),
+                                 "solves": 2 * n_omega * S, "max_relres": ginfo.max_relres}
+        # Gauss-Newton Hessian-vector products: 201^2, 4 frequencies, 32
+        # sources, 100 receivers, 8 directions
+        w4 = I.config_c4()
+        G4 = helm.Grid.of(w4)
+        m4 = torch.as_tensor(w4.m, device="cuda")
+        dirs = torch.as_tensor(np.stack(w4.directions), device="cuda")
+        helm.gn_hvp(G4, m4, w4.omegas, w4.sources, w4.receivers, dirs, precision=prec, tol=TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hv, hinfo = helm.gn_hvp(G4, m4, w4.omegas, w4.sources, w4.receivers, dirs, precision=prec, tol=TOL)
+        torch.cuda.synchronize()
+        th = time.perf_counter() - t0
+        n_solves = len(w4.omegas) * len(w4.sources) * (2 + 2 * len(w4.directions))
+        extras["gn_hvp_201"] = {"ms": round(th * 1e3, 3), "directions": len(w4.directions),
+                                "solves": n_solves, "solves_per_s": round(n_solves / th, 2),
+                                "max_relres": hinfo.max_relres}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -214,7 +269,7 @@ def main():
                    "precision": prec},
         "p50_ms": round(percentile(lat, 0.5), 3), "p99_ms": round(percentile(lat, 0.99), 3),
         "ir_iters": max(i.ir_iters for i in infos), "max_relres": max(i.max_relres for i in infos),
-        "fp64_plain": fp64, "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+        "fp64_plain": fp64, "extras": extras, "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
