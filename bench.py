@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Helmholtz RHS solves/s at 401^2 (rel. residual<=1e-10) vs FP64 plain; p50/p99 ms"
 TOL = 1e-10
 PEAK = {"fp64": 78.6, "fp32_ir": 157.3}           # dense matrix-core TFLOP/s (MI355X)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_step_c3_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_step_401x401_5freq_64src_fp32ir_traffic.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2301_10762_amd", "csrc", f)
                for f in ("helm_factor.hip", "helm_device.h", "helm_internal.h")]
 

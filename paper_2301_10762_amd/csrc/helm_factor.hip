@@ -448,24 +448,40 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     const bool single = ps.last_panel && d.npan == 1;   // next tile is Y = T itself
     const int w = t >> 6, l = t & 63, lr = l & 15, lg = l >> 4;
     const int wr = w >> 1, wc = w & 1;   // this wave's 16 x 16 output tile of the products
+    // every global load is issued up front at a clamped (in-range) address;
+    // entries outside the kb x kbn tiles are zeroed when they are placed.
     // T arrives transposed (Tt[c][k]): read it in order, place it as sT[k][c]
+    C tl[4], xa[4], xb[4], xz[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int idx = t + 256 * i;
         const int hi = idx >> 5, lo = idx & 31;
-        sT[lo][hi] = (hi < kb && lo < kb) ? gld(Tcur + idx) : mk<C>(0.0, 0.0);
-        if (!single) {
-            sXa[hi][lo] = (hi < kbn && lo < kb) ? gld(X + (size_t)(kn0 + hi) * np + k0 + lo) : mk<C>(0.0, 0.0);
-            sXb[hi][lo] = (hi < kb && lo < kbn) ? gld(X + (size_t)(k0 + hi) * np + kn0 + lo) : mk<C>(0.0, 0.0);
-        }
+        tl[i] = gld(Tcur + idx);
+        xa[i] = gld(X + (size_t)(kn0 + min(hi, kbn - 1)) * np + k0 + min(lo, kb - 1));
+        xb[i] = gld(X + (size_t)(k0 + min(hi, kb - 1)) * np + kn0 + min(lo, kbn - 1));
     }
     // X_{K'K'} in the accumulator layout of this wave's tile
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
+        xz[e] = gld(X + (size_t)(kn0 + min(rr, kbn - 1)) * np + kn0 + min(cc, kbn - 1));
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the first wait
+    const C cz = mk<C>(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = t + 256 * i;
+        const int hi = idx >> 5, lo = idx & 31;
+        sT[lo][hi] = (hi < kb && lo < kb) ? tl[i] : cz;
+        sXa[hi][lo] = (!single && hi < kbn && lo < kb) ? xa[i] : cz;
+        sXb[hi][lo] = (!single && hi < kb && lo < kbn) ? xb[i] : cz;
+    }
     using V = typename CT<T>::v4;
     V zr, zi;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
-        const C v = (!single && rr < kbn && cc < kbn) ? gld(X + (size_t)(kn0 + rr) * np + kn0 + cc) : mk<C>(0.0, 0.0);
+        const C v = (!single && rr < kbn && cc < kbn) ? xz[e] : cz;
         zr[e] = v.x;
         zi[e] = v.y;
     }
@@ -553,50 +569,59 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
     //    columns) and T for the W product, V_J = X_{K,J} for the update (kept
     //    in registers until W is done), and this tile of X'
     C (*sT)[33] = sV;   // T shares the V buffer until W is formed
-    C xik[8], tv[4], vv[8];
+    // every load is issued at a clamped (in-range) address; out-of-range and
+    // identity entries are substituted afterwards
+    C xik[8], tv[4], vv[8], xt[2][2][4];
     {
-        const int rr = t >> 2, c8 = 8 * (t & 3), row = I0 + rr;
+        const int rr = t >> 2, c8 = 8 * (t & 3), row = min(I0 + rr, np - 1);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = c8 + q;
-            xik[q] = (row < np && c < kb) ? gld(X + (size_t)row * np + k0 + c) : mk<C>(0.0, 0.0);
-        }
+        for (int q = 0; q < 8; ++q) xik[q] = gld(X + (size_t)row * np + k0 + min(c8 + q, kb - 1));
 #pragma unroll
         for (int q = 0; q < 4; ++q) tv[q] = gld(Tcur + t + 256 * q);   // Tt[c][k], idx = 32 c + k
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int i = t + 256 * q, k = i >> 6, cc = i & 63, col = J0 + cc;
-            C v = mk<C>(0.0, 0.0);
-            if (k < kb && col < np)
-                v = (col >= k0 && col < k0 + kb) ? mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0)
-                                                 : gld(X + (size_t)(k0 + k) * np + col);
-            vv[q] = v;
+            const int i = t + 256 * q, k = i >> 6, cc = i & 63;
+            vv[q] = gld(X + (size_t)(k0 + min(k, kb - 1)) * np + min(J0 + cc, np - 1));
         }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    xt[bi][bj][e] = gld(X + (size_t)min(R[bi] + acc_row<T>(lg, e), np - 1) * np +
+                                        min(Cc[bj] + lr, np - 1));
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the first wait
+    const C zero = mk<C>(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = t + 256 * q, k = i >> 6, col = J0 + (i & 63);
+        if (!(k < kb && col < np)) vv[q] = zero;
+        else if (col >= k0 && col < k0 + kb) vv[q] = mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0);
     }
     V accr[2][2], acci[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
+            const int col = Cc[bj] + lr;
+            const bool inK = col >= k0 && col < k0 + kb;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { accr[bi][bj][e] = 0; acci[bi][bj][e] = 0; }
-            if (vr[bi] && vc[bj]) {
-                const int col = Cc[bj] + lr;
-                const bool inK = col >= k0 && col < k0 + kb;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = R[bi] + acc_row<T>(lg, e);
-                    const C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : gld(X + (size_t)row * np + col);
-                    accr[bi][bj][e] = v.x;
-                    acci[bi][bj][e] = v.y;
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int row = R[bi] + acc_row<T>(lg, e);
+                C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : xt[bi][bj][e];
+                if (!(vr[bi] && vc[bj])) v = zero;
+                accr[bi][bj][e] = v.x;
+                acci[bi][bj][e] = v.y;
             }
         }
     // 2. X_{I,K} and T into LDS
     {
         const int rr = t >> 2, c8 = 8 * (t & 3);
+        const bool rok = I0 + rr < np;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = xik[q];
+        for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = (rok && c8 + q < kb) ? xik[q] : zero;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = t + 256 * q, c = i >> 5, k = i & 31;
@@ -712,11 +737,13 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         }
 }
 
+// uni > 0: every chain of the launch has uni workgroups (chain = block / uni)
 template <typename T>
-__global__ __launch_bounds__(256) void k_factor_step(const ChainTab tab, int n, int tstep) {
+__global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int n, int tstep, int uni) {
     using C = typename CT<T>::c;
     __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
-    const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
+    const int ci = uni > 0 ? (int)(blockIdx.x / (unsigned)uni)
+                           : find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
     const ChainInfo d = tab.c[ci];
     if (tstep >= d.T) return;
     const PanelStep ps = panel_step(d, tstep);
@@ -1224,8 +1251,11 @@ void launch_factor_init(const ChainTab& tab, int n, int total, bool fp32, hipStr
     else hipLaunchKernelGGL(k_factor_init<double>, dim3(total), dim3(256), 0, st, tab, n);
 }
 void launch_factor_step(const ChainTab& tab, int n, int t, int total, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t);
-    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t);
+    int uni = step_blocks(tab.c[0].np);
+    for (int q = 0; q < n; ++q)
+        if (tab.c[q].utile0 != q * uni || step_blocks(tab.c[q].np) != uni) uni = 0;
+    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
+    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
 }
 void launch_tile_inverse(int count, int kb, int pivot, const double* A, double* T, int* status, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, pivot, (const double2*)A, (double2*)T,
