@@ -180,6 +180,18 @@ void helm_set_tile_pivoting(int always);
  * exchanged panels cannot stay in the non-coherent L2). */
 void helm_set_factor_path(int persistent);
 
+/* Device memory of factors and scratch is recycled through a cache of freed
+ * blocks: helm_factor_destroy and the end of every call return their blocks
+ * to it (with an event marking their last use on the stream), and a later
+ * request of about the same size takes a cached block after queueing a wait
+ * on that event.  The cache holds at most `bytes` (default 32 GiB); the
+ * oldest blocks beyond the limit go back to the device's memory pool once
+ * their last use has finished.  helm_set_cache_limit(0) empties the cache.
+ * This memory is outside the helm_factor_bytes() accounting of live factors.
+ * Returns the previous limit.  Not for use while another thread is inside
+ * the library. */
+size_t helm_set_cache_limit(size_t bytes);
+
 /* Lane-layout check of the matrix-core instruction used by the kernels:
  * D = A(16x4) * B(4x16) in FP64 (prec 0) or FP32 (prec 1) on one wavefront. */
 int helm_mfma_probe(int prec, const double* A_dev, const double* B_dev, double* D_dev, void* stream);
@@ -199,6 +211,7 @@ int helm_kernel_time(int kind, double* total_ms, int64_t* count);
  * 2 = persistent factorisations redone one launch per step because a wait
  * timed out, 3 = the code of the last such wait (bit 30 set; bit 20: the
  * next-tile workgroup; bit 16: the merge-block wait; low 16 bits: the step),
+ * 4 = bytes of device memory held in the block cache (below),
  * -1 for an unknown index. */
 int64_t helm_counter(int which);
 

@@ -25,7 +25,8 @@ struct helm_factor_s {
     void* G;       // nz * np * np complex (16 B for FP64, 8 B for FP32)
     double* m;     // device copy of the model
     size_t bytes;
-    hipStream_t st;   // the stream it was made on (its memory is freed there)
+    size_t gbytes;    // size of G
+    hipStream_t st;   // the stream it was made on (its memory is released there)
 };
 
 namespace {
@@ -65,11 +66,8 @@ int check_grid(const helm_grid* g) {
     return HELM_OK;
 }
 
-// stream-ordered scratch memory, released on scope exit (after the work that
-// uses it, in stream order)
-// Device memory of factors and scratch comes from the device's stream-ordered
-// pool, which keeps freed memory for reuse (so repeated factorisations do not
-// pay for fresh gigabyte allocations).
+// The device's stream-ordered pool, from which the block cache below
+// allocates, keeps memory released to it for reuse.
 void keep_pool_memory() {
     static std::once_flag once;
     std::call_once(once, [] {
@@ -82,20 +80,119 @@ void keep_pool_memory() {
     });
 }
 
+// Device memory of factors and scratch goes through a small cache of freed
+// blocks.  A released block keeps an event recorded on the stream that last
+// used it; a later request of about the same size (on any stream of the same
+// device) takes it after queueing a wait on that event, so a factorisation
+// or a refinement step does not pay for a fresh allocation or a release
+// (each a driver call of tens to hundreds of microseconds for large blocks).
+// Blocks beyond the cache limit are released to the device's stream-ordered
+// pool, oldest first, once their last use has finished.
+struct DevCache {
+    struct Blk {
+        void* p;
+        size_t bytes;
+        int dev;
+        hipEvent_t ready;
+    };
+    std::mutex mu;
+    std::vector<Blk> free;   // oldest first
+    size_t held = 0;
+    size_t limit = (size_t)32 << 30;
+
+    static size_t rounded(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        const size_t q = bytes <= ((size_t)1 << 20) ? 256 : ((size_t)2 << 20);
+        return (bytes + q - 1) / q * q;
+    }
+    void evict_locked(size_t keep) {
+        while (held > keep && !free.empty()) {
+            Blk b = free.front();
+            free.erase(free.begin());
+            held -= b.bytes;
+            (void)hipEventSynchronize(b.ready);
+            (void)hipEventDestroy(b.ready);
+            (void)hipFreeAsync(b.p, nullptr);
+        }
+    }
+    hipError_t get(void** out, size_t bytes, hipStream_t st) {
+        const size_t rb = rounded(bytes);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            int best = -1;
+            for (int i = 0; i < (int)free.size(); ++i) {
+                const Blk& b = free[i];
+                if (b.dev == dev && b.bytes >= rb && b.bytes <= rb + rb / 4 &&
+                    (best < 0 || b.bytes < free[best].bytes))
+                    best = i;
+            }
+            if (best >= 0) {
+                Blk b = free[best];
+                free.erase(free.begin() + best);
+                held -= b.bytes;
+                (void)hipStreamWaitEvent(st, b.ready, 0);
+                (void)hipEventDestroy(b.ready);
+                *out = b.p;
+                return hipSuccess;
+            }
+        }
+        hipError_t e = hipMallocAsync(out, rb, st);
+        if (e != hipSuccess) {
+            // give the cached blocks back to the pool and try once more
+            (void)hipGetLastError();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                evict_locked(0);
+            }
+            e = hipMallocAsync(out, rb, st);
+        }
+        return e;
+    }
+    void put(void* p, size_t bytes, hipStream_t st) {
+        if (!p) return;
+        Blk b{p, rounded(bytes), 0, nullptr};
+        (void)hipGetDevice(&b.dev);
+        if (hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) {
+            (void)hipFreeAsync(p, st);
+            return;
+        }
+        (void)hipEventRecord(b.ready, st);
+        std::lock_guard<std::mutex> lk(mu);
+        free.push_back(b);
+        held += b.bytes;
+        evict_locked(limit);
+    }
+    size_t set_limit(size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        const size_t old = limit;
+        limit = bytes;
+        evict_locked(limit);
+        return old;
+    }
+    size_t cached() {
+        std::lock_guard<std::mutex> lk(mu);
+        return held;
+    }
+};
+DevCache g_cache;
+
+// scratch memory, returned to the cache on scope exit (after the work that
+// uses it, in stream order)
 struct Scratch {
     hipStream_t st;
-    std::vector<void*> ptrs;
+    std::vector<std::pair<void*, size_t>> ptrs;
     explicit Scratch(hipStream_t s) : st(s) {}
     ~Scratch() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, st);
+        for (auto& pb : ptrs) g_cache.put(pb.first, pb.second, st);
     }
     template <typename T>
     int get(T** out, size_t bytes) {
         void* p = nullptr;
-        if (bytes == 0) bytes = 16;
-        hipError_t e = hipMallocAsync(&p, bytes, st);
+        hipError_t e = g_cache.get(&p, bytes, st);
         if (e != hipSuccess) return fail(HELM_ENOMEM, std::string("scratch allocation failed: ") + hipGetErrorString(e));
-        ptrs.push_back(p);
+        ptrs.emplace_back(p, bytes);
         *out = (T*)p;
         return HELM_OK;
     }
@@ -319,8 +416,8 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
 
 void destroy(helm_factor_s* f) {
     if (!f) return;
-    if (f->G) (void)hipFreeAsync(f->G, f->st);
-    if (f->m) (void)hipFreeAsync(f->m, f->st);
+    if (f->G) g_cache.put(f->G, f->gbytes, f->st);
+    if (f->m) g_cache.put(f->m, sizeof(double) * N_of(f->g), f->st);
     delete f;
 }
 
@@ -352,12 +449,13 @@ int factor_many(int count, const helm_grid* grids, const double* const* m_devs, 
         f->bytes = factor_bytes_of(grids[c], prec);
         f->st = st;
         size_t gb = (size_t)f->np * f->np * (size_t)grids[c].nz * elem_bytes(prec);
-        if (hipMallocAsync(&f->G, gb, st) != hipSuccess) {
+        f->gbytes = gb;
+        if (g_cache.get(&f->G, gb, st) != hipSuccess) {
             f->G = nullptr;
             cleanup();
             return fail(HELM_ENOMEM, "factor allocation of " + std::to_string(gb) + " bytes failed");
         }
-        if (hipMallocAsync((void**)&f->m, sizeof(double) * N_of(grids[c]), st) != hipSuccess) {
+        if (g_cache.get((void**)&f->m, sizeof(double) * N_of(grids[c]), st) != hipSuccess) {
             f->m = nullptr;
             cleanup();
             return fail(HELM_ENOMEM, "model copy allocation failed");
@@ -705,6 +803,7 @@ int64_t helm_counter(int which) {
         case 1: return g_solves.load();
         case 2: return g_persist_fallbacks.load();
         case 3: return g_persist_last_err.load();
+        case 4: return (int64_t)g_cache.cached();
         default: return -1;
     }
 }
@@ -712,6 +811,8 @@ int64_t helm_counter(int which) {
 void helm_set_tile_pivoting(int always) { g_force_pivot = always ? 1 : 0; }
 
 void helm_set_factor_path(int persistent) { g_persist = persistent ? 1 : 0; }
+
+size_t helm_set_cache_limit(size_t bytes) { return g_cache.set_limit(bytes); }
 
 void helm_kernel_timing(int enable) {
     g_timer.drain();

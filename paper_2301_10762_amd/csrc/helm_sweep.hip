@@ -15,7 +15,8 @@ namespace helm {
 
 constexpr int SW_WAVES = 4;
 constexpr int SW_CTG = 1;     // 16-column tiles per workgroup (the waves split them, then K)
-constexpr int SW_DEPTH = 4;   // 16-wide K chunks in flight per wave
+constexpr int SW_DEPTH = 2;   // 16-wide K chunks in flight per wave
+constexpr int SW_UNROLL = 8;  // chunks per straight-line block of the contraction
 
 int sweep_row_tiles(int np) { return np / 16; }
 int sweep_col_tiles(int S) { return ((S + 15) / 16 + SW_CTG - 1) / SW_CTG; }
@@ -45,8 +46,8 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
 
 // One workgroup per 16-row tile of a front's block row and group of SW_CTG
 // 16-column tiles of the right-hand sides: the product G_j(rows) Y(columns)
-// on the matrix cores, four real products per complex one in separate
-// accumulators.  The waves share out the column tiles and split the
+// on the matrix cores, three real products per complex one (Gauss's form:
+// Gr Yr, Gi Yi and (Gr + Gi)(Yr + Yi), in separate accumulators).  The waves share out the column tiles and split the
 // contraction; the parts are summed in a fixed order through LDS.  Each wave
 // streams its operands with SW_DEPTH chunks of 16 in flight, and several
 // workgroups per compute unit hide the rest of the latency.  Workgroups are
@@ -54,14 +55,16 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
 // (consecutive workgroups go to consecutive XCDs) and share its L2.
 template <typename T, bool FWD, bool CONJB>
 __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int n, int tstep, int groups,
-                                                        int cgroups) {
+                                                        int cgroups, int uni) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     __shared__ T red[SW_WAVES][2][4][64];
     const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
     const int g = (slot / cgroups) * 8 + xcd, cgi = slot % cgroups;
     if (g >= groups) return;
-    const int ci = find_chain(tab.c, n, g, [](const SweepInfo& c) { return c.tile0; });
+    // uni > 0: every front of the launch has uni row tiles
+    const int ci = uni > 0 ? (int)((unsigned)g / (unsigned)uni)
+                           : find_chain(tab.c, n, g, [](const SweepInfo& c) { return c.tile0; });
     const SweepInfo d = tab.c[ci];
     if (tstep >= (FWD ? d.nfwd : d.nbwd)) return;
     const int nct = (d.S + 15) >> 4, ct0 = SW_CTG * cgi;
@@ -97,32 +100,32 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int
     const bool merge_in = more && d.Bm && tstep + 2 == d.nfwd;
     const bool hand_over = FWD && !more && d.Mout;
     const bool lead = active && part == 0;
+    // loaded unconditionally at clamped addresses (so no load waits on
+    // another), then zeroed where unused
     C pre[4];
+    const bool want = lead && (FWD ? (merge_in || more || hand_over) : true);
+    if (lead) {
+        const int sc = min(s, d.S - 1);
+        const int jr = (FWD && (more || hand_over)) ? j + d.dir : j;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int i = i0 + acc_row<T>(lg, e);
-        pre[e] = mk<C>(0.0, 0.0);
-        if (lead && scol && i < nx) {
-            if (FWD) {
-                if (merge_in) pre[e] = gld((const C*)d.Bm + b_tiled(i, s, np));
-                else if (more || hand_over)
-                    pre[e] = conj_if(gld(Bv + (size_t)s * d.ldb + (size_t)(j + d.dir) * nx + i), CONJB);
-            } else {
-                pre[e] = gld(X + (size_t)s * d.ldx + (size_t)j * nx + i);
-            }
+        for (int e = 0; e < 4; ++e) {
+            const int ic = min(i0 + acc_row<T>(lg, e), nx - 1);
+            const C* src = !FWD      ? X + (size_t)sc * d.ldx + (size_t)j * nx + ic
+                           : merge_in ? (const C*)d.Bm + b_tiled(ic, sc, np)
+                                      : Bv + (size_t)sc * d.ldb + (size_t)jr * nx + ic;
+            pre[e] = gld(src);
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
 
-    V rr, ii, ri, ir;
+    V p1, p2, p3;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { rr[e] = 0; ii[e] = 0; ri[e] = 0; ir[e] = 0; }
+    for (int e = 0; e < 4; ++e) { p1[e] = 0; p2[e] = 0; p3[e] = 0; }
     // this wave's chunks of 16 in the contraction; in MFMA step q lane group
-    // lg carries k = 16 ch + 4 q + lg.  Loads are unconditional (chunk index
-    // clamped, tail chunks zeroed) so the waits count exactly SW_DEPTH
-    // chunks in flight.
+    // lg carries k = 16 ch + 4 q + lg.  Chunk indices are clamped, so every
+    // load is in range.
     const int nch = np >> 4;
     const int c_beg = active ? part * nch / P : 0, c_end = active ? (part + 1) * nch / P : 0;
-    const int cnt = c_end - c_beg;
     C ga[SW_DEPTH][4], ya[SW_DEPTH][4];
     auto load = [&](C (&gq)[4], C (&yq)[4], int c) {
         const int cc = min(c, c_end - 1);
@@ -133,30 +136,42 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int
             yq[q] = gld(Yt + o);
         }
     };
-    if (cnt > 0) {
+    // The chunks run in straight-line blocks of SW_UNROLL, each starting
+    // with empty queues: the products of a chunk past the end are skipped (a
+    // wave-uniform branch) while the refills stay unconditional, so the
+    // outstanding loads are the same on every path and each wait covers
+    // exactly the chunk about to be used.
+    for (int c0 = c_beg; c0 < c_end; c0 += SW_UNROLL) {
 #pragma unroll
-        for (int v = 0; v < SW_DEPTH; ++v) load(ga[v], ya[v], c_beg + v);
-        for (int c0 = c_beg; c0 < c_end; c0 += SW_DEPTH) {
+        for (int v = 0; v < SW_DEPTH; ++v) load(ga[v], ya[v], c0 + v);
 #pragma unroll
-            for (int v = 0; v < SW_DEPTH; ++v) {
-                const bool live = c0 + v < c_end;
+        for (int u = 0; u < SW_UNROLL; ++u) {
+            const int v = u % SW_DEPTH;
+            if (c0 + u < c_end) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T yr = live ? ya[v][q].x : (T)0, yi = live ? ya[v][q].y : (T)0;
-                    rr = mfma16(ga[v][q].x, yr, rr);
-                    ii = mfma16(ga[v][q].y, yi, ii);
-                    ri = mfma16(ga[v][q].x, yi, ri);
-                    ir = mfma16(ga[v][q].y, yr, ir);
+                    const T yr = ya[v][q].x, yi = ya[v][q].y;
+                    const T gr = ga[v][q].x, gi = ga[v][q].y;
+                    p1 = mfma16(gr, yr, p1);
+                    p2 = mfma16(gi, yi, p2);
+                    p3 = mfma16(gr + gi, yr + yi, p3);
                 }
-                load(ga[v], ya[v], c0 + v + SW_DEPTH);
             }
+            if (u + SW_DEPTH < SW_UNROLL) load(ga[v], ya[v], c0 + u + SW_DEPTH);
+            __builtin_amdgcn_sched_barrier(0);
         }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = i0 + acc_row<T>(lg, e);
+        if (!(want && scol && i < nx)) pre[e] = mk<C>(0.0, 0.0);
+        else if (FWD && !merge_in) pre[e] = conj_if(pre[e], CONJB);
     }
     T sre[4], sim[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        sre[e] = rr[e] - ii[e];
-        sim[e] = ri[e] + ir[e];
+        sre[e] = p1[e] - p2[e];
+        sim[e] = p3[e] - p1[e] - p2[e];
     }
     if (P > 1) {
 #pragma unroll
@@ -220,16 +235,19 @@ void launch_sweep_init(const SweepTab& tab, int n, int total, bool fp32, bool co
 void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp32, bool forward, bool conj_b,
                   hipStream_t st_) {
     const dim3 grid(sweep_grid(groups, st)), block(64 * SW_WAVES);
+    int uni = sweep_row_tiles(tab.c[0].np);
+    for (int q = 0; q < n; ++q)
+        if (tab.c[q].tile0 != q * uni || sweep_row_tiles(tab.c[q].np) != uni) uni = 0;
     if (fp32) {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, tab, n, t, groups, st);
-            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, tab, n, t, groups, st);
-        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, tab, n, t, groups, st);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
     } else {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, tab, n, t, groups, st);
-            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, tab, n, t, groups, st);
-        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, tab, n, t, groups, st);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
     }
 }
 

@@ -112,6 +112,8 @@ def lib():
     L.helm_set_tile_pivoting.restype = None
     L.helm_set_factor_path.argtypes = [ctypes.c_int]
     L.helm_set_factor_path.restype = None
+    L.helm_set_cache_limit.argtypes = [ctypes.c_size_t]
+    L.helm_set_cache_limit.restype = ctypes.c_size_t
     L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
     L.helm_kernel_timing.argtypes = [ctypes.c_int]
     L.helm_kernel_timing.restype = None
@@ -174,7 +176,8 @@ def _i32(seq):
 def counters() -> dict:
     L = lib()
     return {"launches": int(L.helm_counter(0)), "solves": int(L.helm_counter(1)),
-            "persist_fallbacks": int(L.helm_counter(2)), "persist_last_err": int(L.helm_counter(3))}
+            "persist_fallbacks": int(L.helm_counter(2)), "persist_last_err": int(L.helm_counter(3)),
+            "cached_bytes": int(L.helm_counter(4))}
 
 
 KERNEL_KINDS = {"factor_step": 0, "factor_init": 1, "sweep": 2}
@@ -374,6 +377,12 @@ def set_factor_path(persistent: bool):
     """One launch per panel step (default) or one persistent launch per
     factorisation (process-wide)."""
     lib().helm_set_factor_path(int(persistent))
+
+
+def set_cache_limit(nbytes: int) -> int:
+    """Bytes of freed device blocks the library keeps for reuse (0 empties
+    the cache); returns the previous limit."""
+    return int(lib().helm_set_cache_limit(int(nbytes)))
 
 
 def mfma_probe(prec: int, A, B):

@@ -119,3 +119,35 @@ def test_persistent_with_forced_tile_pivoting(helm):
     Fo = oracle.Factor(g, m, w)
     assert rel(Xp, Fo.solve(B)) < 1e-9
     Fo.close()
+
+
+def test_block_cache_reuses_freed_factor_memory(helm):
+    """A destroyed factor's memory goes to the library's block cache and the
+    next factorisation of the same size takes it: the cache shrinks, and the
+    result is bitwise the one computed on fresh memory.  A zero limit empties
+    the cache."""
+    nx, nz, hx, hz = 130, 33, 0.02, 0.02
+    m, w, B = _system(nx, nz, hx, hz, seed=11)
+    grid = helm.Grid(nx, nz, hx, hz)
+    Bd = torch.as_tensor(B, device="cuda")
+    md = torch.as_tensor(m, device="cuda")
+    old = helm.set_cache_limit(0)
+    try:
+        helm.set_cache_limit(1 << 34)
+        F = helm.factor(grid, md, w, "fp32_ir")
+        X1, _ = helm.solve(F, Bd, tol=1e-10)
+        X1 = X1.cpu().numpy()
+        F.close()
+        torch.cuda.synchronize()
+        held = helm.counters()["cached_bytes"]
+        assert held >= 144 * 144 * 33 * 8   # at least this factor's G (np = 144) went to the cache
+        F = helm.factor(grid, md, w, "fp32_ir")
+        assert helm.counters()["cached_bytes"] < held
+        X2, info = helm.solve(F, Bd, tol=1e-10)
+        F.close()
+        assert np.array_equal(X2.cpu().numpy(), X1)
+        assert info.max_relres <= 1e-10
+        helm.set_cache_limit(0)
+        assert helm.counters()["cached_bytes"] == 0
+    finally:
+        helm.set_cache_limit(old)
