@@ -281,6 +281,97 @@ __device__ __forceinline__ bool gj_rows(typename CT<T>::c (&a)[4], RowScratch<T>
     return sh.small != 0;
 }
 
+// Unpivoted Gauss-Jordan with 2 x 2 diagonal pivot blocks (complex64 tiles).
+// The tile lives in registers (layout above) and, between steps, in one of
+// two LDS copies L[2][32][33]: every thread writes its four entries after a
+// step and reads what the next step needs (two pivot rows, its entries of
+// the two pivot columns, the 2 x 2 pivot block P) after one barrier, so a
+// barrier is paid per pair of pivots.  With F = (columns p, p+1) - (unit
+// columns) and Fs = F P^{-1}, a step is a_ij -= Fs_i . (rows p, p+1)_j off
+// the pivot columns and (pivot columns) = (unit columns) - Fs, which is two
+// consecutive steps of the uniform form above.  The pivots are flagged small
+// as in the 1 x 1 form: |a_pp|^2 < thr, or |det P|^2 < thr |a_pp|^2 (the
+// second pivot of the pair).
+template <typename T, int KBT, int PE>
+__device__ __forceinline__ void gj2_step(typename CT<T>::c (&a)[4], typename CT<T>::c* L, int pc, int r, int rr,
+                                         int cg, float thr, bool& small) {
+    using C = typename CT<T>::c;
+    constexpr int PAR = (PE >> 1) & 1;
+    const int p = 4 * pc + PE, q = p + 1;
+    const C* B = L + PAR * 32 * 33;
+    C* Bn = L + (PAR ^ 1) * 32 * 33;
+    const C pa = B[p * 33 + p], pb = B[p * 33 + q], pcc = B[q * 33 + p], pd = B[q * 33 + q];
+    C r1[4], r2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        r1[e] = B[p * 33 + 4 * cg + e];
+        r2[e] = B[q * 33 + 4 * cg + e];
+    }
+    C f1 = B[rr * 33 + p], f2 = B[rr * 33 + q];
+    // P^{-1} = [[d, -b], [-c, a]] / det
+    const C det = csub(cmul(pa, pd), cmul(pb, pcc));
+    const T n1 = pa.x * pa.x + pa.y * pa.y, nd = det.x * det.x + det.y * det.y;
+    if (!((float)n1 >= thr) || !((float)nd >= thr * (float)n1)) small = true;
+    const C id = crcp(det);
+    const C i11 = cmul(pd, id), i22 = cmul(pa, id);
+    const C i12 = cmul(mk<C>(-pb.x, -pb.y), id), i21 = cmul(mk<C>(-pcc.x, -pcc.y), id);
+    if (r == p) f1.x -= (T)1;
+    if (r == q) f2.x -= (T)1;
+    const C s1 = cadd(cmul(f1, i11), cmul(f2, i21)), s2 = cadd(cmul(f1, i12), cmul(f2, i22));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        a[e].x = fma(-s1.x, r1[e].x, fma(s1.y, r1[e].y, a[e].x));
+        a[e].y = fma(-s1.x, r1[e].y, fma(-s1.y, r1[e].x, a[e].y));
+        a[e].x = fma(-s2.x, r2[e].x, fma(s2.y, r2[e].y, a[e].x));
+        a[e].y = fma(-s2.x, r2[e].y, fma(-s2.y, r2[e].x, a[e].y));
+    }
+    if (cg == pc) {
+        a[PE] = mk<C>((r == p ? (T)1 : (T)0) - s1.x, -s1.y);
+        a[PE + 1] = mk<C>((r == q ? (T)1 : (T)0) - s2.x, -s2.y);
+    }
+    if (q + 1 < KBT) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bn[r * 33 + 4 * cg + e] = a[e];
+        __syncthreads();
+    }
+}
+
+template <typename T, int KBT>
+__device__ __forceinline__ bool gj_pairs(typename CT<T>::c (&a)[4], typename CT<T>::c* L, RowScratch<T>& sh,
+                                         float tau2) {
+    constexpr int NW = KBT / 8;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < KBT) && (4 * cg < KBT);
+    const int rr = r < KBT ? r : 0;
+    {
+        float m2 = 0.0f;
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, (float)(a[e].x * a[e].x + a[e].y * a[e].y));
+        }
+        const uint32_t wm = wave_max_u32(__float_as_uint(m2));
+        if (l == 0) sh.amax[w] = (w < NW) ? __uint_as_float(wm) : 0.0f;
+        if (t == 0) sh.small = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) L[r * 33 + 4 * cg + e] = a[e];
+    }
+    __syncthreads();
+    float thr = sh.amax[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) thr = fmaxf(thr, sh.amax[q]);
+    thr *= tau2;
+    bool small = false;
+#pragma unroll 1
+    for (int pc = 0; pc < KBT / 4; ++pc) {
+        gj2_step<T, KBT, 0>(a, L, pc, r, rr, cg, thr, small);
+        gj2_step<T, KBT, 2>(a, L, pc, r, rr, cg, thr, small);
+    }
+    if (small) sh.small = 1;
+    __syncthreads();
+    return sh.small != 0;
+}
+
 // Data exchanged between the workgroups of a front (panels, T, the merge
 // block) is written and read with relaxed device-scope atomic accesses, which
 // are coherent at the device level without cache write-back or
@@ -314,17 +405,22 @@ constexpr float TAU2 = 1e-4f;
 
 // Invert the kb x kb tile in a[] and store its inverse transposed
 // (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
-// (pivoted path).  Returns the first zero-pivot step (pivoted path) or -1;
+// (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted complex64 path).  Returns the first zero-pivot step (pivoted path) or -1;
 // *small is set when the unpivoted path met a pivot below the tolerance.
 template <typename T, bool COH = false>
 __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, int pivot, GJScratch<T>& sh,
-                                                typename CT<T>::c (*M)[33], typename CT<T>::c* Tt, bool* small) {
+                                                typename CT<T>::c (*M)[33], typename CT<T>::c* L2,
+                                                typename CT<T>::c* Tt, bool* small) {
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
     const bool act = (r < kb) && (4 * cg < kb);
     if (!pivot) {
-        // diagonal pivots
+        // diagonal pivots: pairs for complex64 tiles (one barrier per two
+        // pivots), single pivots for complex128
         RowScratch<T>& rs = *(RowScratch<T>*)&sh;
-        *small = (kb == 32) ? gj_rows<T, 32>(a, rs, TAU2) : gj_rows<T, 16>(a, rs, TAU2);
+        if constexpr (sizeof(T) == 4)
+            *small = (kb == 32) ? gj_pairs<T, 32>(a, L2, rs, TAU2) : gj_pairs<T, 16>(a, L2, rs, TAU2);
+        else
+            *small = (kb == 32) ? gj_rows<T, 32>(a, rs, TAU2) : gj_rows<T, 16>(a, rs, TAU2);
         if (act) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -383,6 +479,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_factor_init(const ChainTab tab, int n) {
     using C = typename CT<T>::c;
     __shared__ C M[32][33];
+    __shared__ C L2[2 * 32 * 33];
     __shared__ GJScratch<T> sh;
     const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
     const ChainInfo d = tab.c[ci];
@@ -408,7 +505,7 @@ __global__ __launch_bounds__(256) void k_factor_init(const ChainTab tab, int n) 
         a[e] = mk<C>(v.x, v.y);
     }
     bool small;
-    const int zero = invert_and_store<T>(a, kb, d.pivot, sh, M, (C*)d.Tb, &small);
+    const int zero = invert_and_store<T>(a, kb, d.pivot, sh, M, L2, (C*)d.Tb, &small);
     if (zero >= 0 && t == 0) report_zero_pivot(d.status, d.row0, zero);
     if (small && t == 0) d.status[3] = 1;
 }
@@ -536,7 +633,7 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     }
     __syncthreads();   // sXa is reused as the inversion buffer
     bool small;
-    const int zero = invert_and_store<T>(a, kbn, d.pivot, sh, sXa, Tnext, &small);
+    const int zero = invert_and_store<T>(a, kbn, d.pivot, sh, sXa, &sT[0][0], Tnext, &small);
     if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
     if (small && t == 0) d.status[3] = 1;
 }
@@ -755,11 +852,13 @@ __global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int 
     C* Y = ps.last_panel ? G + (size_t)row * n2 : (C*)(ps.p & 1 ? d.P1 : d.P0);
     const C* Tcur = (const C*)d.Tb + (size_t)(tstep & 1) * KB * KB;
     C* Tnext = (C*)d.Tb + (size_t)((tstep + 1) & 1) * KB * KB;
+    // the first workgroup of a chain (dispatched first) prepares the next
+    // diagonal tile, the critical path of the step; the others update tiles
     const int ti = blockIdx.x - d.utile0;
-    if (ti == step_blocks(np) - 1) {
+    if (ti == 0) {
         next_tile<T>(d, ps, X, Tcur, Tnext, smem);
     } else {
-        update_tile<T>(d, ps, ti, X, Y, Tcur, smem);
+        update_tile<T>(d, ps, ti - 1, X, Y, Tcur, smem);
     }
 }
 
@@ -1092,7 +1191,7 @@ __device__ __forceinline__ void persist_next(const ChainInfo& d, char* smem, int
             a[e] = mk<C>(v.x, v.y);
         }
         bool small;
-        const int zero = invert_and_store<T, true>(a, kb, d.pivot, sh, sXa, (C*)d.Tb, &small);
+        const int zero = invert_and_store<T, true>(a, kb, d.pivot, sh, sXa, &sT[0][0], (C*)d.Tb, &small);
         if (zero >= 0 && t == 0) report_zero_pivot(d.status, d.row0, zero);
         if (small && t == 0) d.status[3] = 1;
         front_signal(d.ctr);
@@ -1190,7 +1289,7 @@ __device__ __forceinline__ void persist_next(const ChainInfo& d, char* smem, int
         }
         __syncthreads();   // sXa is reused as the inversion buffer
         bool small;
-        const int zero = invert_and_store<T, true>(a, kbn, d.pivot, sh, sXa, Tnext, &small);
+        const int zero = invert_and_store<T, true>(a, kbn, d.pivot, sh, sXa, &sT[0][0], Tnext, &small);
         if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
         if (small && t == 0) d.status[3] = 1;
         front_signal(d.ctr);
@@ -1236,7 +1335,7 @@ __global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const d
         a[e] = (r < kb && c < kb) ? Am[r * kb + c] : make_double2(0.0, 0.0);
     }
     bool small;
-    const int zero = invert_and_store<double>(a, kb, pivot, sh, M, Tt, &small);
+    const int zero = invert_and_store<double>(a, kb, pivot, sh, M, nullptr, Tt, &small);
     __syncthreads();
     for (int i = t; i < kb * kb; i += 256) {
         const int rr = i / kb, c = i % kb;
