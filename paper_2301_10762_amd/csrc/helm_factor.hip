@@ -834,13 +834,20 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         }
 }
 
-// uni > 0: every chain of the launch has uni workgroups (chain = block / uni)
+// Workgroups 0 .. n-1 of a step launch prepare the next diagonal tile of
+// chains 0 .. n-1 (the critical path of the step, so they are dispatched
+// first); the rest update the 64 x 64 tiles, chain by chain (ftile0).
+// uni > 0: every chain has uni - 1 update workgroups.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int n, int tstep, int uni) {
     using C = typename CT<T>::c;
     __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
-    const int ci = uni > 0 ? (int)(blockIdx.x / (unsigned)uni)
-                           : find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
+    const int b = blockIdx.x;
+    const bool nxt = b < n;
+    const int u = b - n;
+    const int ci = nxt ? b
+                       : uni > 0 ? (int)((unsigned)u / (unsigned)(uni - 1))
+                                 : find_chain(tab.c, n, u, [](const ChainInfo& c) { return c.ftile0; });
     const ChainInfo d = tab.c[ci];
     if (tstep >= d.T) return;
     const PanelStep ps = panel_step(d, tstep);
@@ -852,13 +859,10 @@ __global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int 
     C* Y = ps.last_panel ? G + (size_t)row * n2 : (C*)(ps.p & 1 ? d.P1 : d.P0);
     const C* Tcur = (const C*)d.Tb + (size_t)(tstep & 1) * KB * KB;
     C* Tnext = (C*)d.Tb + (size_t)((tstep + 1) & 1) * KB * KB;
-    // the first workgroup of a chain (dispatched first) prepares the next
-    // diagonal tile, the critical path of the step; the others update tiles
-    const int ti = blockIdx.x - d.utile0;
-    if (ti == 0) {
+    if (nxt) {
         next_tile<T>(d, ps, X, Tcur, Tnext, smem);
     } else {
-        update_tile<T>(d, ps, ti - 1, X, Y, Tcur, smem);
+        update_tile<T>(d, ps, u - d.ftile0, X, Y, Tcur, smem);
     }
 }
 
@@ -1352,7 +1356,7 @@ void launch_factor_init(const ChainTab& tab, int n, int total, bool fp32, hipStr
 void launch_factor_step(const ChainTab& tab, int n, int t, int total, bool fp32, hipStream_t st) {
     int uni = step_blocks(tab.c[0].np);
     for (int q = 0; q < n; ++q)
-        if (tab.c[q].utile0 != q * uni || step_blocks(tab.c[q].np) != uni) uni = 0;
+        if (tab.c[q].ftile0 != q * (uni - 1) || step_blocks(tab.c[q].np) != uni) uni = 0;
     if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
     else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
 }

@@ -294,7 +294,7 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     ChainTab ctab;
     std::memset(&ctab, 0, sizeof(ctab));
     ChainInfo* tab = ctab.c;
-    for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = INT32_MAX;
+    for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = tab[c].ftile0 = INT32_MAX;
     int utot = 0, itot = 0, Tmax = 0, nf = 0;
     size_t buf = 0;
     int wgs = 0;
@@ -362,6 +362,7 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
                 top.peer_target = factor_step_blocks(f->np) * (ci.T + 1);
             }
             ci.utile0 = utot;
+            ci.ftile0 = utot - nf;   // update workgroups of the fronts before this one
             utot += factor_step_blocks(f->np);
             ci.itile0 = itot;
             itot += factor_init_blocks(f->np);

@@ -47,7 +47,9 @@ struct ChainInfo {
     int np, npan, T;        // padded size, panels per block, steps (nblk * npan)
     int row0, dir, nblk;    // first grid row, +1 (down) or -1 (up), blocks of this front
     int pivot;              // 0: diagonal pivots (flagged if small), 1: partial pivoting in tiles
-    int utile0;             // first workgroup of this front in a step launch
+    int utile0;             // first workgroup of this front in a persistent launch
+    int ftile0;             // first update workgroup of this front in a step launch, counted
+                            // after the one next-tile workgroup per front that leads the grid
     int itile0;             // first workgroup in the initial launch
 };
 
