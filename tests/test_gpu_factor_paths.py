@@ -79,8 +79,11 @@ def test_paths_agree_and_match_oracle(helm, nx, nz, hx, hz, precision):
     assert ip.max_relres <= 1e-10 and is_.max_relres <= 1e-10
 
 
-def test_persistent_batch_of_mixed_grids(helm):
-    helm.set_factor_path(True)
+@pytest.mark.parametrize("persistent,precision", [(True, "fp64"), (False, "fp64"), (False, "fp32_ir")])
+def test_batch_of_mixed_grids(helm, persistent, precision):
+    """Fronts of different widths in one launch: the persistent schedule, and
+    the step launches with their scanned front lookup."""
+    helm.set_factor_path(persistent)
     before = helm.counters()["persist_fallbacks"]
     specs = [GRIDS[0], GRIDS[1], GRIDS[3], GRIDS[5]]
     grids, ms, ws, Bs = [], [], [], []
@@ -90,7 +93,7 @@ def test_persistent_batch_of_mixed_grids(helm):
         ms.append(torch.as_tensor(m, device="cuda"))
         ws.append(w * (1 + 0.1 * k))
         Bs.append(torch.as_tensor(B, device="cuda"))
-    Fs = helm.factor_batch(grids, ms, ws, "fp64")
+    Fs = helm.factor_batch(grids, ms, ws, precision)
     Xs, infos = helm.solve_batch(Fs, Bs, tol=1e-10)
     for F, X, B, m, w, g, info in zip(Fs, Xs, Bs, ms, ws, grids, infos):
         og = oracle.Grid(g.nx, g.nz, g.hx, g.hz)
