@@ -114,6 +114,24 @@ __device__ __forceinline__ double2 block_entry(const Coef& c, int j, int r, int 
 // coupling E_ii between rows j and j+1 (zero in the padding)
 __device__ __forceinline__ double row_coupling(const Coef& c, int i) { return i < c.nx ? -z_coupling(c, i) : 0.0; }
 
+// Copy of table entry ci (a kernel argument) with every dword read in one
+// round of scalar loads.  Left to itself the compiler fetches each field
+// where it is first used, after the early exits of a kernel, which chains
+// several round trips to the kernel-argument memory.  The empty asm with each
+// dword as an in-out scalar operand makes all of them live here.
+template <typename Info>
+__device__ __forceinline__ Info load_entry(const Info* tab, int ci) {
+    static_assert(sizeof(Info) % 4 == 0, "table entries are whole dwords");
+    constexpr int W = (int)(sizeof(Info) / 4);
+    uint32_t w[W];
+    __builtin_memcpy(w, &tab[ci], sizeof(Info));
+#pragma unroll
+    for (int i = 0; i < W; ++i) asm volatile("" : "+s"(w[i]));
+    Info d;
+    __builtin_memcpy(&d, w, sizeof(Info));
+    return d;
+}
+
 // Chain owning work item `bid`, given each chain's first item.  Tables are
 // allocated with MAXB entries (unused ones start at INT_MAX), so the scan has
 // no data-dependent loads: all entries are fetched at once.

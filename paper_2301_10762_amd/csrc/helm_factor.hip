@@ -848,7 +848,7 @@ __global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int 
     const int ci = nxt ? b
                        : uni > 0 ? (int)((unsigned)u / (unsigned)(uni - 1))
                                  : find_chain(tab.c, n, u, [](const ChainInfo& c) { return c.ftile0; });
-    const ChainInfo d = tab.c[ci];
+    const ChainInfo d = load_entry(tab.c, ci);
     if (tstep >= d.T) return;
     const PanelStep ps = panel_step(d, tstep);
     const int np = d.np;

@@ -15,7 +15,8 @@ namespace helm {
 
 constexpr int SW_WAVES = 4;
 constexpr int SW_CTG = 1;     // 16-column tiles per workgroup (the waves split them, then K)
-constexpr int SW_DEPTH = 2;   // 16-wide K chunks in flight per wave
+constexpr int SW_GDEPTH = 2;  // 16-wide K chunks of the factor block in flight per wave
+constexpr int SW_YDEPTH = 2;  // and of the coupling vector
 constexpr int SW_UNROLL = 8;  // chunks per straight-line block of the contraction
 
 int sweep_row_tiles(int np) { return np / 16; }
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int
     // uni > 0: every front of the launch has uni row tiles
     const int ci = uni > 0 ? (int)((unsigned)g / (unsigned)uni)
                            : find_chain(tab.c, n, g, [](const SweepInfo& c) { return c.tile0; });
-    const SweepInfo d = tab.c[ci];
+    const SweepInfo d = load_entry(tab.c, ci);
     if (tstep >= (FWD ? d.nfwd : d.nbwd)) return;
     const int nct = (d.S + 15) >> 4, ct0 = SW_CTG * cgi;
     if (ct0 >= nct) return;
@@ -126,38 +127,45 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int
     // load is in range.
     const int nch = np >> 4;
     const int c_beg = active ? part * nch / P : 0, c_end = active ? (part + 1) * nch / P : 0;
-    C ga[SW_DEPTH][4], ya[SW_DEPTH][4];
-    auto load = [&](C (&gq)[4], C (&yq)[4], int c) {
+    C ga[SW_GDEPTH][4], ya[SW_YDEPTH][4];
+    auto gload = [&](C (&gq)[4], int c) {
         const int cc = min(c, c_end - 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const size_t o = (size_t)(4 * cc + q) * 64;
-            gq[q] = gld(Gt + o);
-            yq[q] = gld(Yt + o);
-        }
+        for (int q = 0; q < 4; ++q) gq[q] = gld(Gt + (size_t)(4 * cc + q) * 64);
+    };
+    auto yload = [&](C (&yq)[4], int c) {
+        const int cc = min(c, c_end - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yq[q] = gld(Yt + (size_t)(4 * cc + q) * 64);
     };
     // The chunks run in straight-line blocks of SW_UNROLL, each starting
     // with empty queues: the products of a chunk past the end are skipped (a
     // wave-uniform branch) while the refills stay unconditional, so the
     // outstanding loads are the same on every path and each wait covers
-    // exactly the chunk about to be used.
+    // exactly the chunk about to be used.  The factor block (from HBM) is
+    // fetched SW_GDEPTH chunks ahead, the coupling vector (from L2)
+    // SW_YDEPTH chunks ahead.
     for (int c0 = c_beg; c0 < c_end; c0 += SW_UNROLL) {
 #pragma unroll
-        for (int v = 0; v < SW_DEPTH; ++v) load(ga[v], ya[v], c0 + v);
+        for (int v = 0; v < SW_GDEPTH; ++v) {
+            gload(ga[v], c0 + v);
+            if (v < SW_YDEPTH) yload(ya[v], c0 + v);
+        }
 #pragma unroll
         for (int u = 0; u < SW_UNROLL; ++u) {
-            const int v = u % SW_DEPTH;
+            const int vg = u % SW_GDEPTH, vy = u % SW_YDEPTH;
             if (c0 + u < c_end) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T yr = ya[v][q].x, yi = ya[v][q].y;
-                    const T gr = ga[v][q].x, gi = ga[v][q].y;
+                    const T yr = ya[vy][q].x, yi = ya[vy][q].y;
+                    const T gr = ga[vg][q].x, gi = ga[vg][q].y;
                     p1 = mfma16(gr, yr, p1);
                     p2 = mfma16(gi, yi, p2);
                     p3 = mfma16(gr + gi, yr + yi, p3);
                 }
             }
-            if (u + SW_DEPTH < SW_UNROLL) load(ga[v], ya[v], c0 + u + SW_DEPTH);
+            if (u + SW_GDEPTH < SW_UNROLL) gload(ga[vg], c0 + u + SW_GDEPTH);
+            if (u + SW_YDEPTH < SW_UNROLL) yload(ya[vy], c0 + u + SW_YDEPTH);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
