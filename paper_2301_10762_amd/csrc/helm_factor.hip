@@ -400,6 +400,21 @@ __device__ __forceinline__ void cst(float2* p, float2 v) {
     __hip_atomic_store((unsigned long long*)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Store of an updated panel element.  Complex64: a device-coherent store
+// (written through to memory, no dirty line left in the XCD's L2); with
+// every step rewriting the whole block, lines left dirty at the end of a
+// launch delay the start of the next launch's workgroups (measured: the
+// last workgroups entered ~4 us after the first, ~2 us with these stores).
+// Complex128: a non-temporal store (two coherent 8-byte halves cost more
+// than they save).
+__device__ __forceinline__ void yst(float2* p, float2 v) { cst(p, v); }
+__device__ __forceinline__ void yst(double2* p, double2 v) {
+    gv2d w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (HELM_GLOBAL gv2d*)p);
+}
+
 // Pivot tolerance of the unpivoted path: |a_pp|^2 >= TAU2 * max|a|^2.
 constexpr float TAU2 = 1e-4f;
 
@@ -818,7 +833,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                 const int row = R[bi] + acc_row<T>(lg, e);
                 const C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
                 // the finished inverse goes to the sweeps' operand layout
-                gst(Y + (ps.last_panel ? a_tiled(row, col, np) : (size_t)row * np + col), g);
+                yst(Y + (ps.last_panel ? a_tiled(row, col, np) : (size_t)row * np + col), g);
                 if (schur) {
                     double2 a1;
                     if (Asrc) {
@@ -828,7 +843,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                         a1 = block_entry(d.cf, rn, row, col);
                     }
                     const double s = row_coupling(d.cf, row) * row_coupling(d.cf, col);
-                    An[(size_t)row * np + col] = mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
+                    yst(An + (size_t)row * np + col, mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y));
                 }
             }
         }
