@@ -82,6 +82,42 @@ __device__ __forceinline__ void cmfma(V& cr, V& ci, T ar, T ai, T br, T bi) {
     ci = mfma16(ai, br, ci);
 }
 
+// The same product in three real products (Gauss): p1 += ar br,
+// p2 += ai bi, p3 += (ar + ai)(br + bi); then re = p1 - p2 and
+// im = p3 - p1 - p2.  An accumulator starting at c is seeded
+// p1 = c.re, p2 = 0, p3 = c.re + c.im.
+template <typename T, typename V>
+__device__ __forceinline__ void cmfma3(V& p1, V& p2, V& p3, T ar, T ai, T br, T bi) {
+    p1 = mfma16(ar, br, p1);
+    p2 = mfma16(ai, bi, p2);
+    p3 = mfma16(ar + ai, br + bi, p3);
+}
+
+// Complex product accumulated either way: with GAUSS, (a1, a2, a3) are the
+// three-product accumulators above; otherwise a1 = re, a3 = im (four real
+// products) and a2 is unused.
+template <bool GAUSS, typename T, typename V>
+__device__ __forceinline__ void cacc(V& a1, V& a2, V& a3, T ar, T ai, T br, T bi) {
+    if constexpr (GAUSS) cmfma3<T, V>(a1, a2, a3, ar, ai, br, bi);
+    else cmfma<T, V>(a1, a3, ar, ai, br, bi);
+}
+template <bool GAUSS, typename V>
+__device__ __forceinline__ void cacc_seed(V& a1, V& a2, V& a3, V re, V im) {
+    a1 = re;
+    a2 = re - re;
+    a3 = GAUSS ? re + im : im;
+}
+template <bool GAUSS, typename V>
+__device__ __forceinline__ void cacc_final(V a1, V a2, V a3, V& re, V& im) {
+    if constexpr (GAUSS) {
+        im = a3 - a1 - a2;
+        re = a1 - a2;
+    } else {
+        re = a1;
+        im = a3;
+    }
+}
+
 // ---------------------------------------------------------------- assembly --
 __device__ __forceinline__ double half_at_ends(int idx, int n) { return (idx == 0 || idx == n - 1) ? 0.5 : 1.0; }
 __device__ __forceinline__ double x_coupling(const Coef& c, int j) { return (c.hz / c.hx) * half_at_ends(j, c.nz); }

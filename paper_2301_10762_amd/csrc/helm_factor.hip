@@ -659,6 +659,9 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                             typename CT<T>::c* Y, const typename CT<T>::c* Tcur, char* smem) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
+    // three real products per complex one in complex128 only: in complex64
+    // the larger rounding of the imaginary parts costs a refinement step
+    constexpr bool GAUSS = sizeof(T) == 8;
     const int np = d.np, kb = ps.kb, k0 = ps.k0;
     const int tiles_x = (np + TILE - 1) / TILE;
     const int I0 = (ti / tiles_x) * TILE, J0 = (ti % tiles_x) * TILE;
@@ -712,21 +715,24 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         if (!(k < kb && col < np)) vv[q] = zero;
         else if (col >= k0 && col < k0 + kb) vv[q] = mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0);
     }
-    V accr[2][2], acci[2][2];
+    // Y = X' + W V, accumulated from X'
+    V a1[2][2], a2[2][2], a3[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             const int col = Cc[bj] + lr;
             const bool inK = col >= k0 && col < k0 + kb;
+            V sre, sim;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = R[bi] + acc_row<T>(lg, e);
                 C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : xt[bi][bj][e];
                 if (!(vr[bi] && vc[bj])) v = zero;
-                accr[bi][bj][e] = v.x;
-                acci[bi][bj][e] = v.y;
+                sre[e] = v.x;
+                sim[e] = v.y;
             }
+            cacc_seed<GAUSS, V>(a1[bi][bj], a2[bi][bj], a3[bi][bj], sre, sim);
         }
     // 2. X_{I,K} and T into LDS
     {
@@ -746,14 +752,16 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         V wre[2], wim[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
+            V q1, q2, q3;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { wre[cb][e] = 0; wim[cb][e] = 0; }
+            for (int e = 0; e < 4; ++e) { q1[e] = 0; q2[e] = 0; q3[e] = 0; }
 #pragma unroll
             for (int s8 = 0; s8 < 8; ++s8) {
                 const int k = 4 * s8 + lg;
                 const C av = sW[16 * w + lr][k], bv = sT[k][cb * 16 + lr];
-                cmfma<T, V>(wre[cb], wim[cb], av.x, av.y, bv.x, bv.y);
+                cacc<GAUSS, T, V>(q1, q2, q3, av.x, av.y, bv.x, bv.y);
             }
+            cacc_final<GAUSS, V>(q1, q2, q3, wre[cb], wim[cb]);
         }
         C tk[2][4];   // rows of K: T - I, read before the buffers are rewritten
 #pragma unroll
@@ -804,8 +812,8 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
                     if (vr[bi] && vc[bj])
-                        cmfma<T, V>(accr[bi][bj], acci[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
-                                    bv[bj][s].y);
+                        cacc<GAUSS, T, V>(a1[bi][bj], a2[bi][bj], a3[bi][bj], av[bi][s].x, av[bi][s].y, bv[bj][s].x,
+                                          bv[bj][s].y);
     }
     // 5. store; after the last panel also D_next = A_next - E Y E, into the
     //    front's next block, or into the merge block after a bottom front's
@@ -828,10 +836,12 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
         for (int bj = 0; bj < 2; ++bj) {
             if (!(vr[bi] && vc[bj])) continue;
             const int col = Cc[bj] + lr;
+            V gre, gim;
+            cacc_final<GAUSS, V>(a1[bi][bj], a2[bi][bj], a3[bi][bj], gre, gim);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = R[bi] + acc_row<T>(lg, e);
-                const C g = mk<C>(accr[bi][bj][e], acci[bi][bj][e]);
+                const C g = mk<C>(gre[e], gim[e]);
                 // the finished inverse goes to the sweeps' operand layout
                 yst(Y + (ps.last_panel ? a_tiled(row, col, np) : (size_t)row * np + col), g);
                 if (schur) {
@@ -968,6 +978,7 @@ __device__ __forceinline__ void persist_publish(const ChainInfo& d, int t2, int 
 
 template <typename T>
 __device__ __forceinline__ void persist_update(const ChainInfo& d, int ti, char* smem, int* err) {
+    constexpr bool GAUSS = sizeof(T) == 8;   // as in update_tile
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     const int np = d.np;
@@ -1073,14 +1084,16 @@ __device__ __forceinline__ void persist_update(const ChainInfo& d, int ti, char*
             V wre[2], wim[2];
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
+                V q1, q2, q3;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) { wre[cb][e] = 0; wim[cb][e] = 0; }
+                for (int e = 0; e < 4; ++e) { q1[e] = 0; q2[e] = 0; q3[e] = 0; }
 #pragma unroll
                 for (int s8 = 0; s8 < 8; ++s8) {
                     const int k = 4 * s8 + lg;
                     const C av = sW[16 * w + lr][k], bv = sT[k][cb * 16 + lr];
-                    cmfma<T, V>(wre[cb], wim[cb], av.x, av.y, bv.x, bv.y);
+                    cacc<GAUSS, T, V>(q1, q2, q3, av.x, av.y, bv.x, bv.y);
                 }
+                cacc_final<GAUSS, V>(q1, q2, q3, wre[cb], wim[cb]);
             }
             C tk[2][4];
 #pragma unroll
@@ -1118,6 +1131,14 @@ __device__ __forceinline__ void persist_update(const ChainInfo& d, int ti, char*
             sV[cc][k] = v;
         }
         __syncthreads();
+        // the same accumulation as the step launches, xr and xi serving as
+        // the first and third accumulators
+        V x2[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                cacc_seed<GAUSS, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], xr[bi][bj], xi[bi][bj]);
         for (int kk = 0; kk < kb; kk += 16) {
             C av[2][4], bv[2][4];
 #pragma unroll
@@ -1134,9 +1155,14 @@ __device__ __forceinline__ void persist_update(const ChainInfo& d, int ti, char*
 #pragma unroll
                     for (int bj = 0; bj < 2; ++bj)
                         if (vr[bi] && vc[bj])
-                            cmfma<T, V>(xr[bi][bj], xi[bi][bj], av[bi][s4].x, av[bi][s4].y, bv[bj][s4].x,
-                                        bv[bj][s4].y);
+                            cacc<GAUSS, T, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], av[bi][s4].x, av[bi][s4].y,
+                                              bv[bj][s4].x, bv[bj][s4].y);
         }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                cacc_final<GAUSS, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], xr[bi][bj], xi[bi][bj]);
         const bool more = ts + 1 < d.T;
         if (ps.last_panel || more) {
             __syncthreads();   // every wave is done with sW, sV
