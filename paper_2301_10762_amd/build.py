@@ -23,6 +23,9 @@ FLAGS = [
     "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the leading scalar arguments of the step kernels arrive in SGPRs
+    # (no scalar-load round trip before a workgroup can find its front)
+    "-mllvm", "-amdgpu-kernarg-preload-count=5",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

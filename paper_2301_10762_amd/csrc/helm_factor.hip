@@ -864,7 +864,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 // first); the rest update the 64 x 64 tiles, chain by chain (ftile0).
 // uni > 0: every chain has uni - 1 update workgroups.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_factor_step(const ChainTab tab, int n, int tstep, int uni) {
+__global__ __launch_bounds__(256, 2) void k_factor_step(int n, int tstep, int uni, const ChainTab tab) {
     using C = typename CT<T>::c;
     __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
     const int b = blockIdx.x;
@@ -1398,8 +1398,8 @@ void launch_factor_step(const ChainTab& tab, int n, int t, int total, bool fp32,
     int uni = step_blocks(tab.c[0].np);
     for (int q = 0; q < n; ++q)
         if (tab.c[q].ftile0 != q * (uni - 1) || step_blocks(tab.c[q].np) != uni) uni = 0;
-    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
-    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, tab, n, t, uni);
+    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, n, t, uni, tab);
+    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, n, t, uni, tab);
 }
 void launch_tile_inverse(int count, int kb, int pivot, const double* A, double* T, int* status, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, pivot, (const double2*)A, (double2*)T,

@@ -55,8 +55,8 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
 // numbered so that the column tiles of one row tile run on the same XCD
 // (consecutive workgroups go to consecutive XCDs) and share its L2.
 template <typename T, bool FWD, bool CONJB>
-__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(const SweepTab tab, int n, int tstep, int groups,
-                                                        int cgroups, int uni) {
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int groups, int cgroups, int uni,
+                                                        const SweepTab tab) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     __shared__ T red[SW_WAVES][2][4][64];
@@ -248,14 +248,14 @@ void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp
         if (tab.c[q].tile0 != q * uni || sweep_row_tiles(tab.c[q].np) != uni) uni = 0;
     if (fp32) {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, tab, n, t, groups, st, uni);
-            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
-        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
     } else {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, tab, n, t, groups, st, uni);
-            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
-        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, tab, n, t, groups, st, uni);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
     }
 }
 
