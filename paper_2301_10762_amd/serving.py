@@ -7,6 +7,9 @@ order, until the chain limit of one batched launch sequence (16 chains; one
 chain per frequency) or the HBM budget is reached.  Admitted requests are
 factored together (one set of launches for all their chains) and solved
 together, so requests that arrive while a batch runs join the next one.
+By default the next batch is admitted and factored while the current one is
+solved (two batches in flight, on two streams); its memory then counts
+against the budget together with the batch in flight.
 This is the paper's observation that the solves for different models are
 independent (Appendix, "Parallelisation"), applied to a request stream.
 
@@ -28,6 +31,7 @@ import dataclasses
 import json
 import math
 import sys
+import threading
 import time
 
 MAX_CHAINS = 16
@@ -65,15 +69,32 @@ class ServeResult:
         return self.done - self.arrival
 
 
-class HelmBackend:
-    """The device path: helm.factor_batch / helm.solve_batch."""
+@dataclasses.dataclass
+class _Prepared:
+    batch: list
+    t0: float
+    Fs: dict = dataclasses.field(default_factory=dict)      # (request, frequency) -> factor
+    slots: list = dataclasses.field(default_factory=list)   # entries of Fs to factor
+    grids: list = dataclasses.field(default_factory=list)
+    ms: list = dataclasses.field(default_factory=list)
+    oms: list = dataclasses.field(default_factory=list)
+    keys: set = dataclasses.field(default_factory=set)      # resident factors used
+    bytes: int = 0
+    Bs: dict = None
 
-    def __init__(self, precision="fp32_ir", tol=1e-10, stream=None):
+
+class HelmBackend:
+    """The device path: helm.factor_batch / helm.solve_batch.  Factors are
+    made on one stream and solved on another, so that a pipelined server
+    can factor the next batch while the current one is solved."""
+
+    def __init__(self, precision="fp32_ir", tol=1e-10, stream=None, solve_stream=None):
         from . import helm
         self.helm = helm
         self.precision = precision
         self.tol = tol
         self.stream = stream
+        self.solve_stream = solve_stream if solve_stream is not None else stream
         self.factorisations = 0
 
     def factor_bytes(self, grid) -> int:
@@ -99,7 +120,7 @@ class HelmBackend:
         return torch.as_tensor(req.m, dtype=torch.float64).reshape(-1).to("cuda")
 
     def solve(self, Fs, Bs):
-        return self.helm.solve_batch(Fs, Bs, tol=self.tol, stream=self.stream)
+        return self.helm.solve_batch(Fs, Bs, tol=self.tol, stream=self.solve_stream)
 
     def release(self, F):
         F.close()
@@ -124,6 +145,8 @@ class Server:
         self.cache_bytes = 0
         self.batches = 0
         self.rejected = []
+        self.inflight_bytes = 0          # a factored batch waiting for its solves (pipelined runs)
+        self.inflight_keys = set()
 
     # -- memory accounting --------------------------------------------------
     def _need(self, req: ServeRequest, reuse) -> int:
@@ -154,9 +177,11 @@ class Server:
         self.queue.append(req)
 
     def admit(self):
-        """Requests of the next batch, FIFO, within the chain and memory limits."""
-        batch, chains, used = [], 0, 0
-        keep = set()
+        """Requests of the next batch, FIFO, within the chain and memory
+        limits (memory of a batch still in flight counts against the budget,
+        and the resident factors it uses are not evicted)."""
+        batch, chains, used = [], 0, self.inflight_bytes
+        keep = set(self.inflight_keys)
         while self.queue:
             req = self.queue[0]
             if chains + len(req.omegas) > self.max_chains:
@@ -173,53 +198,70 @@ class Server:
             used += need
         return batch
 
-    def step(self):
-        """Run one batch; returns its results (empty if the queue is empty)."""
-        batch = self.admit()
-        if not batch:
-            return []
-        t0 = self.clock()
-        grids, ms, oms, slots = [], [], [], []
-        Fs = {}                                    # (request index, frequency index) -> factor
+    def _begin(self, batch) -> "_Prepared":
+        """Bookkeeping of an admitted batch: resident factors it reuses, the
+        systems to factor, its right-hand sides (host thread of the caller)."""
+        prep = _Prepared(batch, self.clock())
         for r, req in enumerate(batch):
             m = self.be.model(req)
             for q, w in enumerate(req.omegas):
                 key = (req.model_key, float(w))
                 if req.model_key is not None and key in self.cache:
                     self.cache.move_to_end(key)
-                    Fs[(r, q)] = self.cache[key][0]
+                    prep.Fs[(r, q)] = self.cache[key][0]
+                    prep.keys.add(key)
                 else:
-                    grids.append(req.grid)
-                    ms.append(m)
-                    oms.append(float(w))
-                    slots.append((r, q))
-        if grids:
-            for slot, F in zip(slots, self.be.factor(grids, ms, oms)):
-                Fs[slot] = F
-        order = [(r, q) for r, req in enumerate(batch) for q in range(len(req.omegas))]
-        Bs = {r: self.be.rhs(req) for r, req in enumerate(batch)}
-        X, infos = self.be.solve([Fs[k] for k in order], [Bs[k[0]] for k in order])
+                    prep.grids.append(req.grid)
+                    prep.ms.append(m)
+                    prep.oms.append(float(w))
+                    prep.slots.append((r, q))
+            prep.bytes += self._need(req, prep.keys)
+        prep.Bs = {r: self.be.rhs(req) for r, req in enumerate(batch)}
         self.be.sync()
+        return prep
+
+    def _factor(self, prep: "_Prepared"):
+        if prep.grids:
+            for slot, F in zip(prep.slots, self.be.factor(prep.grids, prep.ms, prep.oms)):
+                prep.Fs[slot] = F
+
+    def _solve(self, prep: "_Prepared"):
+        order = [(r, q) for r, req in enumerate(prep.batch) for q in range(len(req.omegas))]
+        X, infos = self.be.solve([prep.Fs[k] for k in order], [prep.Bs[k[0]] for k in order])
+        self.be.sync()
+        return X, infos
+
+    def _finish(self, prep: "_Prepared", X, infos):
         t1 = self.clock()
         out, c = [], 0
-        for r, req in enumerate(batch):
+        for r, req in enumerate(prep.batch):
             k = len(req.omegas)
-            out.append(ServeResult(req.rid, X[c:c + k], infos[c:c + k], req.arrival, t0, t1, self.batches))
+            out.append(ServeResult(req.rid, X[c:c + k], infos[c:c + k], req.arrival, prep.t0, t1, self.batches))
             c += k
         # keep or free the factors made for this batch
-        for r, q in slots:
-            req = batch[r]
-            F = Fs[(r, q)]
+        for r, q in prep.slots:
+            req = prep.batch[r]
+            F = prep.Fs[(r, q)]
             key = (req.model_key, float(req.omegas[q]))
             if self.resident and req.model_key is not None and key not in self.cache:
                 b = self.be.factor_bytes(req.grid)
-                if self._evict(b, set()):
+                if self._evict(b, set(self.inflight_keys)):
                     self.cache[key] = (F, b)
                     self.cache_bytes += b
                     continue
             self.be.release(F)
         self.batches += 1
         return out
+
+    def step(self):
+        """Run one batch; returns its results (empty if the queue is empty)."""
+        batch = self.admit()
+        if not batch:
+            return []
+        prep = self._begin(batch)
+        self._factor(prep)
+        X, infos = self._solve(prep)
+        return self._finish(prep, X, infos)
 
     def close(self):
         for F, _ in self.cache.values():
@@ -228,24 +270,72 @@ class Server:
         self.cache_bytes = 0
 
 
-def run_stream(server: Server, requests, realtime: bool = True):
+def run_stream(server: Server, requests, realtime: bool = True, pipelined: bool = False):
     """Feed `requests` (sorted by arrival) to the server as they arrive and
-    run it until all are done.  Returns the results in completion order."""
+    run it until all are done.  Returns the results in completion order.
+
+    pipelined: while one batch is solved, the next admitted batch is
+    factored (on the backend's factor stream, from a second host thread);
+    the admission counts the memory of the batch in flight."""
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     results = []
     t0 = server.clock()
-    while pending or server.queue:
+
+    def arrivals():
         now = server.clock() - t0 if realtime else math.inf
         while pending and pending[0].arrival <= now:
             server.submit(pending.popleft())
-        if not server.queue:
-            if pending and realtime:
-                time.sleep(max(0.0, pending[0].arrival - (server.clock() - t0)))
-            continue
-        for res in server.step():
+
+    def collect(out):
+        for res in out:
             res.start -= t0
             res.done -= t0
             results.append(res)
+
+    if not pipelined:
+        while pending or server.queue:
+            arrivals()
+            if not server.queue:
+                if pending and realtime:
+                    time.sleep(max(0.0, pending[0].arrival - (server.clock() - t0)))
+                continue
+            collect(server.step())
+        return results
+
+    inflight = None
+    while pending or server.queue or inflight is not None:
+        arrivals()
+        batch = server.admit() if server.queue else []
+        nxt = server._begin(batch) if batch else None
+        if inflight is None and nxt is None:
+            if pending and realtime:
+                time.sleep(max(0.0, pending[0].arrival - (server.clock() - t0)))
+            continue
+        err = []
+
+        def factor_next():
+            try:
+                server._factor(nxt)
+            except BaseException as e:      # re-raised below
+                err.append(e)
+
+        th = None
+        if nxt is not None:
+            th = threading.Thread(target=factor_next)
+            th.start()
+        solved = server._solve(inflight) if inflight is not None else None
+        if th is not None:
+            th.join()
+        if err:
+            raise err[0]
+        # from here the batch in flight is nxt: its memory and resident
+        # factors are protected while the finished batch's factors are
+        # cached or released
+        server.inflight_bytes = nxt.bytes if nxt is not None else 0
+        server.inflight_keys = set(nxt.keys) if nxt is not None else set()
+        if inflight is not None:
+            collect(server._finish(inflight, *solved))
+        inflight = nxt
     return results
 
 
@@ -278,6 +368,8 @@ def main(argv=None):
     p.add_argument("--budget-gb", type=float, default=64.0)
     p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     p.add_argument("--max-chains", type=int, default=MAX_CHAINS)
+    p.add_argument("--serial", action="store_true",
+                   help="one batch at a time (default: the next batch is factored while the current is solved)")
     args = p.parse_args(argv)
 
     import torch
@@ -291,7 +383,7 @@ def main(argv=None):
         g = helm.Grid(q.n, q.n, I.H_KM, I.H_KM)
         reqs.append(ServeRequest(q.rid, g, torch.as_tensor(m.reshape(-1), device="cuda"), [omega], list(src),
                                  arrival=q.t_arrival))
-    be = HelmBackend(args.precision, 1e-10)
+    be = HelmBackend(args.precision, 1e-10, stream=torch.cuda.Stream(), solve_stream=torch.cuda.Stream())
     # warm-up: one small request through the whole path
     warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",
                         dtype=torch.float64), [1.0], [5])
@@ -299,10 +391,11 @@ def main(argv=None):
     srv.submit(warm)
     srv.step()
     torch.cuda.synchronize()
-    res = run_stream(srv, reqs)
+    res = run_stream(srv, reqs, pipelined=not args.serial)
     worst = max(i.max_relres for r in res for i in r.infos)
     out = summary(res, reqs)
     out.update({"precision": args.precision, "max_relres": worst, "budget_gb": args.budget_gb,
+                "schedule": "serial" if args.serial else "pipelined",
                 "rate": args.rate, "sizes": sorted({q.n for q in stream})})
     print(json.dumps(out), flush=True)
     srv.close()

@@ -131,3 +131,23 @@ def test_autograd_gradcheck(helm):
     scale = abs(float(f(m).item()))
     assert scale > 0
     assert torch.autograd.gradcheck(f, (m,), eps=1e-6, atol=1e-6 * scale + 1e-12, rtol=1e-5, fast_mode=False)
+
+
+def test_pipelined_serving_equals_serial(helm):
+    """Factoring the next batch while the current one is solved (two streams,
+    two host threads) gives bitwise the results of the serial schedule."""
+    from paper_2301_10762_amd import serving as SV
+
+    def reqs():
+        return [make_request(SV, helm, rid, *spec)[0] for rid, spec in enumerate(SPECS)]
+    srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36, max_chains=3)
+    ser = {r.rid: r for r in SV.run_stream(srv, reqs(), realtime=False)}
+    be = SV.HelmBackend("fp32_ir", 1e-10, stream=torch.cuda.Stream(), solve_stream=torch.cuda.Stream())
+    srv = SV.Server(be, 1 << 36, max_chains=3)
+    print("pipelined serving", flush=True)
+    pip = SV.run_stream(srv, reqs(), realtime=False, pipelined=True)
+    assert sorted(r.rid for r in pip) == sorted(ser) and srv.batches >= 2
+    for r in pip:
+        assert max(i.max_relres for i in r.infos) <= 1e-10
+        for x, y in zip(r.X, ser[r.rid].X):
+            assert torch.equal(x, y), r.rid

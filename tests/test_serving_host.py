@@ -40,6 +40,7 @@ class FakeBackend:
         self.calls.append(len(grids))
         out = [FakeFactor(len(self.made) + c, g, w) for c, (g, w) in enumerate(zip(grids, omegas))]
         self.made += out
+        self.max_live = max(getattr(self, "max_live", 0), self.live())
         return out
 
     def rhs(self, req):
@@ -171,3 +172,32 @@ def test_run_stream_serves_everything_and_summarises():
     s = SV.summary(res, reqs)
     assert s["requests"] == 10 and s["batches"] == 3
     assert s["p50_ms"] <= s["p99_ms"] <= s["max_ms"]
+
+
+def test_pipelined_stream_serves_everything_without_leaks():
+    """Two batches in flight: every request is served once, resident
+    factors are reused, and no factor is leaked or released twice."""
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=4, resident=True)
+    reqs = [req(r, key=("k", r % 3), arrival=0.001 * r) for r in range(12)]
+    res = SV.run_stream(srv, reqs, realtime=False, pipelined=True)
+    assert sorted(x.rid for x in res) == list(range(12))
+    assert srv.inflight_bytes == 0 and not srv.inflight_keys
+    assert be.live() == len(srv.cache) == 3
+    srv.close()
+    assert be.live() == 0
+
+
+def test_pipelined_admission_counts_the_batch_in_flight():
+    """With room for two requests in all, a batch of two cannot be followed
+    by another while it is in flight: batches alternate with the solves."""
+    be = FakeBackend()
+    one = per_request_bytes(10, 4)
+    srv = SV.Server(be, 2 * one + one // 2, max_chains=16)
+    reqs = [req(r, arrival=0.0) for r in range(5)]
+    res = SV.run_stream(srv, reqs, realtime=False, pipelined=True)
+    assert sorted(x.rid for x in res) == list(range(5))
+    sizes = [len([x for x in res if x.batch == b]) for b in sorted({x.batch for x in res})]
+    assert sum(sizes) == 5 and max(sizes) <= 2
+    assert be.max_live <= 2                         # never a second batch beside the one in flight
+    assert be.live() == 0
