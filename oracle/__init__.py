@@ -23,6 +23,12 @@ What each function follows:
     (Lemma "Adjoint-state formula for H^(1)", eqs (defv), (H1v))  -> gn_hvp
   * regulariser Gamma = alpha (Dx^T Dx + Dz^T Dz) + mu I (eqs (Gamma),
     (ThisGamma))                                          -> regulariser
+  * full Hessian product (H^(1) + H^(2) + Gamma) mt, four solves per
+    frequency and source (Lemmas for H^(1) and H^(2), eqs (Jac_exp),
+    (defujk), (I6))                                       -> hvp
+  * preconditioner P2 = Gamma(alpha0, mu) by Cholesky (eq (P2)) -> gamma_solve
+  * PCG for H rho = m' - m_FWI (eq (rho), stopping rule of the
+    preconditioning section)                               -> pcg
 
 Readings where the paper is silent (each pinned by a test in tests/):
   * corner mass weight hx*hz/4 (mean of the two triangulation directions);
@@ -308,3 +314,87 @@ def gn_hvp(g: Grid, m, omegas, sources, receivers, directions, alpha: float = 0.
     G = regulariser(g, alpha, mu)
     with_reg = out + np.array([G @ t for t in dirs]) if dirs else out
     return out, with_reg
+
+
+def hvp(g: Grid, m, omegas, d_obs, sources, receivers, directions, alpha: float = 0.0, mu: float = 0.0):
+    """Full Hessian products (H^(1) + H^(2) + Gamma) mt for each direction mt.
+
+    Follows the adjoint-state lemmas for H^(1) and H^(2) (eqs (H1v), (I6)),
+    the second-derivative formula (eqs (Jac_exp), (defujk)) and the list of
+    four solves in the discussion of the cost of a product with H, written for
+    the discrete operator: with gk = w^2 d_k + b_k i w / (2 sqrt m_k) and its
+    derivative hk = d gk / d m_k = -i w b_k / (4 m_k^{3/2}), per frequency and
+    source
+        u = A^{-1} e_s,  lambda = A^{-*} R^*(d - R u),  v = A^{-1}(g mt u),
+        z = A^{-*}(R^* R v - conj(g) mt lambda),
+        (H mt)_j += Re g_j u_j conj(z_j) - Re g_j v_j conj(lambda_j)
+                    - Re h_j mt_j u_j conj(lambda_j),
+    then Gamma mt is added.  d_obs: [n_omega][S][Nr].  Returns [n_dir][N]."""
+    m = _check_model(g, m)
+    dirs = [np.asarray(t, dtype=np.float64) for t in directions]
+    out = np.zeros((len(dirs), g.N))
+    _, b = weights(g)
+    for iw, w in enumerate(omegas):
+        F = Factor(g, m, w)
+        U = F.solve(unit_sources(g, sources))
+        eps = np.asarray(d_obs[iw]) - restrict(U, receivers)
+        Lam = F.adjoint_solve(restrict_adjoint(eps, receivers, g.N))
+        gk = grad_weight(g, m, w)[None, :]
+        hk = (-1j * w * b / (4.0 * m ** 1.5))[None, :]
+        for a, mt in enumerate(dirs):
+            V = F.solve(gk * mt[None, :] * U)
+            rhs = restrict_adjoint(restrict(V, receivers), receivers, g.N) - np.conj(gk) * mt[None, :] * Lam
+            Z = F.adjoint_solve(rhs)
+            out[a] += np.real(np.sum(gk * U * np.conj(Z), axis=0))
+            out[a] -= np.real(np.sum(gk * V * np.conj(Lam), axis=0))
+            out[a] -= np.real(np.sum(hk * mt[None, :] * U * np.conj(Lam), axis=0))
+        F.close()
+    G = regulariser(g, alpha, mu)
+    return out + np.array([G @ t for t in dirs]) if dirs else out
+
+
+def gamma_solve(g: Grid, alpha: float, mu: float, Y) -> np.ndarray:
+    """P2^{-1} y with P2 = Gamma(alpha, mu) (eq (P2)), applied through the
+    Cholesky factor of P2 as the paper does: L L^T x = y by two triangular
+    solves.  Y: [n][N] or [N]."""
+    import scipy.linalg as sl
+    P = regulariser(g, alpha, mu).toarray()
+    L = np.linalg.cholesky(P)
+    Y = np.asarray(Y, dtype=np.float64)
+    cols = np.atleast_2d(Y).T
+    X = sl.solve_triangular(L.T, sl.solve_triangular(L, cols, lower=True), lower=False)
+    return X.T.reshape(Y.shape)
+
+
+def pcg(apply_h, b, apply_pinv=None, x0=None, rtol: float = 1e-6, maxit: int = 1000):
+    """Preconditioned conjugate gradients for the Hessian system H rho = b
+    (eq (rho); the section on preconditioning the Hessian): stop once
+    ||r_n||_2 <= rtol ||r_0||_2; the start vector is all ones unless given.
+    apply_h(x) -> H x and apply_pinv(r) -> P^{-1} r act on [N] arrays.
+    Returns (x, iterations, [||r_n|| / ||r_0||])."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.ones_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    pinv = apply_pinv if apply_pinv is not None else (lambda r: r.copy())
+    r = b - apply_h(x)
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    if r0 == 0.0:
+        return x, 0, hist
+    z = pinv(r)
+    p = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < maxit:
+        q = apply_h(p)
+        step = rz / float(p @ q)
+        x = x + step * p
+        r = r - step * q
+        it += 1
+        hist.append(float(np.linalg.norm(r)) / r0)
+        if hist[-1] <= rtol:
+            break
+        z = pinv(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, hist

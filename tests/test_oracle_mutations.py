@@ -89,3 +89,35 @@ def test_gn_missing_conjugate_caught(monkeypatch):
     monkeypatch.setattr(np, "conj", lambda x: x)
     (h1, h2), _ = oracle.gn_hvp(g, w.m, w.omegas, w.sources, w.receivers, [d1, d2])
     assert abs(d2 @ h1 - d1 @ h2) > 1e-6 * abs(d2 @ h1)
+
+
+# ---------------------------------------------------- full Hessian product --
+
+def _mutant_hvp(old, new):
+    """oracle.hvp with one source fragment replaced (the planted mistake)."""
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.hvp))
+    assert src.count(old) == 1, old
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns["hvp"]
+
+
+HVP_MUTATIONS = {
+    "dropped_h_term": ("out[a] -= np.real(np.sum(hk * mt[None, :] * U * np.conj(Lam), axis=0))", "pass"),
+    "h_exponent": ("m ** 1.5", "m ** 0.5"),
+    "h_sign": ("hk = (-1j", "hk = (1j"),
+    "dropped_v_term": ("out[a] -= np.real(np.sum(gk * V * np.conj(Lam), axis=0))", "pass"),
+    "z_rhs_sign": ("- np.conj(gk) * mt[None, :] * Lam", "+ np.conj(gk) * mt[None, :] * Lam"),
+    "z_rhs_unconjugated": ("- np.conj(gk) * mt[None, :] * Lam", "- gk * mt[None, :] * Lam"),
+    "z_rhs_dropped": ("- np.conj(gk) * mt[None, :] * Lam", ""),
+    "forward_instead_of_adjoint": ("Z = F.adjoint_solve(rhs)", "Z = F.solve(rhs)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(HVP_MUTATIONS))
+def test_hvp_mutation_caught(name):
+    from tests.test_oracle_hessian import hvp_fd_error
+    old, new = HVP_MUTATIONS[name]
+    assert hvp_fd_error(_mutant_hvp(old, new)) > 1e-4
