@@ -147,6 +147,70 @@ int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega,
                 double mu, int precision, double tol, void* stream, double* hv_dev,
                 helm_info* info);
 
+/* ---- full Hessian and the Hessian system ---------------------------------
+ * A Hessian context holds the lower-level state at one model m: the factors
+ * of A(m, w) for every frequency, the wavefields u and, when data are given,
+ * the adjoint fields lambda (about 2 * n_omega * S * nx*nz * 16 bytes of HBM
+ * besides the factors), so that every product with H costs two batched
+ * solves per frequency (the four-solve count of the discussion of the cost
+ * of a product with H, u and lambda being shared by all products).
+ */
+typedef struct helm_hess_s* helm_hess_t;
+
+/* helm_hess_create: factor and solve at m.  With dobs_dev (complex128
+ * [n_omega][S][Nr]) the context gives the full Hessian
+ *     H = H^(1) + H^(2) + Gamma(alpha, mu)
+ * (lemmas "Adjoint-state formula for multiplication by H^(1)" and "... for
+ * H^(2)", eqs (H1v), (I6), (Jac_exp)); without data (NULL) it gives the
+ * Gauss-Newton H^(1) + Gamma of helm_gn_hvp.  phi_host and grad_dev
+ * (optional, data required) receive phi and grad phi as helm_misfit_grad
+ * computes them.  Sources may not coincide with receivers when data are
+ * given.  info counts the u and lambda solves.  Synchronises `stream`.
+ * *out is released with helm_hess_destroy.                                 */
+int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega,
+                     const double* omegas_host, const double* dobs_dev, int32_t S,
+                     const int32_t* src_host, int32_t Nr, const int32_t* rec_host, double alpha,
+                     double mu, int precision, double tol, void* stream, double* phi_host,
+                     double* grad_dev, helm_info* info, helm_hess_t* out);
+
+/* helm_hess_apply: hv_a = H mt_a for n_dir directions.  Per frequency and
+ * source, with g = w^2 d + b i w / (2 sqrt m) and h = dg/dm = -i w b /
+ * (4 m^{3/2}):
+ *     v = A^{-1}(g mt u),  z = A^{-*}(R^* R v - conj(g) mt lambda),
+ *     hv_j += Re g_j u_j conj(z_j) - Re g_j v_j conj(lambda_j)
+ *             - Re h_j mt_j u_j conj(lambda_j),
+ * (Gauss-Newton context: z = A^{-*} R^* R v and only the first term), then
+ * hv += Gamma mt.  mt_dev, hv_dev: doubles [n_dir][nx*nz], not
+ * overlapping; hv overwritten.  Solves use the context's precision and tol.
+ * Synchronises `stream`.  Calls on one context must not overlap.           */
+int helm_hess_apply(helm_hess_t h, int32_t n_dir, const double* mt_dev, double* hv_dev,
+                    void* stream, helm_info* info);
+
+/* helm_hess_pcg: preconditioned conjugate gradients for the Hessian system
+ * H x = b (eq (rho)) with the preconditioner P2 = Gamma(p_alpha, p_mu)
+ * (eq (P2)); p_mu <= 0 (and p_alpha = 0) runs plain CG.  x_dev holds the
+ * start vector on entry (the paper starts from all ones) and the solution on
+ * return.  Stops once ||r_n||_2 <= rtol ||r_0||_2 (r_n by the CG recurrence,
+ * r_0 = b - H x_0) or after maxit iterations.  P2^{-1} is applied exactly
+ * through the eigen-decomposition of Gamma (orthonormal DCT-II in x and z,
+ * four FP64 matrix-core products) where the paper uses a Cholesky factor:
+ * the same operator.  *iters and *relres report the iterations and the
+ * final ||r_n|| / ||r_0||.  Returns HELM_ENOCONV if the tolerance was not
+ * reached, or if p.Hp <= 0 (H not positive definite along a direction;
+ * x then holds the last iterate).  b_dev, x_dev: nx*nz doubles.           */
+int helm_hess_pcg(helm_hess_t h, const double* b_dev, double* x_dev, double p_alpha, double p_mu,
+                  double rtol, int32_t maxit, void* stream, int32_t* iters, double* relres,
+                  helm_info* info);
+
+void helm_hess_destroy(helm_hess_t h);
+
+/* helm_gamma_solve: X = Gamma(alpha, mu)^{-1} Y for n grid vectors (eq (P2)
+ * with eqs (Gamma), (ThisGamma)), alpha >= 0, mu > 0, by the DCT-II
+ * eigen-decomposition described at helm_hess_pcg.  Y_dev, X_dev: doubles
+ * [n][nx*nz]; X may equal Y.  Synchronises `stream`.                       */
+int helm_gamma_solve(const helm_grid* grid, double alpha, double mu, int32_t n, const double* Y_dev,
+                     double* X_dev, void* stream);
+
 /* ---- building blocks exposed for tests and measurement ------------------ */
 
 /* r = B - A(m, w) X (FP64, five-point form of App. A.1) and, per column,

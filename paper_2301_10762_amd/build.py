@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhelm.so")
-SOURCES = ["helm_factor.hip", "helm_sweep.hip", "helm_kernels.hip", "helm_host.hip"]
+SOURCES = ["helm_factor.hip", "helm_sweep.hip", "helm_kernels.hip", "helm_gamma.hip", "helm_host.hip"]
 ARCH = os.environ.get("HELM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

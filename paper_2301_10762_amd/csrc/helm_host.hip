@@ -29,6 +29,25 @@ struct helm_factor_s {
     hipStream_t st;   // the stream it was made on (its memory is released there)
 };
 
+// Lower-level state at one model for Hessian products (the appendix on
+// products with the Hessian): the factors of A(m, w) for every frequency,
+// the wavefields u and, when data are given, the adjoint fields lambda.
+struct helm_hess_s {
+    helm_grid g;
+    int n_omega = 0, S = 0, Nr = 0, prec = 0;
+    double tol = 0.0, alpha = 0.0, mu = 0.0;
+    int full = 0;                        // 1: H1 + H2 + Gamma (data given); 0: H1 + Gamma
+    std::vector<helm_factor_s*> F;       // one factorisation per frequency
+    std::vector<double*> U, L;           // complex128 [S][N] per frequency (L only when full)
+    int* drec = nullptr;                 // receiver nodes, device
+    double* m = nullptr;                 // device copy of the model
+    hipStream_t st = nullptr;            // stream of creation (memory is released there)
+    std::vector<std::pair<void*, size_t>> owned;
+    // P2 = Gamma(p_alpha, p_mu) tables of the last PCG call
+    double p_alpha = -1.0, p_mu = -1.0;
+    double *Cx = nullptr, *Cz = nullptr, *eig = nullptr;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -791,6 +810,343 @@ int check_nodes(const int32_t* nodes, int count, int64_t N, const char* what) {
     return HELM_OK;
 }
 
+// ------------------------------------------------------- Hessian products --
+
+template <typename T>
+int hess_own(helm_hess_s* h, T** out, size_t bytes) {
+    void* p = nullptr;
+    hipError_t e = g_cache.get(&p, bytes, h->st);
+    if (e != hipSuccess) return fail(HELM_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e));
+    h->owned.emplace_back(p, bytes);
+    *out = (T*)p;
+    return HELM_OK;
+}
+
+void hess_free(helm_hess_s* h) {
+    if (!h) return;
+    for (auto f : h->F) destroy(f);
+    for (auto& pb : h->owned) g_cache.put(pb.first, pb.second, h->st);
+    delete h;
+}
+
+// Orthonormal DCT-II matrices of sizes nx and nz and the eigenvalues of
+// Gamma(alpha, mu) on that basis, uploaded (complete on return).  Angles are
+// reduced exactly in integers before the cosine is taken.
+int gamma_tables(int nx, int nz, double alpha, double mu, double* Cx, double* Cz, double* eig, hipStream_t st) {
+    const double pi = 3.14159265358979323846;
+    auto dct = [&](int n, std::vector<double>& c) {
+        c.assign((size_t)n * n, 0.0);
+        for (int p = 0; p < n; ++p) {
+            const double sc = std::sqrt((p == 0 ? 1.0 : 2.0) / n);
+            for (int i = 0; i < n; ++i) {
+                const int64_t a = ((int64_t)p * (2 * i + 1)) % (4 * (int64_t)n);   // angle pi a / (2 n)
+                c[(size_t)p * n + i] = sc * std::cos(pi * (double)a / (2.0 * n));
+            }
+        }
+    };
+    auto lap = [&](int n, int p) {   // (n-1)^2 * 4 sin^2(pi p / (2 n))
+        const double sn = std::sin(pi * p / (2.0 * n));
+        return (double)(n - 1) * (n - 1) * 4.0 * sn * sn;
+    };
+    std::vector<double> cx, cz, ev((size_t)nx * nz);
+    dct(nx, cx);
+    dct(nz, cz);
+    for (int q = 0; q < nz; ++q)
+        for (int p = 0; p < nx; ++p) ev[(size_t)q * nx + p] = alpha * (lap(nx, p) + lap(nz, q)) + mu;
+    HIPCHECK(hipMemcpyAsync(Cx, cx.data(), sizeof(double) * cx.size(), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(Cz, cz.data(), sizeof(double) * cz.size(), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(eig, ev.data(), sizeof(double) * ev.size(), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+}
+
+void merge_info(helm_info* into, const helm_info& a) {
+    into->ir_iters = std::max(into->ir_iters, a.ir_iters);
+    into->max_relres = std::max(into->max_relres, a.max_relres);
+    into->solves += a.solves;
+}
+
+// Factor A(m, w) for every frequency and solve for u (and, with data, for
+// lambda = A^{-*} R^*(d - R u), phi and grad phi when asked for).  The
+// fields stay with the returned context; the stream is synchronised.
+int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const double* omegas_host,
+               const double* dobs_dev, int S, const int32_t* src_host, int Nr, const int32_t* rec_host, double alpha,
+               double mu, int precision, double tol, hipStream_t st, double* phi_host, double* grad_dev,
+               helm_info* info, helm_hess_s** out) {
+    *out = nullptr;
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (n_omega <= 0 || S <= 0 || Nr <= 0 || !omegas_host || !m_dev)
+        return fail(HELM_EINVAL, "bad frequency, source or receiver counts, or NULL pointers");
+    if (precision != HELM_FP64 && precision != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
+    const int64_t N = N_of(*grid);
+    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
+    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
+    const bool full = dobs_dev != nullptr;
+    if (full)
+        for (int s = 0; s < S; ++s)
+            for (int p = 0; p < Nr; ++p)
+                if (src_host[s] == rec_host[p]) return fail(HELM_EINVAL, "a source coincides with a receiver");
+    helm_hess_s* h = new helm_hess_s();
+    *out = h;
+    h->g = *grid;
+    h->n_omega = n_omega;
+    h->S = S;
+    h->Nr = Nr;
+    h->prec = precision;
+    h->tol = tol;
+    h->alpha = alpha;
+    h->mu = mu;
+    h->full = full ? 1 : 0;
+    h->st = st;
+    std::vector<helm_grid> grids(n_omega, *grid);
+    std::vector<const double*> ms(n_omega, m_dev);
+    h->F.assign(n_omega, nullptr);
+    if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, h->F.data()))) return rc;
+    h->m = h->F[0]->m;
+    Scratch sc(st);
+    int* dsrc;
+    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
+    if ((rc = hess_own(h, &h->drec, sizeof(int) * Nr))) return rc;
+    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
+    if ((rc = upload_sync(h->drec, rec_host, sizeof(int) * Nr, st))) return rc;
+    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
+    double* E;
+    if ((rc = sc.get(&E, fb))) return rc;
+    h->U.assign(n_omega, nullptr);
+    for (int w = 0; w < n_omega; ++w)
+        if ((rc = hess_own(h, &h->U[w], fb))) return rc;
+    launch_unit_sources(E, N, N, dsrc, S, st);
+    g_launches += 1;
+    // forward wavefields u = A^{-1} e_s, all frequencies in one batch
+    std::vector<SolveJob> jobs;
+    std::vector<helm_info> infos(n_omega);
+    for (int w = 0; w < n_omega; ++w) jobs.push_back({h->F[w], E, h->U[w], S, N, &infos[w]});
+    if ((rc = solve_jobs(jobs, false, tol, st))) return rc;
+    helm_info tot{};
+    tot.bad_block = tot.bad_row = -1;
+    for (auto& i1 : infos) merge_info(&tot, i1);
+    if (full) {
+        // residuals at the receivers, phi, adjoint sources R^* eps, then lambda
+        double *eps, *phip;
+        std::vector<double*> Radj(n_omega);
+        if ((rc = sc.get(&eps, sizeof(double) * 2 * (size_t)Nr * S * n_omega))) return rc;
+        if ((rc = sc.get(&phip, sizeof(double) * (size_t)S * n_omega + 8))) return rc;
+        h->L.assign(n_omega, nullptr);
+        for (int w = 0; w < n_omega; ++w) {
+            if ((rc = hess_own(h, &h->L[w], fb))) return rc;
+            if ((rc = sc.get(&Radj[w], fb))) return rc;
+        }
+        for (int w = 0; w < n_omega; ++w) {
+            launch_misfit(h->U[w], N, dobs_dev + 2 * (size_t)w * S * Nr, h->drec, Nr, S,
+                          eps + 2 * (size_t)w * S * Nr, phip + (size_t)w * S, st);
+            launch_zero(Radj[w], fb, st);
+            launch_scatter_adj(eps + 2 * (size_t)w * S * Nr, h->drec, Nr, S, Radj[w], N, st);
+            g_launches += 3;
+        }
+        std::vector<SolveJob> ajobs;
+        std::vector<helm_info> ainfos(n_omega);
+        for (int w = 0; w < n_omega; ++w) ajobs.push_back({h->F[w], Radj[w], h->L[w], S, N, &ainfos[w]});
+        if ((rc = solve_jobs(ajobs, true, tol, st))) return rc;
+        for (auto& i2 : ainfos) merge_info(&tot, i2);
+        double reg = 0.0;
+        if (grad_dev) {
+            launch_zero(grad_dev, sizeof(double) * N, st);
+            for (int w = 0; w < n_omega; ++w) launch_grad(coef_of(h->F[w]), h->U[w], N, h->L[w], N, S, grad_dev, st);
+            g_launches += 1 + n_omega;
+        }
+        if (grad_dev && (alpha != 0.0 || mu != 0.0)) {
+            const int nblk = (int)((N + 255) / 256);
+            double *part, *q;
+            if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
+            if ((rc = sc.get(&q, sizeof(double)))) return rc;
+            launch_gamma(m_dev, grid->nx, grid->nz, alpha, mu, grad_dev, part, nblk, st);
+            launch_sum_scalar(part, nblk, q, st);
+            g_launches += 2;
+            HIPCHECK(hipMemcpyAsync(&reg, q, sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        if (phi_host) {
+            std::vector<double> hp((size_t)S * n_omega);
+            HIPCHECK(hipMemcpyAsync(hp.data(), phip, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            double phi = 0.0;
+            for (double v : hp) phi += v;
+            *phi_host = phi + 0.5 * reg;
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    if (info) *info = tot;
+    return HELM_OK;
+}
+
+// hv_a = H mt_a for n_dir directions: per frequency v = A^{-1}(g mt u) for
+// every source and direction, then
+//   z = A^{-*}(R^* R v - conj(g) mt lambda)   (full) or A^{-*}(R^* R v),
+//   hv += Re g u conj(z) - Re g v conj(lambda) - Re h mt u conj(lambda)  (full)
+//   or    Re g u conj(z),
+// all frequencies of a stage batched into one solve; finally hv += Gamma mt.
+// Synchronises the stream.
+int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStream_t st, helm_info* info) {
+    const int64_t N = N_of(h->g);
+    const int S = h->S, nw = h->n_omega, cols = n_dir * S;
+    const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
+    Scratch sc(st);
+    std::vector<double*> W(nw), V(nw), Z(nw);
+    int rc;
+    for (int w = 0; w < nw; ++w) {
+        if ((rc = sc.get(&W[w], vb))) return rc;
+        if ((rc = sc.get(&V[w], vb))) return rc;
+        if ((rc = sc.get(&Z[w], vb))) return rc;
+    }
+    for (int w = 0; w < nw; ++w) launch_gn_rhs(coef_of(h->F[w]), h->U[w], N, S, mt, n_dir, W[w], N, st);
+    g_launches += nw;
+    std::vector<SolveJob> j1, j2;
+    std::vector<helm_info> i1(nw), i2(nw);
+    for (int w = 0; w < nw; ++w) j1.push_back({h->F[w], W[w], V[w], cols, N, &i1[w]});
+    if ((rc = solve_jobs(j1, false, h->tol, st))) return rc;
+    // W now holds the right-hand side of the z solve
+    for (int w = 0; w < nw; ++w) {
+        if (h->full) launch_zeta_rhs(coef_of(h->F[w]), h->L[w], N, S, mt, n_dir, W[w], N, st);
+        else launch_zero(W[w], vb, st);
+        launch_sample_scatter(V[w], N, h->drec, h->Nr, cols, W[w], N, st);
+        g_launches += 2;
+    }
+    for (int w = 0; w < nw; ++w) j2.push_back({h->F[w], W[w], Z[w], cols, N, &i2[w]});
+    if ((rc = solve_jobs(j2, true, h->tol, st))) return rc;
+    launch_zero(hv, sizeof(double) * N * n_dir, st);
+    for (int w = 0; w < nw; ++w) {
+        if (h->full)
+            launch_hv_full(coef_of(h->F[w]), h->U[w], h->L[w], N, S, V[w], Z[w], N, mt, n_dir, hv, st);
+        else
+            launch_hv(coef_of(h->F[w]), h->U[w], N, S, Z[w], N, n_dir, hv, N, st);
+    }
+    g_launches += 1 + nw;
+    if (h->alpha != 0.0 || h->mu != 0.0) {
+        const int nblk = (int)((N + 255) / 256);
+        double* part;
+        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
+        for (int a = 0; a < n_dir; ++a)
+            launch_gamma(mt + (size_t)a * N, h->g.nx, h->g.nz, h->alpha, h->mu, hv + (size_t)a * N, part, nblk, st);
+        g_launches += n_dir;
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    if (info) {
+        helm_info tot{};
+        tot.bad_block = tot.bad_row = -1;
+        for (int w = 0; w < nw; ++w) {
+            merge_info(&tot, i1[w]);
+            merge_info(&tot, i2[w]);
+        }
+        *info = tot;
+    }
+    return HELM_OK;
+}
+
+// Preconditioned conjugate gradients for H x = b (eq (rho)) with P2 =
+// Gamma(p_alpha, p_mu) (eq (P2); none when p_mu <= 0), stopping once
+// ||r_n|| <= rtol ||r_0||.  x holds the start vector on entry.  The scalars
+// of each iteration come back to the host (three small reads against two
+// batched solves per frequency for the product with H).
+int hess_pcg(helm_hess_s* h, const double* b, double* x, double p_alpha, double p_mu, double rtol, int maxit,
+             hipStream_t st, int32_t* iters, double* relres, helm_info* info) {
+    if (!b || !x || maxit < 0 || !(rtol >= 0.0)) return fail(HELM_EINVAL, "bad pcg arguments");
+    const bool prec = p_mu > 0.0;
+    if (!prec && p_alpha != 0.0) return fail(HELM_EINVAL, "P2 = Gamma(alpha, mu) needs mu > 0");
+    if (prec && !(p_alpha >= 0.0)) return fail(HELM_EINVAL, "P2 = Gamma(alpha, mu) needs alpha >= 0");
+    const int64_t N = N_of(h->g);
+    const int nx = h->g.nx, nz = h->g.nz;
+    Scratch sc(st);
+    double *r, *z, *p, *q, *part, *scal, *T1 = nullptr, *T2 = nullptr;
+    int rc;
+    if ((rc = sc.get(&r, sizeof(double) * N))) return rc;
+    if ((rc = sc.get(&p, sizeof(double) * N))) return rc;
+    if ((rc = sc.get(&q, sizeof(double) * N))) return rc;
+    if ((rc = sc.get(&part, sizeof(double) * dot_blocks(N)))) return rc;
+    if ((rc = sc.get(&scal, sizeof(double) * 4))) return rc;
+    z = r;
+    if (prec) {
+        if ((rc = sc.get(&z, sizeof(double) * N))) return rc;
+        if ((rc = sc.get(&T1, sizeof(double) * N))) return rc;
+        if ((rc = sc.get(&T2, sizeof(double) * N))) return rc;
+        if (h->p_alpha != p_alpha || h->p_mu != p_mu || !h->Cx) {
+            if (!h->Cx) {
+                if ((rc = hess_own(h, &h->Cx, sizeof(double) * nx * nx))) return rc;
+                if ((rc = hess_own(h, &h->Cz, sizeof(double) * nz * nz))) return rc;
+                if ((rc = hess_own(h, &h->eig, sizeof(double) * N))) return rc;
+            }
+            // the tables were allocated on the creation stream
+            HIPCHECK(hipStreamSynchronize(h->st));
+            if ((rc = gamma_tables(nx, nz, p_alpha, p_mu, h->Cx, h->Cz, h->eig, st))) return rc;
+            h->p_alpha = p_alpha;
+            h->p_mu = p_mu;
+        }
+    }
+    auto dot = [&](const double* u, const double* v, double* out) -> int {
+        launch_dot(u, v, N, part, scal, st);
+        g_launches += 2;
+        HIPCHECK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        return HELM_OK;
+    };
+    auto precondition = [&]() {
+        if (prec) {
+            launch_gamma_solve(h->Cx, h->Cz, h->eig, nx, nz, 1, r, z, T1, T2, st);
+            g_launches += 4;
+        }
+    };
+    helm_info tot{}, ia{};
+    tot.bad_block = tot.bad_row = -1;
+    // r = b - H x
+    if ((rc = hess_apply(h, 1, x, q, st, &ia))) return rc;
+    merge_info(&tot, ia);
+    launch_lincomb(r, 1.0, b, -1.0, q, N, st);
+    g_launches += 1;
+    double rr0 = 0.0, rr = 0.0, rz = 0.0, pq = 0.0;
+    if ((rc = dot(r, r, &rr0))) return rc;
+    int it = 0;
+    double rel = rr0 > 0.0 ? 1.0 : 0.0;
+    bool indefinite = false;
+    if (rr0 > 0.0) {
+        precondition();
+        launch_lincomb(p, 1.0, z, 0.0, z, N, st);
+        g_launches += 1;
+        if ((rc = dot(r, z, &rz))) return rc;
+        while (it < maxit) {
+            if ((rc = hess_apply(h, 1, p, q, st, &ia))) return rc;
+            merge_info(&tot, ia);
+            if ((rc = dot(p, q, &pq))) return rc;
+            if (!(pq > 0.0)) {
+                indefinite = true;
+                break;
+            }
+            const double a = rz / pq;
+            launch_lincomb(x, 1.0, x, a, p, N, st);
+            launch_lincomb(r, 1.0, r, -a, q, N, st);
+            g_launches += 2;
+            if ((rc = dot(r, r, &rr))) return rc;
+            ++it;
+            rel = std::sqrt(rr / rr0);
+            if (rel <= rtol) break;
+            precondition();
+            double rz1 = 0.0;
+            if ((rc = dot(r, z, &rz1))) return rc;
+            launch_lincomb(p, 1.0, z, rz1 / rz, p, N, st);
+            g_launches += 1;
+            rz = rz1;
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (info) *info = tot;
+    if (indefinite) return fail(HELM_ENOCONV, "p.Hp <= 0: the Hessian is not positive definite along a search direction");
+    if (!(rel <= rtol)) return fail(HELM_ENOCONV, "PCG stopped at relative residual " + std::to_string(rel));
+    return HELM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI ==
@@ -916,175 +1272,86 @@ int helm_misfit_grad(const helm_grid* grid, const double* m_dev, int32_t n_omega
                      const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
                      double alpha, double mu, int precision, double tol, void* stream, double* phi_host,
                      double* grad_dev, helm_info* info) {
-    int rc = check_grid(grid);
-    if (rc) return rc;
-    if (n_omega <= 0 || S <= 0 || Nr <= 0 || !omegas_host || !dobs_dev || !phi_host || !grad_dev || !m_dev)
-        return fail(HELM_EINVAL, "bad misfit_grad arguments");
-    const int64_t N = N_of(*grid);
-    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
-    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
-    for (int s = 0; s < S; ++s)
-        for (int p = 0; p < Nr; ++p)
-            if (src_host[s] == rec_host[p]) return fail(HELM_EINVAL, "a source coincides with a receiver");
-    hipStream_t st = S_(stream);
-    std::vector<helm_grid> grids(n_omega, *grid);
-    std::vector<const double*> ms(n_omega, m_dev);
-    std::vector<helm_factor_t> F(n_omega, nullptr);
-    if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, F.data()))) return rc;
-    struct Guard {
-        std::vector<helm_factor_t>& F;
-        ~Guard() {
-            for (auto f : F) destroy(f);
-        }
-    } guard{F};
-    Scratch sc(st);
-    int *dsrc, *drec;
-    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
-    if ((rc = sc.get(&drec, sizeof(int) * Nr))) return rc;
-    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
-    if ((rc = upload_sync(drec, rec_host, sizeof(int) * Nr, st))) return rc;
-    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
-    double *E, *eps, *phip;
-    std::vector<double*> U(n_omega), L(n_omega), Radj(n_omega);
-    if ((rc = sc.get(&E, fb))) return rc;
-    if ((rc = sc.get(&eps, sizeof(double) * 2 * (size_t)Nr * S * n_omega))) return rc;
-    if ((rc = sc.get(&phip, sizeof(double) * (size_t)S * n_omega + 8))) return rc;
-    for (int w = 0; w < n_omega; ++w) {
-        if ((rc = sc.get(&U[w], fb))) return rc;
-        if ((rc = sc.get(&L[w], fb))) return rc;
-        if ((rc = sc.get(&Radj[w], fb))) return rc;
-    }
-    launch_unit_sources(E, N, N, dsrc, S, st);
-    // forward wavefields u = A^{-1} e_s for all frequencies
-    std::vector<SolveJob> jobs;
-    std::vector<helm_info> infos(n_omega);
-    for (int w = 0; w < n_omega; ++w) jobs.push_back({F[w], E, U[w], S, N, &infos[w]});
-    if ((rc = solve_jobs(jobs, false, precision == HELM_FP32_IR ? tol : tol, st))) return rc;
-    // residuals at the receivers, phi, and the adjoint sources R^* eps
-    for (int w = 0; w < n_omega; ++w) {
-        launch_misfit(U[w], N, dobs_dev + 2 * (size_t)w * S * Nr, drec, Nr, S, eps + 2 * (size_t)w * S * Nr,
-                      phip + (size_t)w * S, st);
-        launch_zero(Radj[w], fb, st);
-        launch_scatter_adj(eps + 2 * (size_t)w * S * Nr, drec, Nr, S, Radj[w], N, st);
-        g_launches += 3;
-    }
-    // adjoint wavefields lambda = A^{-*} R^* eps
-    std::vector<SolveJob> ajobs;
-    std::vector<helm_info> ainfos(n_omega);
-    for (int w = 0; w < n_omega; ++w) ajobs.push_back({F[w], Radj[w], L[w], S, N, &ainfos[w]});
-    if ((rc = solve_jobs(ajobs, true, tol, st))) return rc;
-    launch_zero(grad_dev, sizeof(double) * N, st);
-    for (int w = 0; w < n_omega; ++w) launch_grad(coef_of(F[w]), U[w], N, L[w], N, S, grad_dev, st);
-    g_launches += 1 + n_omega;
-    double reg = 0.0;
-    if (alpha != 0.0 || mu != 0.0) {
-        const int nblk = (int)((N + 255) / 256);
-        double *part, *q;
-        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
-        if ((rc = sc.get(&q, sizeof(double)))) return rc;
-        launch_gamma(m_dev, grid->nx, grid->nz, alpha, mu, grad_dev, part, nblk, st);
-        launch_sum_scalar(part, nblk, q, st);
-        g_launches += 2;
-        HIPCHECK(hipMemcpyAsync(&reg, q, sizeof(double), hipMemcpyDeviceToHost, st));
-    }
-    std::vector<double> hp((size_t)S * n_omega);
-    HIPCHECK(hipMemcpyAsync(hp.data(), phip, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    double phi = 0.0;
-    for (double v : hp) phi += v;
-    *phi_host = phi + 0.5 * reg;
-    if (info) {
-        info->ir_iters = 0;
-        info->max_relres = 0.0;
-        info->bad_block = info->bad_row = -1;
-        info->solves = 0;
-        for (int w = 0; w < n_omega; ++w) {
-            info->ir_iters = std::max(info->ir_iters, std::max(infos[w].ir_iters, ainfos[w].ir_iters));
-            info->max_relres = std::max(info->max_relres, std::max(infos[w].max_relres, ainfos[w].max_relres));
-            info->solves += infos[w].solves + ainfos[w].solves;
-        }
-    }
-    HIPCHECK(hipGetLastError());
-    return HELM_OK;
+    if (!dobs_dev || !phi_host || !grad_dev) return fail(HELM_EINVAL, "bad misfit_grad arguments");
+    helm_hess_s* h = nullptr;
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, alpha, mu, precision,
+                        tol, S_(stream), phi_host, grad_dev, info, &h);
+    hess_free(h);
+    return rc;
 }
 
 int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host, int32_t S,
                 const int32_t* src_host, int32_t Nr, const int32_t* rec_host, int32_t n_dir, const double* mt_dev,
                 double alpha, double mu, int precision, double tol, void* stream, double* hv_dev, helm_info* info) {
+    if (n_dir <= 0 || !mt_dev || !hv_dev) return fail(HELM_EINVAL, "bad gn_hvp arguments");
+    helm_hess_s* h = nullptr;
+    helm_info i0{};
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, nullptr, S, src_host, Nr, rec_host, alpha, mu, precision,
+                        tol, S_(stream), nullptr, nullptr, &i0, &h);
+    if (rc == HELM_OK) rc = hess_apply(h, n_dir, mt_dev, hv_dev, S_(stream), info);
+    if (rc == HELM_OK && info) {
+        info->solves += i0.solves;
+        info->ir_iters = std::max(info->ir_iters, i0.ir_iters);
+        info->max_relres = std::max(info->max_relres, i0.max_relres);
+    }
+    hess_free(h);
+    return rc;
+}
+
+int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host,
+                     const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
+                     double alpha, double mu, int precision, double tol, void* stream, double* phi_host,
+                     double* grad_dev, helm_info* info, helm_hess_t* out) {
+    if (!out) return fail(HELM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!dobs_dev && (phi_host || grad_dev)) return fail(HELM_EINVAL, "phi and grad need data");
+    helm_hess_s* h = nullptr;
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, alpha, mu, precision,
+                        tol, S_(stream), phi_host, grad_dev, info, &h);
+    if (rc) {
+        hess_free(h);
+        return rc;
+    }
+    *out = h;
+    return HELM_OK;
+}
+
+int helm_hess_apply(helm_hess_t h, int32_t n_dir, const double* mt_dev, double* hv_dev, void* stream,
+                    helm_info* info) {
+    if (!h) return fail(HELM_EINVAL, "Hessian handle is NULL");
+    if (n_dir <= 0 || !mt_dev || !hv_dev) return fail(HELM_EINVAL, "bad hess_apply arguments");
+    return hess_apply(h, n_dir, mt_dev, hv_dev, S_(stream), info);
+}
+
+int helm_hess_pcg(helm_hess_t h, const double* b_dev, double* x_dev, double p_alpha, double p_mu, double rtol,
+                  int32_t maxit, void* stream, int32_t* iters, double* relres, helm_info* info) {
+    if (!h) return fail(HELM_EINVAL, "Hessian handle is NULL");
+    return hess_pcg(h, b_dev, x_dev, p_alpha, p_mu, rtol, maxit, S_(stream), iters, relres, info);
+}
+
+void helm_hess_destroy(helm_hess_t h) { hess_free(h); }
+
+int helm_gamma_solve(const helm_grid* grid, double alpha, double mu, int32_t n, const double* Y_dev, double* X_dev,
+                     void* stream) {
     int rc = check_grid(grid);
     if (rc) return rc;
-    if (n_omega <= 0 || S <= 0 || Nr <= 0 || n_dir <= 0 || !omegas_host || !mt_dev || !hv_dev || !m_dev)
-        return fail(HELM_EINVAL, "bad gn_hvp arguments");
-    const int64_t N = N_of(*grid);
-    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
-    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
+    if (n <= 0 || !Y_dev || !X_dev) return fail(HELM_EINVAL, "bad gamma_solve arguments");
+    if (!(mu > 0.0) || !(alpha >= 0.0) || !std::isfinite(alpha) || !std::isfinite(mu))
+        return fail(HELM_EINVAL, "Gamma(alpha, mu) needs alpha >= 0 and mu > 0");
     hipStream_t st = S_(stream);
-    std::vector<helm_grid> grids(n_omega, *grid);
-    std::vector<const double*> ms(n_omega, m_dev);
-    std::vector<helm_factor_t> F(n_omega, nullptr);
-    if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, F.data()))) return rc;
-    struct Guard {
-        std::vector<helm_factor_t>& F;
-        ~Guard() {
-            for (auto f : F) destroy(f);
-        }
-    } guard{F};
+    const int64_t N = N_of(*grid);
     Scratch sc(st);
-    int *dsrc, *drec;
-    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
-    if ((rc = sc.get(&drec, sizeof(int) * Nr))) return rc;
-    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
-    if ((rc = upload_sync(drec, rec_host, sizeof(int) * Nr, st))) return rc;
-    const int cols = n_dir * S;
-    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
-    const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
-    double *E, *U, *Vr, *V, *RV, *Z;
-    if ((rc = sc.get(&E, fb))) return rc;
-    if ((rc = sc.get(&U, fb))) return rc;
-    if ((rc = sc.get(&Vr, vb))) return rc;
-    if ((rc = sc.get(&V, vb))) return rc;
-    if ((rc = sc.get(&RV, vb))) return rc;
-    if ((rc = sc.get(&Z, vb))) return rc;
-    launch_unit_sources(E, N, N, dsrc, S, st);
-    launch_zero(hv_dev, sizeof(double) * N * n_dir, st);
-    g_launches += 2;
-    int64_t solves = 0;
-    int ir = 0;
-    double worst = 0.0;
-    for (int w = 0; w < n_omega; ++w) {
-        helm_info i1, i2, i3;
-        std::vector<SolveJob> j1{{F[w], E, U, S, N, &i1}};
-        if ((rc = solve_jobs(j1, false, tol, st))) return rc;
-        launch_gn_rhs(coef_of(F[w]), U, N, S, mt_dev, n_dir, Vr, N, st);
-        std::vector<SolveJob> j2{{F[w], Vr, V, cols, N, &i2}};
-        if ((rc = solve_jobs(j2, false, tol, st))) return rc;
-        launch_zero(RV, vb, st);
-        launch_sample_scatter(V, N, drec, Nr, cols, RV, N, st);
-        std::vector<SolveJob> j3{{F[w], RV, Z, cols, N, &i3}};
-        if ((rc = solve_jobs(j3, true, tol, st))) return rc;
-        launch_hv(coef_of(F[w]), U, N, S, Z, N, n_dir, hv_dev, N, st);
-        g_launches += 4;
-        solves += i1.solves + i2.solves + i3.solves;
-        ir = std::max(ir, std::max(i1.ir_iters, std::max(i2.ir_iters, i3.ir_iters)));
-        worst = std::max(worst, std::max(i1.max_relres, std::max(i2.max_relres, i3.max_relres)));
-    }
-    if (alpha != 0.0 || mu != 0.0) {
-        const int nblk = (int)((N + 255) / 256);
-        double* part;
-        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
-        for (int a = 0; a < n_dir; ++a)
-            launch_gamma(mt_dev + (size_t)a * N, grid->nx, grid->nz, alpha, mu, hv_dev + (size_t)a * N, part, nblk,
-                         st);
-        g_launches += n_dir;
-    }
-    HIPCHECK(hipStreamSynchronize(st));
-    if (info) {
-        info->ir_iters = ir;
-        info->max_relres = worst;
-        info->bad_block = info->bad_row = -1;
-        info->solves = solves;
-    }
+    double *Cx, *Cz, *eig, *T1, *T2;
+    if ((rc = sc.get(&Cx, sizeof(double) * grid->nx * grid->nx))) return rc;
+    if ((rc = sc.get(&Cz, sizeof(double) * grid->nz * grid->nz))) return rc;
+    if ((rc = sc.get(&eig, sizeof(double) * N))) return rc;
+    if ((rc = sc.get(&T1, sizeof(double) * N * n))) return rc;
+    if ((rc = sc.get(&T2, sizeof(double) * N * n))) return rc;
+    if ((rc = gamma_tables(grid->nx, grid->nz, alpha, mu, Cx, Cz, eig, st))) return rc;
+    launch_gamma_solve(Cx, Cz, eig, grid->nx, grid->nz, n, Y_dev, X_dev, T1, T2, st);
+    g_launches += 4;
     HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
     return HELM_OK;
 }
 

@@ -155,6 +155,18 @@ void launch_sample_scatter(const double* V, int64_t ldv, const int* rec, int Nr,
                            int64_t ldr, hipStream_t st);
 void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz,
                int n_dir, double* hv, int64_t N, hipStream_t st);
+void launch_zeta_rhs(const Coef& cf, const double* L, int64_t ldl, int S, const double* mt, int n_dir, double* W,
+                     int64_t ldw, hipStream_t st);
+void launch_hv_full(const Coef& cf, const double* U, const double* L, int64_t ldu, int S, const double* V,
+                    const double* Z, int64_t ldz, const double* mt, int n_dir, double* hv, hipStream_t st);
+int dot_blocks(int64_t n);
+void launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t st);
+void launch_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t st);
+// Gamma(alpha, mu)^{-1} on nvec grid vectors by its eigen-decomposition:
+// Cx (nx x nx) and Cz (nz x nz) orthonormal DCT-II matrices, eig (nz x nx)
+// the eigenvalues; T1, T2 are nvec * nx * nz scratch; X may equal Y.
+void launch_gamma_solve(const double* Cx, const double* Cz, const double* eig, int nx, int nz, int nvec,
+                        const double* Y, double* X, double* T1, double* T2, hipStream_t st);
 void launch_gamma(const double* m, int nx, int nz, double alpha, double mu, double* g, double* part,
                   int nblk, hipStream_t st);
 void launch_sum_scalar(const double* part, int n, double* out, hipStream_t st);

@@ -176,14 +176,19 @@ __global__ void k_scatter_adj(const double2* eps, const int* rec, int Nr, int S,
     }
 }
 
-// nodal weight of G_{m,w}(beta_k .): w^2 d_k + b_k i w / (2 sqrt m_k)
-__device__ __forceinline__ double2 grad_weight(const Coef& c, int i, int j) {
-    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
+// boundary weight b_k: half the length of each boundary edge at node k
+__device__ __forceinline__ double bnd_weight(const Coef& c, int i, int j) {
     double bnd = 0.0;
     if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
     if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
+    return bnd;
+}
+
+// nodal weight of G_{m,w}(beta_k .): w^2 d_k + b_k i w / (2 sqrt m_k)
+__device__ __forceinline__ double2 grad_weight(const Coef& c, int i, int j) {
+    double mass = c.hx * c.hz * half_at_ends(i, c.nx) * half_at_ends(j, c.nz);
     double mk_ = c.m[(size_t)j * c.nx + i];
-    return make_double2(c.omega * c.omega * mass, c.omega * bnd / (2.0 * sqrt(mk_)));
+    return make_double2(c.omega * c.omega * mass, c.omega * bnd_weight(c, i, j) / (2.0 * sqrt(mk_)));
 }
 
 // g_k += -Re sum_s wk u_{s,k} conj(l_{s,k})
@@ -243,6 +248,68 @@ __global__ void k_hv(Coef cf, const double2* U, int64_t ldu, int S, const double
         si += u.y * z.x - u.x * z.y;
     }
     hv[(size_t)a * N + k] += wk.x * sr - wk.y * si;
+}
+
+// W[(a*S + s)] = -conj(wk) * mt_a[k] * l_s[k]: the second-order part of the
+// right-hand side of the last adjoint solve of a Hessian product (the
+// receiver part R^* R v is added onto it afterwards)
+__global__ void k_zeta_rhs(Coef cf, const double2* L, int64_t ldl, int S, const double* mt, double2* W,
+                           int64_t ldw) {
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    const int col = blockIdx.y;
+    const int a = col / S, s = col % S;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double2 wk = grad_weight(cf, (int)(k % cf.nx), (int)(k / cf.nx));
+    double2 l = L[(size_t)s * ldl + k];
+    double t = mt[(size_t)a * N + k];
+    // -(wr - i wi)(lr + i li) t
+    W[(size_t)col * ldw + k] = make_double2(-t * (wk.x * l.x + wk.y * l.y), -t * (wk.x * l.y - wk.y * l.x));
+}
+
+// Full Hessian product, one frequency:
+// hv_a[k] += Re wk sum_s (u conj z - v conj l) - mt_a[k] Re hk sum_s u conj l,
+// hk = d wk / d m_k = -i w b_k / (4 m_k^{3/2})
+__global__ __launch_bounds__(256) void k_hv_full(Coef cf, const double2* U, const double2* L, int64_t ldu, int S,
+                                                 const double2* V, const double2* Z, int64_t ldz, const double* mt,
+                                                 double* hv) {
+    const int64_t N = (int64_t)cf.nx * cf.nz;
+    const int a = blockIdx.y;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int i = (int)(k % cf.nx), j = (int)(k / cf.nx);
+    double2 wk = grad_weight(cf, i, j);
+    double ar = 0.0, ai = 0.0;   // sum_s u conj z - v conj l
+    double pi = 0.0;             // Im sum_s u conj l
+    for (int s = 0; s < S; ++s) {
+        const size_t o = (size_t)s * ldu + k, oz = (size_t)(a * S + s) * ldz + k;
+        double2 u = U[o], l = L[o], v = V[oz], z = Z[oz];
+        ar += u.x * z.x + u.y * z.y - (v.x * l.x + v.y * l.y);
+        ai += u.y * z.x - u.x * z.y - (v.y * l.x - v.x * l.y);
+        pi += u.y * l.x - u.x * l.y;
+    }
+    const double mk_ = cf.m[k];
+    const double hi = -cf.omega * bnd_weight(cf, i, j) / (4.0 * mk_ * sqrt(mk_));   // hk = i hi
+    hv[(size_t)a * N + k] += (wk.x * ar - wk.y * ai) + mt[(size_t)a * N + k] * hi * pi;
+}
+
+// partial sums of x . y, one per 256-thread block
+__global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, int64_t n, double* part) {
+    __shared__ double sq[256];
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    sq[threadIdx.x] = k < n ? x[k] * y[k] : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sq[threadIdx.x] += sq[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
+}
+
+// out = a x + b y (out may be x or y)
+__global__ void k_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = a * x[k] + b * y[k];
 }
 
 // g += Gamma m and partial sums of m^T Gamma m, Gamma = alpha (Dx^T Dx + Dz^T Dz) + mu I,
@@ -359,6 +426,26 @@ void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double
                double* hv, int64_t N, hipStream_t st) {
     hipLaunchKernelGGL(k_hv, dim3(grid1(N).x, n_dir), dim3(256), 0, st, cf, (const double2*)U, ldu, S,
                        (const double2*)Z, ldz, n_dir, hv);
+}
+void launch_zeta_rhs(const Coef& cf, const double* L, int64_t ldl, int S, const double* mt, int n_dir, double* W,
+                     int64_t ldw, hipStream_t st) {
+    hipLaunchKernelGGL(k_zeta_rhs, dim3(grid1((int64_t)cf.nx * cf.nz).x, n_dir * S), dim3(256), 0, st, cf,
+                       (const double2*)L, ldl, S, mt, (double2*)W, ldw);
+}
+void launch_hv_full(const Coef& cf, const double* U, const double* L, int64_t ldu, int S, const double* V,
+                    const double* Z, int64_t ldz, const double* mt, int n_dir, double* hv, hipStream_t st) {
+    hipLaunchKernelGGL(k_hv_full, dim3(grid1((int64_t)cf.nx * cf.nz).x, n_dir), dim3(256), 0, st, cf,
+                       (const double2*)U, (const double2*)L, ldu, S, (const double2*)V, (const double2*)Z, ldz, mt,
+                       hv);
+}
+int dot_blocks(int64_t n) { return (int)((n + 255) / 256); }
+void launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t st) {
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(256), 0, st, x, y, n, part);
+    hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(64), 0, st, part, nb, out);
+}
+void launch_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lincomb, grid1(n), dim3(256), 0, st, out, a, x, b, y, n);
 }
 void launch_gamma(const double* m, int nx, int nz, double alpha, double mu, double* g, double* part, int nblk,
                   hipStream_t st) {

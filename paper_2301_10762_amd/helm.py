@@ -106,6 +106,14 @@ def lib():
                                    ctypes.POINTER(i32), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp, I]
     L.helm_gn_hvp.argtypes = [G, _vp, i32, ctypes.POINTER(f64), i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
                               i32, _vp, f64, f64, ctypes.c_int, f64, _vp, _vp, I]
+    L.helm_hess_create.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
+                                   ctypes.POINTER(i32), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp,
+                                   I, ctypes.POINTER(_vp)]
+    L.helm_hess_apply.argtypes = [_vp, i32, _vp, _vp, _vp, I]
+    L.helm_hess_pcg.argtypes = [_vp, _vp, _vp, f64, f64, f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), I]
+    L.helm_hess_destroy.argtypes = [_vp]
+    L.helm_hess_destroy.restype = None
+    L.helm_gamma_solve.argtypes = [G, f64, f64, i32, _vp, _vp, _vp]
     L.helm_residual.argtypes = [G, _vp, f64, ctypes.c_int, _vp, _vp, _vp, i32, i64, _vp, _vp]
     L.helm_tile_inverse.argtypes = [i32, i32, ctypes.c_int, _vp, _vp, _vp]
     L.helm_set_tile_pivoting.argtypes = [ctypes.c_int]
@@ -124,7 +132,7 @@ def lib():
     L.helm_last_error.restype = ctypes.c_char_p
     for name in ("helm_factor", "helm_factor_batch", "helm_factor_bytes", "helm_solve", "helm_adjoint_solve",
                  "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
-                 "helm_mfma_probe"):
+                 "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -343,6 +351,90 @@ def gn_hvp(grid: Grid, m, omegas, sources, receivers, directions, alpha: float =
                              mt.shape[0], _ptr(mt), float(alpha), float(mu), _PREC[precision], float(tol),
                              _stream(stream), _ptr(hv), ctypes.byref(info)))
     return hv, Info.of(info)
+
+
+class Hessian:
+    """Lower-level state at one model for products with the Hessian of phi
+    (helm_hess_create): with d_obs ([n_omega][S][Nr] complex) the full
+    H = H^(1) + H^(2) + Gamma, without it the Gauss-Newton H^(1) + Gamma.
+    with_grad=True also returns phi and grad phi (data required)."""
+
+    def __init__(self, grid: Grid, m, omegas, sources, receivers, d_obs=None, alpha: float = 0.0, mu: float = 0.0,
+                 precision="fp64", tol: float = 0.0, stream=None, with_grad: bool = False):
+        torch = _torch()
+        self.grid = grid
+        self.h = None
+        md = _dev_f64(m, grid.N)
+        n_omega = len(omegas)
+        src, psrc = _i32(sources)
+        rec, prec = _i32(receivers)
+        dd = None
+        if d_obs is not None:
+            dd = _dev_c128(d_obs)
+            if tuple(dd.shape) != (n_omega, len(src), len(rec)):
+                raise ValueError("d_obs must be [n_omega][S][Nr]")
+        elif with_grad:
+            raise ValueError("phi and grad need data")
+        warr = (ctypes.c_double * n_omega)(*[float(w) for w in omegas])
+        phi = ctypes.c_double(0.0)
+        self.grad = torch.empty(grid.N, dtype=torch.float64, device="cuda") if with_grad else None
+        info = _Info()
+        h = ctypes.c_void_p()
+        _check(lib().helm_hess_create(ctypes.byref(grid.c()), _ptr(md), n_omega, warr,
+                                      _ptr(dd) if dd is not None else None, len(src), psrc, len(rec), prec,
+                                      float(alpha), float(mu), _PREC[precision], float(tol), _stream(stream),
+                                      ctypes.byref(phi) if with_grad else None,
+                                      _ptr(self.grad) if with_grad else None, ctypes.byref(info), ctypes.byref(h)))
+        self.h = h
+        self.phi = float(phi.value) if with_grad else None
+        self.info = Info.of(info)
+
+    def apply(self, directions, stream=None):
+        """H mt for each row of `directions` ([n_dir][N] or [N])."""
+        torch = _torch()
+        mt = _dev_f64(directions).reshape(-1, self.grid.N).contiguous()
+        hv = torch.empty_like(mt)
+        info = _Info()
+        _check(lib().helm_hess_apply(self.h, mt.shape[0], _ptr(mt), _ptr(hv), _stream(stream), ctypes.byref(info)))
+        return hv, Info.of(info)
+
+    def pcg(self, b, x0=None, prec_alpha: float = 0.0, prec_mu: float = 0.0, rtol: float = 1e-6,
+            maxit: int = 1000, stream=None):
+        """PCG for H x = b with P2 = Gamma(prec_alpha, prec_mu) (none when
+        prec_mu <= 0); start vector all ones unless x0 is given.  Returns
+        (x, iterations, final ||r|| / ||r0||, info)."""
+        torch = _torch()
+        bd = _dev_f64(b, self.grid.N).contiguous()
+        x = (torch.ones(self.grid.N, dtype=torch.float64, device="cuda") if x0 is None
+             else _dev_f64(x0, self.grid.N).clone())
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        info = _Info()
+        _check(lib().helm_hess_pcg(self.h, _ptr(bd), _ptr(x), float(prec_alpha), float(prec_mu), float(rtol),
+                                   int(maxit), _stream(stream), ctypes.byref(it), ctypes.byref(rel),
+                                   ctypes.byref(info)))
+        return x, int(it.value), float(rel.value), Info.of(info)
+
+    def close(self):
+        if self.h:
+            lib().helm_hess_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gamma_solve(grid: Grid, alpha: float, mu: float, Y, stream=None):
+    """Gamma(alpha, mu)^{-1} Y for each row of Y (the P2 preconditioner)."""
+    torch = _torch()
+    Yd = _dev_f64(Y).reshape(-1, grid.N).contiguous()
+    X = torch.empty_like(Yd)
+    _check(lib().helm_gamma_solve(ctypes.byref(grid.c()), float(alpha), float(mu), Yd.shape[0], _ptr(Yd), _ptr(X),
+                                  _stream(stream)))
+    return X
 
 
 def residual(grid: Grid, m, omega: float, B, X, adjoint: bool = False, stream=None):

@@ -47,3 +47,41 @@ def test_host_side_argument_checks_without_gpu():
     assert L.helm_factor_bytes(ctypes.byref(g), 1, ctypes.byref(out)) == 0
     assert out.value == 416 * 416 * 401 * 8 + 401 * 401 * 8
     assert L.helm_factor_bytes(ctypes.byref(g), 7, ctypes.byref(out)) == helm.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_hessian_entry_points_check_arguments_without_gpu():
+    """The Hessian and preconditioner entry points reject bad arguments
+    before touching the device."""
+    from paper_2301_10762_amd import helm
+    L = helm.lib()
+    fake = ctypes.c_void_p(16)
+    g = helm._Grid(9, 9, 0.1, 0.1)
+    # Gamma(alpha, 0) is singular; negative alpha is not a regulariser
+    assert L.helm_gamma_solve(ctypes.byref(g), 1.0, 0.0, 1, fake, fake, None) == helm.EINVAL
+    assert L.helm_gamma_solve(ctypes.byref(g), -1.0, 1.0, 1, fake, fake, None) == helm.EINVAL
+    assert L.helm_gamma_solve(ctypes.byref(g), 1.0, 1.0, 0, fake, fake, None) == helm.EINVAL
+    bad = helm._Grid(1, 9, 0.1, 0.1)
+    assert L.helm_gamma_solve(ctypes.byref(bad), 1.0, 1.0, 1, fake, fake, None) == helm.EINVAL
+    # NULL context
+    info = helm._Info()
+    assert L.helm_hess_apply(None, 1, fake, fake, None, ctypes.byref(info)) == helm.EINVAL
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0)
+    assert L.helm_hess_pcg(None, fake, fake, 0.0, 0.0, 1e-6, 10, None, ctypes.byref(it), ctypes.byref(rr),
+                           ctypes.byref(info)) == helm.EINVAL
+    # phi / grad without data, and no output handle
+    w = (ctypes.c_double * 1)(1.0)
+    src = (ctypes.c_int32 * 1)(40)
+    rec = (ctypes.c_int32 * 1)(0)
+    phi = ctypes.c_double(0)
+    out = ctypes.c_void_p()
+    assert L.helm_hess_create(ctypes.byref(g), fake, 1, w, None, 1, src, 1, rec, 0.0, 0.0, 0, 0.0, None,
+                              ctypes.byref(phi), None, ctypes.byref(info), ctypes.byref(out)) == helm.EINVAL
+    assert L.helm_hess_create(ctypes.byref(g), fake, 1, w, None, 1, src, 1, rec, 0.0, 0.0, 0, 0.0, None,
+                              None, None, ctypes.byref(info), None) == helm.EINVAL
+    # node indices out of range
+    src_bad = (ctypes.c_int32 * 1)(81)
+    assert L.helm_hess_create(ctypes.byref(g), fake, 1, w, None, 1, src_bad, 1, rec, 0.0, 0.0, 0, 0.0, None,
+                              None, None, ctypes.byref(info), ctypes.byref(out)) == helm.EINVAL
+    assert not out.value
+    helm.lib().helm_hess_destroy(None)
