@@ -55,6 +55,8 @@ def parse():
                    help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
+    p.add_argument("--hessian-only", action="store_true",
+                   help="only run the full-Hessian product and PCG measurement at 201^2 and print it")
     return p.parse_args()
 
 
@@ -96,6 +98,64 @@ def read_traffic(prec):
         return None
 
 
+def hessian_extra(helm, I, w4, G4, dirs, alpha=1e-4, mu=1e-8, precisions=("fp64", "fp32_ir")):
+    """Full-Hessian product (8 directions) and PCG with P2 = Gamma(alpha, mu)
+    at 201^2, for each precision of the context's factors."""
+    import numpy as np
+    import torch
+    n_omega, S4 = len(w4.omegas), len(w4.sources)
+    E4 = torch.as_tensor(I.point_sources(G4.N, w4.sources), device="cuda")
+    Fs = helm.factor_batch([G4] * n_omega, [torch.as_tensor(w4.m_true, device="cuda")] * n_omega, w4.omegas,
+                           "fp64")
+    Xt, _ = helm.solve_batch(Fs, [E4] * n_omega, tol=TOL)
+    for F in Fs:
+        F.close()
+    ridx = torch.as_tensor(np.asarray(w4.receivers, dtype=np.int64), device="cuda")
+    d4 = torch.stack([x[:, ridx] for x in Xt]).contiguous()
+    del Xt, E4
+    m_fwi = w4.m_true + 0.1 * (w4.m - w4.m_true)
+    b = w4.m_true - m_fwi
+    out = {"alpha": alpha, "mu": mu, "model": "m_true + 0.1 (m0 - m_true)", "rhs": "m_true - m",
+           "pcg_rtol": 1e-6}
+    for prec in precisions:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = helm.Hessian(G4, m_fwi, w4.omegas, w4.sources, w4.receivers, d4, alpha, mu, precision=prec, tol=TOL)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        try:
+            H.apply(dirs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hv, hi = H.apply(dirs)
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+            n_prod = n_omega * S4 * 2 * len(w4.directions)
+            t0 = time.perf_counter()
+            x, it, rr, pi = H.pcg(b, prec_alpha=alpha, prec_mu=mu, rtol=1e-6, maxit=200)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t0
+            plain = None
+            if prec == precisions[0]:
+                t0 = time.perf_counter()
+                _, it0, rr0, _ = H.pcg(b, rtol=1e-6, maxit=4 * it, strict=False)
+                torch.cuda.synchronize()
+                t_plain = time.perf_counter() - t0
+                plain = {"iterations": it0, "relres": rr0, "ms": round(t_plain * 1e3, 3),
+                         "converged": bool(rr0 <= 1e-6)}
+        finally:
+            H.close()
+        out[prec] = {"context_ms": round(tc * 1e3, 3),
+                     "product": {"ms": round(ta * 1e3, 3), "directions": len(w4.directions), "solves": n_prod,
+                                 "solves_per_s": round(n_prod / ta, 2), "max_relres": hi.max_relres},
+                     "pcg_p2": {"iterations": it, "relres": rr, "ms": round(tp * 1e3, 3),
+                                "ms_per_iteration": round(tp * 1e3 / max(it, 1), 3),
+                                "solves_per_s": round(2 * n_omega * S4 * (it + 1) / tp, 2)}}
+        if plain:
+            out[prec]["cg_plain"] = plain
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -120,6 +180,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
+
+    if args.hessian_only:
+        w4 = I.config_c4()
+        G4 = helm.Grid.of(w4)
+        dirs = torch.as_tensor(np.stack(w4.directions), device="cuda")
+        print(json.dumps({"hessian_201": hessian_extra(helm, I, w4, G4, dirs)}), flush=True)
         return
 
     w = I.config_c3()
@@ -284,6 +351,12 @@ def main():
         extras["gn_hvp_201"] = {"ms": round(th * 1e3, 3), "directions": len(w4.directions),
                                 "solves": n_solves, "solves_per_s": round(n_solves / th, 2),
                                 "max_relres": hinfo.max_relres}
+        # Full Hessian H1 + H2 + Gamma and the Hessian system H rho = m' - m
+        # at the same 201^2 workload.  The model stands in for an FWI result
+        # (m_true + 0.1 (m0 - m_true)); the data are this library's forward
+        # data at the true model.  One context (factors, u, lambda) serves
+        # the 8-direction product and every PCG iteration.
+        extras["hessian_201"] = hessian_extra(helm, I, w4, G4, dirs)
 
     cpu = None
     if not args.no_cpu_baseline:

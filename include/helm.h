@@ -181,7 +181,7 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
  *             - Re h_j mt_j u_j conj(lambda_j),
  * (Gauss-Newton context: z = A^{-*} R^* R v and only the first term), then
  * hv += Gamma mt.  mt_dev, hv_dev: doubles [n_dir][nx*nz], not
- * overlapping; hv overwritten.  Solves use the context's precision and tol.
+ * overlapping; hv overwritten; n_dir * S <= 65535.  Solves use the context's precision and tol.
  * Synchronises `stream`.  Calls on one context must not overlap.           */
 int helm_hess_apply(helm_hess_t h, int32_t n_dir, const double* mt_dev, double* hv_dev,
                     void* stream, helm_info* info);

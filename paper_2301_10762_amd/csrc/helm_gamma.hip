@@ -33,8 +33,8 @@ struct GemmOp {
     int M, N, K;
 };
 
-constexpr int GT = 64;   // output tile 64 x 64 per workgroup (2 x 2 waves of 32 x 32)
-constexpr int GK = 16;   // k-chunk staged in LDS
+constexpr int GT = 32;   // output tile 32 x 32 per workgroup, one 16 x 16 quarter per wave
+constexpr int GK = 64;   // k-chunk staged in LDS: 16 loads in flight per thread, few serial chunks
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmOp op) {
     __shared__ double sA[GK][GT + 1];   // sA[k][r]
@@ -46,58 +46,51 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmOp op) {
     const double* A = op.A + b * op.sab;
     const double* B = op.B + b * op.sbb;
     const int lr = lane & 15, lg = lane >> 4;
-    v4d acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < op.K; k0 += GK) {
-        // 64 x 16 elements of each operand, four per thread, the unit-stride
-        // index fastest across the workgroup
+        // 32 x 64 elements of each operand, eight per thread, the
+        // unit-stride index fastest across the workgroup; all loads of a
+        // chunk are issued before the first is stored
+        double va[8], vb[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int e = t + 256 * q;
             int rr, kk;
-            if (op.sak == 1) { kk = e & (GK - 1); rr = e >> 4; }
-            else { rr = e & (GT - 1); kk = e >> 6; }
+            if (op.sak == 1) { kk = e & (GK - 1); rr = e >> 6; }
+            else { rr = e & (GT - 1); kk = e >> 5; }
             const int gr = r0 + rr, gk = k0 + kk;
-            sA[kk][rr] = (gr < op.M && gk < op.K) ? A[gr * op.sar + gk * op.sak] : 0.0;
+            va[q] = (gr < op.M && gk < op.K) ? A[gr * op.sar + gk * op.sak] : 0.0;
             int cc, kb;
-            if (op.sbk == 1) { kb = e & (GK - 1); cc = e >> 4; }
-            else { cc = e & (GT - 1); kb = e >> 6; }
+            if (op.sbk == 1) { kb = e & (GK - 1); cc = e >> 6; }
+            else { cc = e & (GT - 1); kb = e >> 5; }
             const int gc = c0 + cc, gk2 = k0 + kb;
-            sB[kb][cc] = (gc < op.N && gk2 < op.K) ? B[gk2 * op.sbk + gc * op.sbc] : 0.0;
+            vb[q] = (gc < op.N && gk2 < op.K) ? B[gk2 * op.sbk + gc * op.sbc] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + 256 * q;
+            if (op.sak == 1) sA[e & (GK - 1)][e >> 6] = va[q];
+            else sA[e >> 5][e & (GT - 1)] = va[q];
+            if (op.sbk == 1) sB[e & (GK - 1)][e >> 6] = vb[q];
+            else sB[e >> 5][e & (GT - 1)] = vb[q];
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GK; kk += 4) {
-            double a[2], bb[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = sA[kk + lg][32 * wr + 16 * i + lr];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) bb[j] = sB[kk + lg][32 * wc + 16 * j + lr];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], bb[j], acc[i][j]);
-        }
+        for (int kk = 0; kk < GK; kk += 4)
+            acc = mfma16(sA[kk + lg][16 * wr + lr], sB[kk + lg][16 * wc + lr], acc);
         __syncthreads();
     }
     double* C = op.C + b * op.scb;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = r0 + 32 * wr + 16 * i + acc_row<double>(lg, e);
-                const int c = c0 + 32 * wc + 16 * j + lr;
-                if (r < op.M && c < op.N) {
-                    double v = acc[i][j][e];
-                    if (op.div) v /= op.div[(int64_t)r * op.N + c];
-                    C[r * op.scr + c * op.scc] = v;
-                }
-            }
+    for (int e = 0; e < 4; ++e) {
+        const int r = r0 + 16 * wr + acc_row<double>(lg, e);
+        const int c = c0 + 16 * wc + lr;
+        if (r < op.M && c < op.N) {
+            double v = acc[e];
+            if (op.div) v /= op.div[(int64_t)r * op.N + c];
+            C[r * op.scr + c * op.scc] = v;
+        }
+    }
 }
 
 static void gemm(const GemmOp& op, int batch, hipStream_t st) {

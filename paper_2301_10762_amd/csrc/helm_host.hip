@@ -40,6 +40,9 @@ struct helm_hess_s {
     std::vector<helm_factor_s*> F;       // one factorisation per frequency
     std::vector<double*> U, L;           // complex128 [S][N] per frequency (L only when full)
     int* drec = nullptr;                 // receiver nodes, device
+    int* dnode = nullptr;                // distinct receiver nodes and the receivers on each, device
+    int* dmult = nullptr;
+    int nu = 0;
     double* m = nullptr;                 // device copy of the model
     hipStream_t st = nullptr;            // stream of creation (memory is released there)
     std::vector<std::pair<void*, size_t>> owned;
@@ -910,6 +913,24 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     if ((rc = hess_own(h, &h->drec, sizeof(int) * Nr))) return rc;
     if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
     if ((rc = upload_sync(h->drec, rec_host, sizeof(int) * Nr, st))) return rc;
+    {
+        std::vector<int> nodes(rec_host, rec_host + Nr), mult;
+        std::sort(nodes.begin(), nodes.end());
+        std::vector<int> uniq;
+        for (int q = 0; q < Nr; ++q) {
+            if (q == 0 || nodes[q] != nodes[q - 1]) {
+                uniq.push_back(nodes[q]);
+                mult.push_back(1);
+            } else {
+                mult.back() += 1;
+            }
+        }
+        h->nu = (int)uniq.size();
+        if ((rc = hess_own(h, &h->dnode, sizeof(int) * h->nu))) return rc;
+        if ((rc = hess_own(h, &h->dmult, sizeof(int) * h->nu))) return rc;
+        if ((rc = upload_sync(h->dnode, uniq.data(), sizeof(int) * h->nu, st))) return rc;
+        if ((rc = upload_sync(h->dmult, mult.data(), sizeof(int) * h->nu, st))) return rc;
+    }
     const size_t fb = sizeof(double) * 2 * (size_t)N * S;
     double* E;
     if ((rc = sc.get(&E, fb))) return rc;
@@ -989,7 +1010,9 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
 // Synchronises the stream.
 int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStream_t st, helm_info* info) {
     const int64_t N = N_of(h->g);
-    const int S = h->S, nw = h->n_omega, cols = n_dir * S;
+    const int S = h->S, nw = h->n_omega;
+    if ((int64_t)n_dir * S > 65535) return fail(HELM_EINVAL, "n_dir * S must not exceed 65535 (split the directions)");
+    const int cols = n_dir * S;
     const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
     Scratch sc(st);
     std::vector<double*> W(nw), V(nw), Z(nw);
@@ -1009,7 +1032,7 @@ int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStrea
     for (int w = 0; w < nw; ++w) {
         if (h->full) launch_zeta_rhs(coef_of(h->F[w]), h->L[w], N, S, mt, n_dir, W[w], N, st);
         else launch_zero(W[w], vb, st);
-        launch_sample_scatter(V[w], N, h->drec, h->Nr, cols, W[w], N, st);
+        launch_sample_scatter(V[w], N, h->dnode, h->dmult, h->nu, cols, W[w], N, st);
         g_launches += 2;
     }
     for (int w = 0; w < nw; ++w) j2.push_back({h->F[w], W[w], Z[w], cols, N, &i2[w]});

@@ -151,8 +151,8 @@ void launch_grad(const Coef& cf, const double* U, int64_t ldu, const double* L, 
                  double* g, hipStream_t st);
 void launch_gn_rhs(const Coef& cf, const double* U, int64_t ldu, int S, const double* mt, int n_dir,
                    double* V, int64_t ldv, hipStream_t st);
-void launch_sample_scatter(const double* V, int64_t ldv, const int* rec, int Nr, int cols, double* RV,
-                           int64_t ldr, hipStream_t st);
+void launch_sample_scatter(const double* V, int64_t ldv, const int* node, const int* mult, int nu, int cols,
+                           double* RV, int64_t ldr, hipStream_t st);
 void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz,
                int n_dir, double* hv, int64_t N, hipStream_t st);
 void launch_zeta_rhs(const Coef& cf, const double* L, int64_t ldl, int S, const double* mt, int n_dir, double* W,

@@ -221,16 +221,19 @@ __global__ void k_gn_rhs(Coef cf, const double2* U, int64_t ldu, int S, const do
     V[(size_t)col * ldv + k] = make_double2(t * (wk.x * u.x - wk.y * u.y), t * (wk.x * u.y + wk.y * u.x));
 }
 
-// RV = R^* R V column by column (buffer zeroed beforehand)
-__global__ void k_sample_scatter(const double2* V, int64_t ldv, const int* rec, int Nr, int cols, double2* RV,
-                                 int64_t ldr) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    for (int p = 0; p < Nr; ++p) {
-        double2 v = V[(size_t)c * ldv + rec[p]];
-        double2* o = RV + (size_t)c * ldr + rec[p];
-        *o = make_double2(o->x + v.x, o->y + v.y);
-    }
+// RV += R^* R V: for on-node receivers R^* R is diagonal, with the number of
+// receivers on a node as its entry; one thread per (distinct receiver node,
+// column), so no two threads touch the same element
+__global__ void k_sample_scatter(const double2* V, int64_t ldv, const int* node, const int* mult, int nu,
+                                 double2* RV, int64_t ldr) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (q >= nu) return;
+    const int k = node[q];
+    const double w = (double)mult[q];
+    double2 v = V[(size_t)c * ldv + k];
+    double2* o = RV + (size_t)c * ldr + k;
+    *o = make_double2(o->x + w * v.x, o->y + w * v.y);
 }
 
 // hv_a[k] += Re sum_s wk u_s[k] conj(z_{a,s}[k])
@@ -417,10 +420,10 @@ void launch_gn_rhs(const Coef& cf, const double* U, int64_t ldu, int S, const do
     hipLaunchKernelGGL(k_gn_rhs, dim3(grid1((int64_t)cf.nx * cf.nz).x, n_dir * S), dim3(256), 0, st, cf,
                        (const double2*)U, ldu, S, mt, n_dir, (double2*)V, ldv);
 }
-void launch_sample_scatter(const double* V, int64_t ldv, const int* rec, int Nr, int cols, double* RV, int64_t ldr,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(k_sample_scatter, grid1(cols, 64), dim3(64), 0, st, (const double2*)V, ldv, rec, Nr, cols,
-                       (double2*)RV, ldr);
+void launch_sample_scatter(const double* V, int64_t ldv, const int* node, const int* mult, int nu, int cols,
+                           double* RV, int64_t ldr, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_scatter, dim3(grid1(nu, 64).x, cols), dim3(64), 0, st, (const double2*)V, ldv,
+                       node, mult, nu, (double2*)RV, ldr);
 }
 void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz, int n_dir,
                double* hv, int64_t N, hipStream_t st) {

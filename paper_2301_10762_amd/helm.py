@@ -399,10 +399,12 @@ class Hessian:
         return hv, Info.of(info)
 
     def pcg(self, b, x0=None, prec_alpha: float = 0.0, prec_mu: float = 0.0, rtol: float = 1e-6,
-            maxit: int = 1000, stream=None):
+            maxit: int = 1000, stream=None, strict: bool = True):
         """PCG for H x = b with P2 = Gamma(prec_alpha, prec_mu) (none when
         prec_mu <= 0); start vector all ones unless x0 is given.  Returns
-        (x, iterations, final ||r|| / ||r0||, info)."""
+        (x, iterations, final ||r|| / ||r0||, info).  strict=False returns
+        the last iterate instead of raising when the tolerance is not met
+        within maxit."""
         torch = _torch()
         bd = _dev_f64(b, self.grid.N).contiguous()
         x = (torch.ones(self.grid.N, dtype=torch.float64, device="cuda") if x0 is None
@@ -410,9 +412,10 @@ class Hessian:
         it = ctypes.c_int32(0)
         rel = ctypes.c_double(0.0)
         info = _Info()
-        _check(lib().helm_hess_pcg(self.h, _ptr(bd), _ptr(x), float(prec_alpha), float(prec_mu), float(rtol),
-                                   int(maxit), _stream(stream), ctypes.byref(it), ctypes.byref(rel),
-                                   ctypes.byref(info)))
+        rc = lib().helm_hess_pcg(self.h, _ptr(bd), _ptr(x), float(prec_alpha), float(prec_mu), float(rtol),
+                                 int(maxit), _stream(stream), ctypes.byref(it), ctypes.byref(rel), ctypes.byref(info))
+        if rc != OK and (strict or rc != ENOCONV or int(it.value) < int(maxit)):
+            _check(rc)
         return x, int(it.value), float(rel.value), Info.of(info)
 
     def close(self):

@@ -144,6 +144,29 @@ def test_full_hessian_ragged_grid_single_direction(helm):
         Hc.close()
 
 
+def test_hessian_repeated_receivers(helm):
+    """Receivers listed twice count twice in R^* R (and in R^* eps)."""
+    print("full Hessian repeated receivers", flush=True)
+    w = I.small_layered(21, 9, 2, 4, ppws=(10.0,), n_dirs=2)
+    rec = [int(w.receivers[0]), int(w.receivers[2]), int(w.receivers[2]), int(w.receivers[3]),
+           int(w.receivers[0]), int(w.receivers[2])]
+    g = oracle.Grid.of(w)
+    d_obs = oracle.synth_data(g, w.m_true, w.omegas, w.sources, rec)
+    Ho = oracle.hvp(g, w.m, w.omegas, d_obs, w.sources, rec, w.directions, 0.01, 0.001)
+    Hgo = oracle.gn_hvp(g, w.m, w.omegas, w.sources, rec, w.directions, 0.01, 0.001)[1]
+    G = helm.Grid.of(w)
+    Hf = helm.Hessian(G, w.m, w.omegas, w.sources, rec, d_obs, 0.01, 0.001, tol=1e-10)
+    Hg = helm.Hessian(G, w.m, w.omegas, w.sources, rec, None, 0.01, 0.001, tol=1e-10)
+    try:
+        a, _ = Hf.apply(np.array(w.directions))
+        b, _ = Hg.apply(np.array(w.directions))
+        assert rel(a.cpu().numpy(), Ho) < 1e-8
+        assert rel(b.cpu().numpy(), Hgo) < 1e-8
+    finally:
+        Hf.close()
+        Hg.close()
+
+
 def test_full_equals_gauss_newton_at_zero_residual(helm):
     print("full vs GN at zero residual", flush=True)
     w = I.small_layered(31, 3, 3, 6, ppws=(10.0, 13.0), n_dirs=2)
