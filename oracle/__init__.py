@@ -29,12 +29,21 @@ What each function follows:
   * preconditioner P2 = Gamma(alpha0, mu) by Cholesky (eq (P2)) -> gamma_solve
   * PCG for H rho = m' - m_FWI (eq (rho), stopping rule of the
     preconditioning section)                               -> pcg
+  * sliding-cubic restriction R(P) and its derivative (App. "Numerical
+    restriction operator")                                 -> Sensors
+  * upper-level derivatives dpsi/dp_{j,l}, dpsi/dalpha (theorems on the
+    derivatives of psi, eqs (gradALT), (gradALT1), (tau_def), (sograda))
+                                                           -> upper_grad
 
 Readings where the paper is silent (each pinned by a test in tests/):
   * corner mass weight hx*hz/4 (mean of the two triangulation directions);
   * b_k = half the length of each boundary edge touching node k;
   * (f, g) = sum f conj(g) (linear in the first argument), Re taken last;
   * on-node receivers: R samples u at the node, R^* scatters onto that node;
+    off-node sensors: tensor-product cubic through the 4 x 4 nearest nodes,
+    the stencil moved inward at the edges;
+  * dpsi/dp carries the conjugates the derivation gives: -Re[(d tau) conj(du)
+    + tau conj(d du)], where the printed a_l shows none;
   * D_n keeps the printed factor (n - 1).
 """
 from __future__ import annotations
@@ -203,13 +212,75 @@ def unit_sources(g: Grid, nodes) -> np.ndarray:
     return E
 
 
+def _lagrange4(t: float):
+    """The cubic Lagrange basis through the points 0, 1, 2, 3, and its
+    derivative, at t."""
+    L = np.array([-(t - 1) * (t - 2) * (t - 3) / 6.0, t * (t - 2) * (t - 3) / 2.0,
+                  -t * (t - 1) * (t - 3) / 2.0, t * (t - 1) * (t - 2) / 6.0])
+    dL = np.array([-((t - 2) * (t - 3) + (t - 1) * (t - 3) + (t - 1) * (t - 2)) / 6.0,
+                   ((t - 2) * (t - 3) + t * (t - 3) + t * (t - 2)) / 2.0,
+                   -((t - 1) * (t - 3) + t * (t - 3) + t * (t - 1)) / 2.0,
+                   ((t - 1) * (t - 2) + t * (t - 2) + t * (t - 1)) / 6.0])
+    return L, dL
+
+
+def _cubic_stencil(p: float, h: float, n: int):
+    """Sliding cubic on n nodes of spacing h (App. "Numerical restriction
+    operator"): for p in the interval [x_i, x_{i+1}] the cubic through
+    x_{i-1} .. x_{i+2}, the four nodes moved inward at the ends of the line.
+    Returns the first node and the weights for the value and the derivative."""
+    i = min(max(int(np.floor(p / h)), 0), n - 2)
+    i0 = min(max(i - 1, 0), n - 4)
+    L, dL = _lagrange4(p / h - i0)
+    return i0, L, dL / h
+
+
+class Sensors:
+    """Sensors at points p_j = (x_j, z_j) of the domain (x = i h_x, z = j h_z)
+    with the sliding-cubic restriction R(P) of App. "Numerical restriction
+    operator": (R(P) u)_j is the bicubic interpolant of the nodal values
+    through the 4 x 4 nodes nearest to p_j.  Needs n_x, n_z >= 4."""
+
+    def __init__(self, g: Grid, positions):
+        if g.nx < 4 or g.nz < 4:
+            raise ValueError("the sliding cubic needs at least four nodes per direction")
+        self.g = g
+        self.pos = np.asarray(positions, dtype=np.float64).reshape(-1, 2)
+
+    def __len__(self):
+        return len(self.pos)
+
+    def matrix(self, deriv: int = 0) -> sp.csr_matrix:
+        """R(P) (deriv 0) or its derivative dR/dx (1) or dR/dz (2) with
+        respect to the sensor coordinates, as an N_r x N matrix."""
+        g = self.g
+        rows, cols, vals = [], [], []
+        for q, (px, pz) in enumerate(self.pos):
+            i0, Lx, dLx = _cubic_stencil(px, g.hx, g.nx)
+            j0, Lz, dLz = _cubic_stencil(pz, g.hz, g.nz)
+            wx = dLx if deriv == 1 else Lx
+            wz = dLz if deriv == 2 else Lz
+            for b in range(4):
+                for a in range(4):
+                    rows.append(q)
+                    cols.append((j0 + b) * g.nx + i0 + a)
+                    vals.append(wx[a] * wz[b])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(len(self.pos), g.N))
+
+
 def restrict(U: np.ndarray, receivers) -> np.ndarray:
-    """R u for on-node receivers (eq (Rv)): the nodal values at the sensors."""
+    """R u (eq (Rv)): for on-node receivers (node indices) the nodal values
+    at the sensors, for Sensors the sliding-cubic interpolant."""
+    if isinstance(receivers, Sensors):
+        return np.ascontiguousarray((receivers.matrix() @ np.asarray(U).T).T)
     return U[:, np.asarray(receivers, dtype=np.int64)]
 
 
 def restrict_adjoint(Z: np.ndarray, receivers, N: int) -> np.ndarray:
-    """R^* z (eq (Rstar)) for on-node receivers: z_p placed on node p (summed if repeated)."""
+    """R^* z (eq (Rstar)): for on-node receivers z_p placed on node p (summed
+    if repeated), for Sensors the transpose of the interpolation weights."""
+    if isinstance(receivers, Sensors):
+        return np.ascontiguousarray((receivers.matrix().T @ np.asarray(Z).T).T).astype(np.complex128)
     out = np.zeros((Z.shape[0], N), dtype=np.complex128)
     rec = np.asarray(receivers, dtype=np.int64)
     for q, k in enumerate(rec):
@@ -398,3 +469,43 @@ def pcg(apply_h, b, apply_pinv=None, x0=None, rtol: float = 1e-6, maxit: int = 1
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, it, hist
+
+
+def upper_grad(g: Grid, m_fwi, m_train, omegas, sources, sensors: "Sensors", rho):
+    """Derivatives of the upper-level objective psi = 1/2 ||m' - m_FWI||^2
+    (eq (SOobj)) for one training model m', given rho from the Hessian system
+    H(m_FWI) rho = m' - m_FWI (eq (rho)):
+
+      dpsi/dp_{j,l} (theorem on the derivative with respect to p_{j,l},
+      eqs (gradALT), (gradALT1), (tau_def)): per frequency and source
+          u = A(m_FWI)^{-1} e_s,  u' = A(m')^{-1} e_s,
+          tau = A(m_FWI)^{-1}(g rho u),  g = w^2 d + b i w/(2 sqrt m_FWI),
+          dpsi/dp_{j,l} += -Re[ (d_l tau)(p_j) conj(du(p_j))
+                                + tau(p_j) conj((d_l du)(p_j)) ],  du = u' - u,
+      with f(p_j) = (R(P) f)_j and (d_l f)(p_j) = (dR(P)/dx_l f)_j;
+      dpsi/dalpha = m_FWI^T R rho with R = Dx^T Dx + Dz^T Dz (eq (sograda)).
+
+    The conjugates are those of the derivation (the inner product conjugates
+    its second argument).  Average over the training models for several.
+    Returns (dpsi/dp as [N_r][2] for (x, z), dpsi/dalpha)."""
+    m_fwi = _check_model(g, m_fwi)
+    m_train = _check_model(g, m_train)
+    rho = np.asarray(rho, dtype=np.float64)
+    R0, Rx, Rz = sensors.matrix(0), sensors.matrix(1), sensors.matrix(2)
+    dp = np.zeros((len(sensors), 2))
+    for w in omegas:
+        F = Factor(g, m_fwi, w)
+        U = F.solve(unit_sources(g, sources))
+        Tau = F.solve(grad_weight(g, m_fwi, w)[None, :] * rho[None, :] * U)
+        F.close()
+        Ft = Factor(g, m_train, w)
+        dU = Ft.solve(unit_sources(g, sources)) - U
+        Ft.close()
+        du = (R0 @ dU.T).T
+        for col, Rl in ((0, Rx), (1, Rz)):
+            dtau = (Rl @ Tau.T).T
+            ddu = (Rl @ dU.T).T
+            tau = (R0 @ Tau.T).T
+            dp[:, col] -= np.real(np.sum(dtau * np.conj(du) + tau * np.conj(ddu), axis=0))
+    Rg = regulariser(g, 1.0, 0.0)
+    return dp, float(m_fwi @ (Rg @ rho))

@@ -121,3 +121,39 @@ def test_hvp_mutation_caught(name):
     from tests.test_oracle_hessian import hvp_fd_error
     old, new = HVP_MUTATIONS[name]
     assert hvp_fd_error(_mutant_hvp(old, new)) > 1e-4
+
+
+# ------------------------------------------------- upper-level derivatives --
+
+def _mutant_upper(old, new):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.upper_grad))
+    assert src.count(old) == 1, old
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns["upper_grad"]
+
+
+UPPER_MUTATIONS = {
+    # the form printed in eq (gradALT1), without the conjugates of the derivation
+    "no_conjugates": ("dtau * np.conj(du) + tau * np.conj(ddu)", "dtau * du + tau * ddu"),
+    "dropped_dtau_term": ("dtau * np.conj(du) + tau * np.conj(ddu)", "tau * np.conj(ddu)"),
+    "dropped_tau_term": ("dtau * np.conj(du) + tau * np.conj(ddu)", "dtau * np.conj(du)"),
+    "tau_without_rho": ("grad_weight(g, m_fwi, w)[None, :] * rho[None, :] * U", "grad_weight(g, m_fwi, w)[None, :] * U"),
+    "adjoint_tau": ("Tau = F.solve(", "Tau = F.adjoint_solve("),
+    "alpha_with_gamma": ("Rg = regulariser(g, 1.0, 0.0)", "Rg = regulariser(g, 1.0, 1.0)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(UPPER_MUTATIONS))
+def test_upper_mutation_caught(name):
+    from tests.test_oracle_upper import _Bilevel, upper_fd_errors
+    import numpy as np
+    b = _Bilevel()
+    b.m_fwi, d, S = b.fwi(b.P, b.alpha, b.m_train)
+    b.rho = np.linalg.solve(b.hessian(b.m_fwi, d, S, b.alpha), b.m_train - b.m_fwi)
+    b.S = S
+    old, new = UPPER_MUTATIONS[name]
+    ep, ea = upper_fd_errors(b, _mutant_upper(old, new))
+    assert max(ep, ea) > 1e-4, (ep, ea)
