@@ -173,6 +173,46 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
                      double mu, int precision, double tol, void* stream, double* phi_host,
                      double* grad_dev, helm_info* info, helm_hess_t* out);
 
+/* helm_hess_create_at: helm_hess_create with the Nr sensors at points of
+ * the domain, rec_xz_host = [Nr][2] doubles (x, z) with 0 <= x <= (nx-1) hx,
+ * 0 <= z <= (nz-1) hz, and R(P) the sliding cubic of App. "Numerical
+ * restriction operator": (R u)_j is the tensor-product Lagrange cubic through
+ * the 4 x 4 nodes nearest to p_j (for p in [x_i, x_{i+1}] the nodes x_{i-1}
+ * .. x_{i+2}, moved inward at the edges), so at a node it is the nodal value.
+ * Needs nx, nz >= 4.  R^* is its transpose.  Everything else (phi, grad,
+ * products, PCG) is as for helm_hess_create.                               */
+int helm_hess_create_at(const helm_grid* grid, const double* m_dev, int32_t n_omega,
+                        const double* omegas_host, const double* dobs_dev, int32_t S,
+                        const int32_t* src_host, int32_t Nr, const double* rec_xz_host,
+                        double alpha, double mu, int precision, double tol, void* stream,
+                        double* phi_host, double* grad_dev, helm_info* info, helm_hess_t* out);
+
+/* helm_upper_grad: derivatives of the upper-level objective
+ * psi = 1/2 ||m' - m_FWI||^2 (eq (SOobj)) for one training model m', at a
+ * context made by helm_hess_create_at at m_FWI with data d = R(P) u(m'):
+ *   tau = A(m_FWI)^{-1}(g rho u) (eq (tau_def)), one solve per frequency and source;
+ *   dpsi/dp_{j,l} = -sum_{w,s} Re[(d_l tau)(p_j) conj(eps_j)
+ *                                + tau(p_j) conj(dd_{j,l} - (d_l u)(p_j))]
+ *   (theorem on the derivative with respect to p_{j,l}, eqs (gradALT),
+ *   (gradALT1), with the conjugates its derivation gives), eps = d - R u;
+ *   dpsi/dalpha = m_FWI^T (Dx^T Dx + Dz^T Dz) rho (eq (sograda)).
+ * rho_dev: nx*nz doubles, the solution of H rho = m' - m_FWI (eq (rho),
+ * helm_hess_pcg).  ddata_dev: complex128 [n_omega][S][Nr][2], the x and z
+ * derivatives of the training wavefield at the sensors, dR/dx_l u(m')
+ * (helm_restrict with deriv 1 and 2).  dpsi_dp_host: [Nr][2] doubles
+ * (x, z); *dpsi_dalpha_host.  For several training models average the
+ * results (the 1/N_m' of eqs (gradALT), (sograda)).  Synchronises
+ * `stream`.                                                               */
+int helm_upper_grad(helm_hess_t h, const double* rho_dev, const double* ddata_dev, void* stream,
+                    double* dpsi_dp_host, double* dpsi_dalpha_host, helm_info* info);
+
+/* helm_restrict: out = R(P) U (deriv 0) or its derivative with respect to
+ * the sensors' x (1) or z (2) coordinate, for S complex128 fields U_dev
+ * (column s at s*ld) and Nr sensors at points as for helm_hess_create_at.
+ * out_dev: complex128 [S][Nr].  Synchronises `stream`.                    */
+int helm_restrict(const helm_grid* grid, int32_t Nr, const double* rec_xz_host, int deriv,
+                  const double* U_dev, int32_t S, int64_t ld, double* out_dev, void* stream);
+
 /* helm_hess_apply: hv_a = H mt_a for n_dir directions.  Per frequency and
  * source, with g = w^2 d + b i w / (2 sqrt m) and h = dg/dm = -i w b /
  * (4 m^{3/2}):

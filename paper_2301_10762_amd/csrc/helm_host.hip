@@ -39,10 +39,16 @@ struct helm_hess_s {
     int full = 0;                        // 1: H1 + H2 + Gamma (data given); 0: H1 + Gamma
     std::vector<helm_factor_s*> F;       // one factorisation per frequency
     std::vector<double*> U, L;           // complex128 [S][N] per frequency (L only when full)
-    int* drec = nullptr;                 // receiver nodes, device
-    int* dnode = nullptr;                // distinct receiver nodes and the receivers on each, device
-    int* dmult = nullptr;
-    int nu = 0;
+    // restriction R(P), device: RTAP taps per sensor (ntap used), value
+    // weights and, for sensors at points, those of d/dx and d/dz; and its
+    // transpose gathered per distinct node (nt nodes)
+    int ntap = 1, nt = 0;
+    bool at_points = false;
+    int* rnode = nullptr;
+    double* rw = nullptr;                // 3 planes of Nr * RTAP
+    int *tnode = nullptr, *tptr = nullptr, *tq = nullptr;
+    double* tw = nullptr;
+    double* eps = nullptr;               // R(u' - u) = d - R u, complex128 [n_omega][S][Nr] (with data)
     double* m = nullptr;                 // device copy of the model
     hipStream_t st = nullptr;            // stream of creation (memory is released there)
     std::vector<std::pair<void*, size_t>> owned;
@@ -869,13 +875,119 @@ void merge_info(helm_info* into, const helm_info& a) {
     into->solves += a.solves;
 }
 
+// A restriction R(P) on the host: RTAP taps per sensor (only the first ntap
+// used), weights for the value and for d/dx, d/dz of the sensor position,
+// and the transpose of the value weights gathered per distinct node.
+struct HostRTab {
+    int Nr = 0, ntap = 1;
+    bool points = false;
+    std::vector<int> node;                    // Nr * RTAP
+    std::vector<double> w;                    // 3 planes of Nr * RTAP
+    std::vector<int> tnode, tptr, tq;
+    std::vector<double> tw;
+};
+
+// Sliding cubic along one grid line (App. "Numerical restriction operator"):
+// at grid coordinate u (position / spacing) on n >= 4 nodes, the Lagrange
+// cubic through the four nodes nearest to u (those of its interval and one
+// on each side, moved inward at the ends).  Weights L for the value and dL
+// for d/du.
+void cubic_stencil(double u, int n, int* first, double L[4], double dL[4]) {
+    int i = (int)std::floor(u);
+    i = std::min(std::max(i, 0), n - 2);
+    const int i0 = std::min(std::max(i - 1, 0), n - 4);
+    const double t = u - i0, a = t, b = t - 1.0, c = t - 2.0, d = t - 3.0;
+    L[0] = -(b * c * d) / 6.0;
+    L[1] = (a * c * d) / 2.0;
+    L[2] = -(a * b * d) / 2.0;
+    L[3] = (a * b * c) / 6.0;
+    dL[0] = -(c * d + b * d + b * c) / 6.0;
+    dL[1] = (c * d + a * d + a * c) / 2.0;
+    dL[2] = -(b * d + a * d + a * b) / 2.0;
+    dL[3] = (b * c + a * c + a * b) / 6.0;
+    *first = i0;
+}
+
+void rtab_transpose(HostRTab* t, int64_t N) {
+    std::vector<std::vector<std::pair<int, double>>> by;   // per touched node: (sensor, weight)
+    std::vector<int> slot(N, -1);
+    for (int q = 0; q < t->Nr; ++q)
+        for (int a = 0; a < t->ntap; ++a) {
+            const double wv = t->w[(size_t)q * RTAP + a];
+            if (wv == 0.0) continue;
+            const int k = t->node[(size_t)q * RTAP + a];
+            if (slot[k] < 0) {
+                slot[k] = (int)by.size();
+                t->tnode.push_back(k);
+                by.emplace_back();
+            }
+            by[slot[k]].emplace_back(q, wv);
+        }
+    t->tptr.assign(1, 0);
+    for (auto& lst : by) {
+        for (auto& e : lst) {
+            t->tq.push_back(e.first);
+            t->tw.push_back(e.second);
+        }
+        t->tptr.push_back((int)t->tq.size());
+    }
+}
+
+// sensors on nodes: one tap of weight 1 (plain sampling)
+int rtab_nodes(const helm_grid& g, int Nr, const int32_t* nodes, HostRTab* t) {
+    int rc = check_nodes(nodes, Nr, N_of(g), "receiver");
+    if (rc) return rc;
+    t->Nr = Nr;
+    t->ntap = 1;
+    t->node.assign((size_t)Nr * RTAP, 0);
+    t->w.assign((size_t)3 * Nr * RTAP, 0.0);
+    for (int q = 0; q < Nr; ++q) {
+        for (int a = 0; a < RTAP; ++a) t->node[(size_t)q * RTAP + a] = nodes[q];
+        t->w[(size_t)q * RTAP] = 1.0;
+    }
+    rtab_transpose(t, N_of(g));
+    return HELM_OK;
+}
+
+// sensors at points (x, z) of the domain: the sliding bicubic, 16 taps
+int rtab_points(const helm_grid& g, int Nr, const double* xz, HostRTab* t) {
+    if (Nr > 0 && !xz) return fail(HELM_EINVAL, "sensor position list is NULL");
+    if (g.nx < 4 || g.nz < 4) return fail(HELM_EINVAL, "sensors at points need nx, nz >= 4 (bicubic stencil)");
+    const double X = g.hx * (g.nx - 1), Z = g.hz * (g.nz - 1);
+    t->Nr = Nr;
+    t->ntap = RTAP;
+    t->points = true;
+    t->node.assign((size_t)Nr * RTAP, 0);
+    t->w.assign((size_t)3 * Nr * RTAP, 0.0);
+    const size_t plane = (size_t)Nr * RTAP;
+    for (int q = 0; q < Nr; ++q) {
+        const double x = xz[2 * q], z = xz[2 * q + 1];
+        if (!(x >= 0.0 && x <= X && z >= 0.0 && z <= Z))
+            return fail(HELM_EINVAL, "sensor " + std::to_string(q) + " lies outside the domain");
+        int i0, j0;
+        double Lx[4], dLx[4], Lz[4], dLz[4];
+        cubic_stencil(x / g.hx, g.nx, &i0, Lx, dLx);
+        cubic_stencil(z / g.hz, g.nz, &j0, Lz, dLz);
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                const size_t e = (size_t)q * RTAP + 4 * b + a;
+                t->node[e] = (j0 + b) * g.nx + i0 + a;
+                t->w[e] = Lx[a] * Lz[b];
+                t->w[plane + e] = dLx[a] / g.hx * Lz[b];
+                t->w[2 * plane + e] = Lx[a] * dLz[b] / g.hz;
+            }
+    }
+    rtab_transpose(t, N_of(g));
+    return HELM_OK;
+}
+
 // Factor A(m, w) for every frequency and solve for u (and, with data, for
 // lambda = A^{-*} R^*(d - R u), phi and grad phi when asked for).  The
 // fields stay with the returned context; the stream is synchronised.
 int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const double* omegas_host,
-               const double* dobs_dev, int S, const int32_t* src_host, int Nr, const int32_t* rec_host, double alpha,
-               double mu, int precision, double tol, hipStream_t st, double* phi_host, double* grad_dev,
-               helm_info* info, helm_hess_s** out) {
+               const double* dobs_dev, int S, const int32_t* src_host, int Nr, const int32_t* rec_host,
+               const double* rec_xz, double alpha, double mu, int precision, double tol, hipStream_t st,
+               double* phi_host, double* grad_dev, helm_info* info, helm_hess_s** out) {
     *out = nullptr;
     int rc = check_grid(grid);
     if (rc) return rc;
@@ -884,12 +996,19 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     if (precision != HELM_FP64 && precision != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
     const int64_t N = N_of(*grid);
     if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
-    if ((rc = check_nodes(rec_host, Nr, N, "receiver"))) return rc;
+    HostRTab rt;
+    if ((rc = rec_xz ? rtab_points(*grid, Nr, rec_xz, &rt) : rtab_nodes(*grid, Nr, rec_host, &rt))) return rc;
     const bool full = dobs_dev != nullptr;
     if (full)
         for (int s = 0; s < S; ++s)
-            for (int p = 0; p < Nr; ++p)
-                if (src_host[s] == rec_host[p]) return fail(HELM_EINVAL, "a source coincides with a receiver");
+            for (int p = 0; p < Nr; ++p) {
+                const bool same = rec_xz ? (std::fabs(rec_xz[2 * p] - (src_host[s] % grid->nx) * grid->hx) <=
+                                                1e-12 * grid->hx &&
+                                            std::fabs(rec_xz[2 * p + 1] - (src_host[s] / grid->nx) * grid->hz) <=
+                                                1e-12 * grid->hz)
+                                         : src_host[s] == rec_host[p];
+                if (same) return fail(HELM_EINVAL, "a source coincides with a receiver");
+            }
     helm_hess_s* h = new helm_hess_s();
     *out = h;
     h->g = *grid;
@@ -910,26 +1029,23 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     Scratch sc(st);
     int* dsrc;
     if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
-    if ((rc = hess_own(h, &h->drec, sizeof(int) * Nr))) return rc;
     if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
-    if ((rc = upload_sync(h->drec, rec_host, sizeof(int) * Nr, st))) return rc;
-    {
-        std::vector<int> nodes(rec_host, rec_host + Nr), mult;
-        std::sort(nodes.begin(), nodes.end());
-        std::vector<int> uniq;
-        for (int q = 0; q < Nr; ++q) {
-            if (q == 0 || nodes[q] != nodes[q - 1]) {
-                uniq.push_back(nodes[q]);
-                mult.push_back(1);
-            } else {
-                mult.back() += 1;
-            }
-        }
-        h->nu = (int)uniq.size();
-        if ((rc = hess_own(h, &h->dnode, sizeof(int) * h->nu))) return rc;
-        if ((rc = hess_own(h, &h->dmult, sizeof(int) * h->nu))) return rc;
-        if ((rc = upload_sync(h->dnode, uniq.data(), sizeof(int) * h->nu, st))) return rc;
-        if ((rc = upload_sync(h->dmult, mult.data(), sizeof(int) * h->nu, st))) return rc;
+    h->ntap = rt.ntap;
+    h->at_points = rt.points;
+    h->nt = (int)rt.tnode.size();
+    if ((rc = hess_own(h, &h->rnode, sizeof(int) * rt.node.size()))) return rc;
+    if ((rc = hess_own(h, &h->rw, sizeof(double) * rt.w.size()))) return rc;
+    if ((rc = hess_own(h, &h->tnode, sizeof(int) * std::max<size_t>(rt.tnode.size(), 1)))) return rc;
+    if ((rc = hess_own(h, &h->tptr, sizeof(int) * rt.tptr.size()))) return rc;
+    if ((rc = hess_own(h, &h->tq, sizeof(int) * std::max<size_t>(rt.tq.size(), 1)))) return rc;
+    if ((rc = hess_own(h, &h->tw, sizeof(double) * std::max<size_t>(rt.tw.size(), 1)))) return rc;
+    if ((rc = upload_sync(h->rnode, rt.node.data(), sizeof(int) * rt.node.size(), st))) return rc;
+    if ((rc = upload_sync(h->rw, rt.w.data(), sizeof(double) * rt.w.size(), st))) return rc;
+    if ((rc = upload_sync(h->tptr, rt.tptr.data(), sizeof(int) * rt.tptr.size(), st))) return rc;
+    if (h->nt > 0) {
+        if ((rc = upload_sync(h->tnode, rt.tnode.data(), sizeof(int) * rt.tnode.size(), st))) return rc;
+        if ((rc = upload_sync(h->tq, rt.tq.data(), sizeof(int) * rt.tq.size(), st))) return rc;
+        if ((rc = upload_sync(h->tw, rt.tw.data(), sizeof(double) * rt.tw.size(), st))) return rc;
     }
     const size_t fb = sizeof(double) * 2 * (size_t)N * S;
     double* E;
@@ -951,7 +1067,8 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
         // residuals at the receivers, phi, adjoint sources R^* eps, then lambda
         double *eps, *phip;
         std::vector<double*> Radj(n_omega);
-        if ((rc = sc.get(&eps, sizeof(double) * 2 * (size_t)Nr * S * n_omega))) return rc;
+        if ((rc = hess_own(h, &h->eps, sizeof(double) * 2 * (size_t)Nr * S * n_omega))) return rc;
+        eps = h->eps;
         if ((rc = sc.get(&phip, sizeof(double) * (size_t)S * n_omega + 8))) return rc;
         h->L.assign(n_omega, nullptr);
         for (int w = 0; w < n_omega; ++w) {
@@ -959,10 +1076,12 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
             if ((rc = sc.get(&Radj[w], fb))) return rc;
         }
         for (int w = 0; w < n_omega; ++w) {
-            launch_misfit(h->U[w], N, dobs_dev + 2 * (size_t)w * S * Nr, h->drec, Nr, S,
+            launch_misfit(h->U[w], N, dobs_dev + 2 * (size_t)w * S * Nr, h->rnode, h->rw, h->ntap, Nr, S,
                           eps + 2 * (size_t)w * S * Nr, phip + (size_t)w * S, st);
             launch_zero(Radj[w], fb, st);
-            launch_scatter_adj(eps + 2 * (size_t)w * S * Nr, h->drec, Nr, S, Radj[w], N, st);
+            if (h->nt > 0)
+                launch_restrict_adj(eps + 2 * (size_t)w * S * Nr, Nr, h->tnode, h->tptr, h->tq, h->tw, h->nt, S,
+                                    Radj[w], N, st);
             g_launches += 3;
         }
         std::vector<SolveJob> ajobs;
@@ -1016,7 +1135,9 @@ int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStrea
     const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
     Scratch sc(st);
     std::vector<double*> W(nw), V(nw), Z(nw);
+    double* RV;
     int rc;
+    if ((rc = sc.get(&RV, sizeof(double) * 2 * (size_t)h->Nr * cols))) return rc;
     for (int w = 0; w < nw; ++w) {
         if ((rc = sc.get(&W[w], vb))) return rc;
         if ((rc = sc.get(&V[w], vb))) return rc;
@@ -1032,8 +1153,10 @@ int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStrea
     for (int w = 0; w < nw; ++w) {
         if (h->full) launch_zeta_rhs(coef_of(h->F[w]), h->L[w], N, S, mt, n_dir, W[w], N, st);
         else launch_zero(W[w], vb, st);
-        launch_sample_scatter(V[w], N, h->dnode, h->dmult, h->nu, cols, W[w], N, st);
-        g_launches += 2;
+        // W += R^T R v
+        launch_restrict(V[w], N, h->rnode, h->rw, h->ntap, h->Nr, cols, RV, h->Nr, st);
+        if (h->nt > 0) launch_restrict_adj(RV, h->Nr, h->tnode, h->tptr, h->tq, h->tw, h->nt, cols, W[w], N, st);
+        g_launches += 3;
     }
     for (int w = 0; w < nw; ++w) j2.push_back({h->F[w], W[w], Z[w], cols, N, &i2[w]});
     if ((rc = solve_jobs(j2, true, h->tol, st))) return rc;
@@ -1170,6 +1293,60 @@ int hess_pcg(helm_hess_s* h, const double* b, double* x, double p_alpha, double 
     return HELM_OK;
 }
 
+// Upper-level derivatives at the context's model m_FWI (sensors at points,
+// data given): tau = A^{-1}(g rho u) for every frequency and source (one
+// batched solve), then per sensor and coordinate
+//   dpsi/dp_{q,l} = -sum Re[(d_l tau)(p_q) conj(eps) + tau(p_q) conj(dd_l - (d_l u)(p_q))]
+// and dpsi/dalpha = m^T (Dx^T Dx + Dz^T Dz) rho.  Synchronises the stream.
+int hess_upper(helm_hess_s* h, const double* rho, const double* dd, hipStream_t st, double* dp_host,
+               double* da_host, helm_info* info) {
+    if (!h->full || !h->at_points)
+        return fail(HELM_EINVAL, "upper-level derivatives need a context with data and sensors at points");
+    if (!rho || !dd || !dp_host || !da_host) return fail(HELM_EINVAL, "bad upper_grad arguments");
+    const int64_t N = N_of(h->g);
+    const int S = h->S, nw = h->n_omega, Nr = h->Nr;
+    const size_t fb = sizeof(double) * 2 * (size_t)N * S;
+    Scratch sc(st);
+    std::vector<double*> B(nw), T(nw);
+    double *dp, *Rrho, *part, *da;
+    int rc;
+    for (int w = 0; w < nw; ++w) {
+        if ((rc = sc.get(&B[w], fb))) return rc;
+        if ((rc = sc.get(&T[w], fb))) return rc;
+        launch_gn_rhs(coef_of(h->F[w]), h->U[w], N, S, rho, 1, B[w], N, st);
+    }
+    g_launches += nw;
+    std::vector<SolveJob> jobs;
+    std::vector<helm_info> infos(nw);
+    for (int w = 0; w < nw; ++w) jobs.push_back({h->F[w], B[w], T[w], S, N, &infos[w]});
+    if ((rc = solve_jobs(jobs, false, h->tol, st))) return rc;
+    if ((rc = sc.get(&dp, sizeof(double) * 2 * Nr))) return rc;
+    launch_zero(dp, sizeof(double) * 2 * Nr, st);
+    const size_t plane = (size_t)Nr * RTAP;
+    for (int w = 0; w < nw; ++w)
+        launch_upper(T[w], h->U[w], N, S, h->eps + 2 * (size_t)w * S * Nr, dd + 4 * (size_t)w * S * Nr, h->rnode,
+                     h->rw, h->rw + plane, h->rw + 2 * plane, Nr, dp, st);
+    const int nblk = (int)((N + 255) / 256);
+    if ((rc = sc.get(&Rrho, sizeof(double) * N))) return rc;
+    if ((rc = sc.get(&part, sizeof(double) * std::max(nblk, dot_blocks(N))))) return rc;
+    if ((rc = sc.get(&da, sizeof(double)))) return rc;
+    launch_zero(Rrho, sizeof(double) * N, st);
+    launch_gamma(rho, h->g.nx, h->g.nz, 1.0, 0.0, Rrho, part, nblk, st);
+    launch_dot(h->m, Rrho, N, part, da, st);
+    g_launches += 1 + nw + 4;
+    HIPCHECK(hipMemcpyAsync(dp_host, dp, sizeof(double) * 2 * Nr, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(da_host, da, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    if (info) {
+        helm_info tot{};
+        tot.bad_block = tot.bad_row = -1;
+        for (auto& i1 : infos) merge_info(&tot, i1);
+        *info = tot;
+    }
+    return HELM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI ==
@@ -1297,8 +1474,8 @@ int helm_misfit_grad(const helm_grid* grid, const double* m_dev, int32_t n_omega
                      double* grad_dev, helm_info* info) {
     if (!dobs_dev || !phi_host || !grad_dev) return fail(HELM_EINVAL, "bad misfit_grad arguments");
     helm_hess_s* h = nullptr;
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, alpha, mu, precision,
-                        tol, S_(stream), phi_host, grad_dev, info, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, nullptr, alpha, mu,
+                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
     hess_free(h);
     return rc;
 }
@@ -1309,8 +1486,8 @@ int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega, con
     if (n_dir <= 0 || !mt_dev || !hv_dev) return fail(HELM_EINVAL, "bad gn_hvp arguments");
     helm_hess_s* h = nullptr;
     helm_info i0{};
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, nullptr, S, src_host, Nr, rec_host, alpha, mu, precision,
-                        tol, S_(stream), nullptr, nullptr, &i0, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, nullptr, S, src_host, Nr, rec_host, nullptr, alpha, mu,
+                        precision, tol, S_(stream), nullptr, nullptr, &i0, &h);
     if (rc == HELM_OK) rc = hess_apply(h, n_dir, mt_dev, hv_dev, S_(stream), info);
     if (rc == HELM_OK && info) {
         info->solves += i0.solves;
@@ -1329,13 +1506,61 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
     *out = nullptr;
     if (!dobs_dev && (phi_host || grad_dev)) return fail(HELM_EINVAL, "phi and grad need data");
     helm_hess_s* h = nullptr;
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, alpha, mu, precision,
-                        tol, S_(stream), phi_host, grad_dev, info, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, nullptr, alpha, mu,
+                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
     if (rc) {
         hess_free(h);
         return rc;
     }
     *out = h;
+    return HELM_OK;
+}
+
+int helm_hess_create_at(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host,
+                        const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr,
+                        const double* rec_xz_host, double alpha, double mu, int precision, double tol, void* stream,
+                        double* phi_host, double* grad_dev, helm_info* info, helm_hess_t* out) {
+    if (!out) return fail(HELM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!rec_xz_host) return fail(HELM_EINVAL, "sensor position list is NULL");
+    if (!dobs_dev && (phi_host || grad_dev)) return fail(HELM_EINVAL, "phi and grad need data");
+    helm_hess_s* h = nullptr;
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, nullptr, rec_xz_host, alpha, mu,
+                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
+    if (rc) {
+        hess_free(h);
+        return rc;
+    }
+    *out = h;
+    return HELM_OK;
+}
+
+int helm_upper_grad(helm_hess_t h, const double* rho_dev, const double* ddata_dev, void* stream,
+                    double* dpsi_dp_host, double* dpsi_dalpha_host, helm_info* info) {
+    if (!h) return fail(HELM_EINVAL, "Hessian handle is NULL");
+    return hess_upper(h, rho_dev, ddata_dev, S_(stream), dpsi_dp_host, dpsi_dalpha_host, info);
+}
+
+int helm_restrict(const helm_grid* grid, int32_t Nr, const double* rec_xz_host, int deriv, const double* U_dev,
+                  int32_t S, int64_t ld, double* out_dev, void* stream) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (Nr <= 0 || S <= 0 || !U_dev || !out_dev || deriv < 0 || deriv > 2 || ld < N_of(*grid))
+        return fail(HELM_EINVAL, "bad restrict arguments");
+    HostRTab rt;
+    if ((rc = rtab_points(*grid, Nr, rec_xz_host, &rt))) return rc;
+    hipStream_t st = S_(stream);
+    Scratch sc(st);
+    int* node;
+    double* w;
+    if ((rc = sc.get(&node, sizeof(int) * rt.node.size()))) return rc;
+    if ((rc = sc.get(&w, sizeof(double) * rt.w.size()))) return rc;
+    if ((rc = upload_sync(node, rt.node.data(), sizeof(int) * rt.node.size(), st))) return rc;
+    if ((rc = upload_sync(w, rt.w.data(), sizeof(double) * rt.w.size(), st))) return rc;
+    launch_restrict(U_dev, ld, node, w + (size_t)deriv * Nr * RTAP, RTAP, Nr, S, out_dev, Nr, st);
+    g_launches += 1;
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
     return HELM_OK;
 }
 

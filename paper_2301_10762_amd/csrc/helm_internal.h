@@ -143,18 +143,22 @@ void launch_conj_inplace(double* X, int64_t ld, int64_t N, int S, hipStream_t st
 void launch_axpy_c128(const double* D, int64_t ldd, double* X, int64_t ldx, int64_t N, int S,
                       hipStream_t st);
 void launch_unit_sources(double* E, int64_t ld, int64_t N, const int* nodes, int S, hipStream_t st);
-void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* rec, int Nr, int S,
-                   double* eps, double* phi_part, hipStream_t st);
-void launch_scatter_adj(const double* eps, const int* rec, int Nr, int S, double* R, int64_t ldr,
-                        hipStream_t st);
 void launch_grad(const Coef& cf, const double* U, int64_t ldu, const double* L, int64_t ldl, int S,
                  double* g, hipStream_t st);
 void launch_gn_rhs(const Coef& cf, const double* U, int64_t ldu, int S, const double* mt, int n_dir,
                    double* V, int64_t ldv, hipStream_t st);
-void launch_sample_scatter(const double* V, int64_t ldv, const int* node, const int* mult, int nu, int cols,
-                           double* RV, int64_t ldr, hipStream_t st);
 void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz,
                int n_dir, double* hv, int64_t N, hipStream_t st);
+constexpr int RTAP = 16;   // taps per sensor of the restriction tables (4 x 4 bicubic)
+void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* node, const double* w, int ntap,
+                   int Nr, int S, double* eps, double* phi_part, hipStream_t st);
+void launch_restrict(const double* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr, int cols,
+                     double* out, int64_t ldo, hipStream_t st);
+void launch_restrict_adj(const double* Z, int64_t ldz, const int* tnode, const int* tptr, const int* tq,
+                         const double* tw, int nt, int cols, double* out, int64_t ldo, hipStream_t st);
+void launch_upper(const double* Tau, const double* U, int64_t ld, int S, const double* eps, const double* dd,
+                  const int* node, const double* w0, const double* wx, const double* wz, int Nr, double* dp,
+                  hipStream_t st);
 void launch_zeta_rhs(const Coef& cf, const double* L, int64_t ldl, int S, const double* mt, int n_dir, double* W,
                      int64_t ldw, hipStream_t st);
 void launch_hv_full(const Coef& cf, const double* U, const double* L, int64_t ldu, int S, const double* V,

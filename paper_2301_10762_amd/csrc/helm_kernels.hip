@@ -149,33 +149,6 @@ __global__ void k_unit_sources(double2* E, int64_t ld, int64_t N, const int* nod
     if (k < N) E[(size_t)s * ld + k] = make_double2(k == nodes[s] ? 1.0 : 0.0, 0.0);
 }
 
-// eps_s = d_s - R u_s and 1/2 |eps_s|^2 (one thread per source, receivers in order)
-__global__ void k_misfit(const double2* U, int64_t ldu, const double2* dobs, const int* rec, int Nr, int S,
-                         double2* eps, double* phi_part) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    double acc = 0.0;
-    for (int p = 0; p < Nr; ++p) {
-        double2 u = U[(size_t)s * ldu + rec[p]];
-        double2 dv = dobs[(size_t)s * Nr + p];
-        double2 e = make_double2(dv.x - u.x, dv.y - u.y);
-        eps[(size_t)s * Nr + p] = e;
-        acc += e.x * e.x + e.y * e.y;
-    }
-    phi_part[s] = 0.5 * acc;
-}
-
-// R^* eps: add eps_p onto node rec[p] (buffer zeroed beforehand)
-__global__ void k_scatter_adj(const double2* eps, const int* rec, int Nr, int S, double2* R, int64_t ldr) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    for (int p = 0; p < Nr; ++p) {
-        double2* o = R + (size_t)s * ldr + rec[p];
-        double2 e = eps[(size_t)s * Nr + p];
-        *o = make_double2(o->x + e.x, o->y + e.y);
-    }
-}
-
 // boundary weight b_k: half the length of each boundary edge at node k
 __device__ __forceinline__ double bnd_weight(const Coef& c, int i, int j) {
     double bnd = 0.0;
@@ -221,21 +194,6 @@ __global__ void k_gn_rhs(Coef cf, const double2* U, int64_t ldu, int S, const do
     V[(size_t)col * ldv + k] = make_double2(t * (wk.x * u.x - wk.y * u.y), t * (wk.x * u.y + wk.y * u.x));
 }
 
-// RV += R^* R V: for on-node receivers R^* R is diagonal, with the number of
-// receivers on a node as its entry; one thread per (distinct receiver node,
-// column), so no two threads touch the same element
-__global__ void k_sample_scatter(const double2* V, int64_t ldv, const int* node, const int* mult, int nu,
-                                 double2* RV, int64_t ldr) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (q >= nu) return;
-    const int k = node[q];
-    const double w = (double)mult[q];
-    double2 v = V[(size_t)c * ldv + k];
-    double2* o = RV + (size_t)c * ldr + k;
-    *o = make_double2(o->x + w * v.x, o->y + w * v.y);
-}
-
 // hv_a[k] += Re sum_s wk u_s[k] conj(z_{a,s}[k])
 __global__ void k_hv(Coef cf, const double2* U, int64_t ldu, int S, const double2* Z, int64_t ldz, int n_dir,
                      double* hv) {
@@ -251,6 +209,112 @@ __global__ void k_hv(Coef cf, const double2* U, int64_t ldu, int S, const double
         si += u.y * z.x - u.x * z.y;
     }
     hv[(size_t)a * N + k] += wk.x * sr - wk.y * si;
+}
+
+// ---- restriction R(P): per sensor q up to RTAP taps (node[q*RTAP + a],
+// weight w[q*RTAP + a]); ntap = 1 for sensors on nodes, 16 for the sliding
+// bicubic of sensors between nodes.  w may be the value weights or those of
+// a derivative with respect to the sensor's coordinates.
+
+// out[c][q] = sum_a w[q][a] U[c][node[q][a]]
+__global__ void k_restrict(const double2* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr,
+                           double2* out, int64_t ldo) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (q >= Nr) return;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < ntap; ++a) {
+        const double wa = w[q * RTAP + a];
+        const double2 u = U[(size_t)c * ldu + node[q * RTAP + a]];
+        re += wa * u.x;
+        im += wa * u.y;
+    }
+    out[(size_t)c * ldo + q] = make_double2(re, im);
+}
+
+// eps_s = d_s - R u_s and 1/2 |eps_s|^2 (one thread per source, sensors in order)
+__global__ void k_misfit(const double2* U, int64_t ldu, const double2* dobs, const int* node, const double* w,
+                         int ntap, int Nr, int S, double2* eps, double* phi_part) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double acc = 0.0;
+    for (int q = 0; q < Nr; ++q) {
+        double re = 0.0, im = 0.0;
+        for (int a = 0; a < ntap; ++a) {
+            const double wa = w[q * RTAP + a];
+            const double2 u = U[(size_t)s * ldu + node[q * RTAP + a]];
+            re += wa * u.x;
+            im += wa * u.y;
+        }
+        double2 dv = dobs[(size_t)s * Nr + q];
+        double2 e = make_double2(dv.x - re, dv.y - im);
+        eps[(size_t)s * Nr + q] = e;
+        acc += e.x * e.x + e.y * e.y;
+    }
+    phi_part[s] = 0.5 * acc;
+}
+
+// out[c][tnode[t]] += sum_{e in row t} tw[e] Z[c][tq[e]]: R^T z gathered per
+// distinct node (the transpose of the taps), so no two threads write one element
+__global__ void k_restrict_adj(const double2* Z, int64_t ldz, const int* tnode, const int* tptr, const int* tq,
+                               const double* tw, int nt, double2* out, int64_t ldo) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (t >= nt) return;
+    double re = 0.0, im = 0.0;
+    for (int e = tptr[t]; e < tptr[t + 1]; ++e) {
+        const double2 z = Z[(size_t)c * ldz + tq[e]];
+        re += tw[e] * z.x;
+        im += tw[e] * z.y;
+    }
+    double2* o = out + (size_t)c * ldo + tnode[t];
+    *o = make_double2(o->x + re, o->y + im);
+}
+
+// Upper-level derivative, one frequency (one block of 64 threads per sensor q,
+// the sources strided over the threads, summed in a fixed order):
+//   dp[q][l] += -sum_s Re[ (d_l tau)(p_q) conj(eps_sq) + tau(p_q) conj(dd_sql - (d_l u)(p_q)) ]
+// eps = R(u' - u) (the misfit), dd = dR/dx_l u' (the training data's derivative)
+__global__ __launch_bounds__(64) void k_upper(const double2* Tau, const double2* U, int64_t ld, int S,
+                                              const double2* eps, const double2* dd, const int* node,
+                                              const double* w0, const double* wx, const double* wz, int Nr,
+                                              double* dp) {
+    __shared__ double sx[64], sz[64];
+    const int q = blockIdx.x;
+    double ax = 0.0, az = 0.0;
+    for (int s = threadIdx.x; s < S; s += 64) {
+        double2 t0 = make_double2(0.0, 0.0), tx = t0, tz = t0, ux = t0, uz = t0;
+        for (int a = 0; a < RTAP; ++a) {
+            const int k = node[q * RTAP + a];
+            const double v0 = w0[q * RTAP + a], vx = wx[q * RTAP + a], vz = wz[q * RTAP + a];
+            const double2 tv = Tau[(size_t)s * ld + k], uv = U[(size_t)s * ld + k];
+            t0.x += v0 * tv.x; t0.y += v0 * tv.y;
+            tx.x += vx * tv.x; tx.y += vx * tv.y;
+            tz.x += vz * tv.x; tz.y += vz * tv.y;
+            ux.x += vx * uv.x; ux.y += vx * uv.y;
+            uz.x += vz * uv.x; uz.y += vz * uv.y;
+        }
+        const double2 e = eps[(size_t)s * Nr + q];
+        const double2 gx = dd[((size_t)s * Nr + q) * 2 + 0], gz = dd[((size_t)s * Nr + q) * 2 + 1];
+        const double2 fx = make_double2(gx.x - ux.x, gx.y - ux.y), fz = make_double2(gz.x - uz.x, gz.y - uz.y);
+        // Re[a conj(b)] = a.x b.x + a.y b.y
+        ax -= tx.x * e.x + tx.y * e.y + t0.x * fx.x + t0.y * fx.y;
+        az -= tz.x * e.x + tz.y * e.y + t0.x * fz.x + t0.y * fz.y;
+    }
+    sx[threadIdx.x] = ax;
+    sz[threadIdx.x] = az;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sx[threadIdx.x] += sx[threadIdx.x + h];
+            sz[threadIdx.x] += sz[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        dp[2 * q] += sx[0];
+        dp[2 * q + 1] += sz[0];
+    }
 }
 
 // W[(a*S + s)] = -conj(wk) * mt_a[k] * l_s[k]: the second-order part of the
@@ -401,14 +465,26 @@ void launch_axpy_c128(const double* D, int64_t ldd, double* X, int64_t ldx, int6
 void launch_unit_sources(double* E, int64_t ld, int64_t N, const int* nodes, int S, hipStream_t st) {
     hipLaunchKernelGGL(k_unit_sources, dim3(grid1(N).x, S), dim3(256), 0, st, (double2*)E, ld, N, nodes);
 }
-void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* rec, int Nr, int S, double* eps,
-                   double* phi_part, hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit, grid1(S, 64), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, rec,
-                       Nr, S, (double2*)eps, phi_part);
+void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* node, const double* w, int ntap,
+                   int Nr, int S, double* eps, double* phi_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit, grid1(S, 64), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, node, w,
+                       ntap, Nr, S, (double2*)eps, phi_part);
 }
-void launch_scatter_adj(const double* eps, const int* rec, int Nr, int S, double* R, int64_t ldr, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter_adj, grid1(S, 64), dim3(64), 0, st, (const double2*)eps, rec, Nr, S,
-                       (double2*)R, ldr);
+void launch_restrict(const double* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr, int cols,
+                     double* out, int64_t ldo, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict, dim3(grid1(Nr, 64).x, cols), dim3(64), 0, st, (const double2*)U, ldu, node, w, ntap,
+                       Nr, (double2*)out, ldo);
+}
+void launch_restrict_adj(const double* Z, int64_t ldz, const int* tnode, const int* tptr, const int* tq,
+                         const double* tw, int nt, int cols, double* out, int64_t ldo, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict_adj, dim3(grid1(nt, 64).x, cols), dim3(64), 0, st, (const double2*)Z, ldz, tnode,
+                       tptr, tq, tw, nt, (double2*)out, ldo);
+}
+void launch_upper(const double* Tau, const double* U, int64_t ld, int S, const double* eps, const double* dd,
+                  const int* node, const double* w0, const double* wx, const double* wz, int Nr, double* dp,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_upper, dim3(Nr), dim3(64), 0, st, (const double2*)Tau, (const double2*)U, ld, S,
+                       (const double2*)eps, (const double2*)dd, node, w0, wx, wz, Nr, dp);
 }
 void launch_grad(const Coef& cf, const double* U, int64_t ldu, const double* L, int64_t ldl, int S, double* g,
                  hipStream_t st) {
@@ -419,11 +495,6 @@ void launch_gn_rhs(const Coef& cf, const double* U, int64_t ldu, int S, const do
                    int64_t ldv, hipStream_t st) {
     hipLaunchKernelGGL(k_gn_rhs, dim3(grid1((int64_t)cf.nx * cf.nz).x, n_dir * S), dim3(256), 0, st, cf,
                        (const double2*)U, ldu, S, mt, n_dir, (double2*)V, ldv);
-}
-void launch_sample_scatter(const double* V, int64_t ldv, const int* node, const int* mult, int nu, int cols,
-                           double* RV, int64_t ldr, hipStream_t st) {
-    hipLaunchKernelGGL(k_sample_scatter, dim3(grid1(nu, 64).x, cols), dim3(64), 0, st, (const double2*)V, ldv,
-                       node, mult, nu, (double2*)RV, ldr);
 }
 void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double* Z, int64_t ldz, int n_dir,
                double* hv, int64_t N, hipStream_t st) {

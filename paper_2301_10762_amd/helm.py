@@ -109,6 +109,11 @@ def lib():
     L.helm_hess_create.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
                                    ctypes.POINTER(i32), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp,
                                    I, ctypes.POINTER(_vp)]
+    L.helm_hess_create_at.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
+                                      ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp,
+                                      I, ctypes.POINTER(_vp)]
+    L.helm_upper_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(f64), ctypes.POINTER(f64), I]
+    L.helm_restrict.argtypes = [G, i32, ctypes.POINTER(f64), ctypes.c_int, _vp, i32, i64, _vp, _vp]
     L.helm_hess_apply.argtypes = [_vp, i32, _vp, _vp, _vp, I]
     L.helm_hess_pcg.argtypes = [_vp, _vp, _vp, f64, f64, f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), I]
     L.helm_hess_destroy.argtypes = [_vp]
@@ -132,7 +137,8 @@ def lib():
     L.helm_last_error.restype = ctypes.c_char_p
     for name in ("helm_factor", "helm_factor_batch", "helm_factor_bytes", "helm_solve", "helm_adjoint_solve",
                  "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
-                 "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve"):
+                 "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve",
+                 "helm_hess_create_at", "helm_upper_grad", "helm_restrict"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -357,7 +363,9 @@ class Hessian:
     """Lower-level state at one model for products with the Hessian of phi
     (helm_hess_create): with d_obs ([n_omega][S][Nr] complex) the full
     H = H^(1) + H^(2) + Gamma, without it the Gauss-Newton H^(1) + Gamma.
-    with_grad=True also returns phi and grad phi (data required)."""
+    with_grad=True also returns phi and grad phi (data required).
+    receivers: node indices, or an [Nr][2] float array of sensor points
+    (x, z) with the sliding-cubic restriction (helm_hess_create_at)."""
 
     def __init__(self, grid: Grid, m, omegas, sources, receivers, d_obs=None, alpha: float = 0.0, mu: float = 0.0,
                  precision="fp64", tol: float = 0.0, stream=None, with_grad: bool = False):
@@ -367,7 +375,14 @@ class Hessian:
         md = _dev_f64(m, grid.N)
         n_omega = len(omegas)
         src, psrc = _i32(sources)
-        rec, prec = _i32(receivers)
+        rarr = np.asarray(receivers)
+        self.at_points = rarr.dtype.kind == "f"
+        if self.at_points:
+            rec = np.ascontiguousarray(rarr, dtype=np.float64).reshape(-1, 2)
+            prec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            rec, prec = _i32(receivers)
+        self.n_omega, self.S, self.Nr = n_omega, len(src), len(rec)
         dd = None
         if d_obs is not None:
             dd = _dev_c128(d_obs)
@@ -380,7 +395,8 @@ class Hessian:
         self.grad = torch.empty(grid.N, dtype=torch.float64, device="cuda") if with_grad else None
         info = _Info()
         h = ctypes.c_void_p()
-        _check(lib().helm_hess_create(ctypes.byref(grid.c()), _ptr(md), n_omega, warr,
+        create = lib().helm_hess_create_at if self.at_points else lib().helm_hess_create
+        _check(create(ctypes.byref(grid.c()), _ptr(md), n_omega, warr,
                                       _ptr(dd) if dd is not None else None, len(src), psrc, len(rec), prec,
                                       float(alpha), float(mu), _PREC[precision], float(tol), _stream(stream),
                                       ctypes.byref(phi) if with_grad else None,
@@ -418,6 +434,22 @@ class Hessian:
             _check(rc)
         return x, int(it.value), float(rel.value), Info.of(info)
 
+    def upper_grad(self, rho, ddata, stream=None):
+        """dpsi/dp ([Nr][2], x and z) and dpsi/dalpha for this training
+        model (helm_upper_grad).  ddata: complex [n_omega][S][Nr][2], the
+        sensor-coordinate derivatives of the training wavefield."""
+        rd = _dev_f64(rho, self.grid.N).contiguous()
+        dd = _dev_c128(ddata)
+        if tuple(dd.shape) != (self.n_omega, self.S, self.Nr, 2):
+            raise ValueError("ddata must be [n_omega][S][Nr][2]")
+        dp = np.zeros((self.Nr, 2))
+        da = ctypes.c_double(0.0)
+        info = _Info()
+        _check(lib().helm_upper_grad(self.h, _ptr(rd), _ptr(dd), _stream(stream),
+                                     dp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(da),
+                                     ctypes.byref(info)))
+        return dp, float(da.value), Info.of(info)
+
     def close(self):
         if self.h:
             lib().helm_hess_destroy(self.h)
@@ -428,6 +460,18 @@ class Hessian:
             self.close()
         except Exception:
             pass
+
+
+def restrict(grid: Grid, positions, U, deriv: int = 0, stream=None):
+    """R(P) U (deriv 0) or d/dx (1), d/dz (2) of it for sensors at points
+    ([Nr][2]) and fields U ([S][N] complex); returns [S][Nr] complex."""
+    torch = _torch()
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    Ud = _dev_c128(U).reshape(-1, grid.N).contiguous()
+    out = torch.empty((Ud.shape[0], len(pos)), dtype=torch.complex128, device="cuda")
+    _check(lib().helm_restrict(ctypes.byref(grid.c()), len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               int(deriv), _ptr(Ud), Ud.shape[0], grid.N, _ptr(out), _stream(stream)))
+    return out
 
 
 def gamma_solve(grid: Grid, alpha: float, mu: float, Y, stream=None):
