@@ -56,7 +56,7 @@ def parse():
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
     p.add_argument("--hessian-only", action="store_true",
-                   help="only run the full-Hessian product and PCG measurement at 201^2 and print it")
+                   help="only run the full-Hessian, PCG and upper-level gradient measurements at 201^2")
     return p.parse_args()
 
 
@@ -156,6 +156,56 @@ def hessian_extra(helm, I, w4, G4, dirs, alpha=1e-4, mu=1e-8, precisions=("fp64"
     return out
 
 
+def bilevel_extra(helm, I, w4, G4, alpha=1e-4, mu=1e-8, precision="fp64"):
+    """One upper-level gradient (Algorithm "Derivative of psi") for one
+    training model at 201^2: the training wavefield and its data at 100
+    sensors between nodes, the context at the FWI stand-in, PCG with P2 for
+    rho, then tau and the derivatives."""
+    import numpy as np
+    import torch
+    n_omega, S4 = len(w4.omegas), len(w4.sources)
+    X = (G4.nx - 1) * G4.hx
+    P = np.column_stack([np.linspace(0.02 * X, 0.98 * X, 100) + 0.37 * G4.hx, np.full(100, 2.5 * G4.hz)])
+    P[:, 0] = np.minimum(P[:, 0], X)
+    m_fwi = w4.m_true + 0.1 * (w4.m - w4.m_true)
+    E4 = torch.as_tensor(I.point_sources(G4.N, w4.sources), device="cuda")
+    out = {"sensors": len(P), "precision": precision, "alpha": alpha, "mu": mu, "pcg_rtol": 1e-6}
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fs = helm.factor_batch([G4] * n_omega, [torch.as_tensor(w4.m_true, device="cuda")] * n_omega, w4.omegas,
+                               precision)
+        Ut, _ = helm.solve_batch(Fs, [E4] * n_omega, tol=TOL)
+        for F in Fs:
+            F.close()
+        d = torch.stack([helm.restrict(G4, P, U, 0) for U in Ut])
+        dd = torch.stack([torch.stack([helm.restrict(G4, P, U, 1), helm.restrict(G4, P, U, 2)], dim=-1) for U in Ut])
+        del Ut
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        H = helm.Hessian(G4, m_fwi, w4.omegas, w4.sources, P, d, alpha, mu, precision=precision, tol=TOL)
+        try:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rho, it, rr, _ = H.pcg(w4.m_true - m_fwi, prec_alpha=alpha, prec_mu=mu, rtol=1e-6, maxit=300)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            dp, da, _ = H.upper_grad(rho, dd)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+        finally:
+            H.close()
+    # solves: training wavefields, u and lambda, two per PCG product (one
+    # more for r_0), tau
+    solves = n_omega * S4 * (1 + 2 + 2 * (it + 1) + 1)
+    out.update({"data_ms": round((t1 - t0) * 1e3, 3), "context_ms": round((t2 - t1) * 1e3, 3),
+                "pcg": {"iterations": it, "relres": rr, "ms": round((t3 - t2) * 1e3, 3)},
+                "upper_grad_ms": round((t4 - t3) * 1e3, 3), "total_ms": round((t4 - t0) * 1e3, 3),
+                "solves": solves, "solves_per_s": round(solves / (t4 - t0), 2),
+                "dpsi_dalpha": da, "dpsi_dp_norm": float(np.linalg.norm(dp))})
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -186,7 +236,8 @@ def main():
         w4 = I.config_c4()
         G4 = helm.Grid.of(w4)
         dirs = torch.as_tensor(np.stack(w4.directions), device="cuda")
-        print(json.dumps({"hessian_201": hessian_extra(helm, I, w4, G4, dirs)}), flush=True)
+        print(json.dumps({"hessian_201": hessian_extra(helm, I, w4, G4, dirs),
+                          "upper_grad_201": bilevel_extra(helm, I, w4, G4)}), flush=True)
         return
 
     w = I.config_c3()
@@ -357,6 +408,9 @@ def main():
         # data at the true model.  One context (factors, u, lambda) serves
         # the 8-direction product and every PCG iteration.
         extras["hessian_201"] = hessian_extra(helm, I, w4, G4, dirs)
+        # the upper-level gradient of one training model with 100 sensors
+        # between nodes (Algorithm "Derivative of psi")
+        extras["upper_grad_201"] = bilevel_extra(helm, I, w4, G4)
 
     cpu = None
     if not args.no_cpu_baseline:

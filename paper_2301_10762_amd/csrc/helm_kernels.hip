@@ -232,13 +232,14 @@ __global__ void k_restrict(const double2* U, int64_t ldu, const int* node, const
     out[(size_t)c * ldo + q] = make_double2(re, im);
 }
 
-// eps_s = d_s - R u_s and 1/2 |eps_s|^2 (one thread per source, sensors in order)
-__global__ void k_misfit(const double2* U, int64_t ldu, const double2* dobs, const int* node, const double* w,
-                         int ntap, int Nr, int S, double2* eps, double* phi_part) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+// eps_s = d_s - R u_s and 1/2 |eps_s|^2: one block of 64 threads per
+// source, the sensors strided over the threads, |eps|^2 summed in a fixed order
+__global__ __launch_bounds__(64) void k_misfit(const double2* U, int64_t ldu, const double2* dobs, const int* node,
+                                               const double* w, int ntap, int Nr, double2* eps, double* phi_part) {
+    __shared__ double sq[64];
+    const int s = blockIdx.x;
     double acc = 0.0;
-    for (int q = 0; q < Nr; ++q) {
+    for (int q = threadIdx.x; q < Nr; q += 64) {
         double re = 0.0, im = 0.0;
         for (int a = 0; a < ntap; ++a) {
             const double wa = w[q * RTAP + a];
@@ -251,7 +252,13 @@ __global__ void k_misfit(const double2* U, int64_t ldu, const double2* dobs, con
         eps[(size_t)s * Nr + q] = e;
         acc += e.x * e.x + e.y * e.y;
     }
-    phi_part[s] = 0.5 * acc;
+    sq[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sq[threadIdx.x] += sq[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) phi_part[s] = 0.5 * sq[0];
 }
 
 // out[c][tnode[t]] += sum_{e in row t} tw[e] Z[c][tq[e]]: R^T z gathered per
@@ -467,8 +474,8 @@ void launch_unit_sources(double* E, int64_t ld, int64_t N, const int* nodes, int
 }
 void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* node, const double* w, int ntap,
                    int Nr, int S, double* eps, double* phi_part, hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit, grid1(S, 64), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, node, w,
-                       ntap, Nr, S, (double2*)eps, phi_part);
+    hipLaunchKernelGGL(k_misfit, dim3(S), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, node, w,
+                       ntap, Nr, (double2*)eps, phi_part);
 }
 void launch_restrict(const double* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr, int cols,
                      double* out, int64_t ldo, hipStream_t st) {
