@@ -34,6 +34,8 @@ What each function follows:
   * upper-level derivatives dpsi/dp_{j,l}, dpsi/dalpha (theorems on the
     derivatives of psi, eqs (gradALT), (gradALT1), (tau_def), (sograda))
                                                            -> upper_grad
+  * lower-level FWI by L-BFGS with a strong-Wolfe line search (App.
+    "Optimisation")                                        -> lbfgs, fwi
 
 Readings where the paper is silent (each pinned by a test in tests/):
   * corner mass weight hx*hz/4 (mean of the two triangulation directions);
@@ -509,3 +511,149 @@ def upper_grad(g: Grid, m_fwi, m_train, omegas, sources, sensors: "Sensors", rho
             dp[:, col] -= np.real(np.sum(dtau * np.conj(du) + tau * np.conj(ddu), axis=0))
     Rg = regulariser(g, 1.0, 0.0)
     return dp, float(m_fwi @ (Rg @ rho))
+
+
+def _cubic_min(a, fa, da, b, fb, db):
+    """Minimiser of the cubic matching f and f' at a and b (Nocedal & Wright,
+    the interpolation step of the line search), or None if it has none."""
+    d1 = da + db - 3.0 * (fa - fb) / (a - b)
+    disc = d1 * d1 - da * db
+    if not np.isfinite(disc) or disc < 0.0:
+        return None
+    d2 = np.copysign(np.sqrt(disc), b - a)
+    den = db - da + 2.0 * d2
+    if den == 0.0:
+        return None
+    return b - (b - a) * (db + d2 - d1) / den
+
+
+def lbfgs(fg, x0, memory: int = 5, max_iters: int = 50, gtol: float = 1e-6, c1: float = 1e-4, c2: float = 0.9,
+          max_evals: int = 20, first_change: float = 0.01):
+    """L-BFGS with a strong-Wolfe line search: the lower-level optimiser of
+    the paper (App. "Optimisation": L-BFGS with Wolfe line search, after
+    Nocedal & Wright), written from the textbook:
+
+    * direction: two-loop recursion over the last `memory` pairs (s, y),
+      initial matrix (s.y / y.y) I; the first iteration (and any iteration
+      whose direction is not a descent direction, after clearing the pairs)
+      uses p = -g with the trial step chosen so that the model changes by
+      first_change * max|x| at most;
+    * line search: trial steps 1 (doubling while the strong Wolfe conditions
+      f <= f0 + c1 a f0', |f'| <= c2 |f0'| are unmet and f still decreases),
+      then zoom on the bracket by the safeguarded cubic interpolation (kept
+      at least a tenth of the bracket from its ends, else bisection);
+      a point where f is undefined (fg raises ValueError, e.g. a model with
+      m_k <= 0) counts as f = +inf;
+    * stop when ||g|| <= gtol ||g_0|| or after max_iters iterations.
+
+    fg(x) -> (f, g).  Returns (x, info) with iterations, evaluations, f and
+    ||g|| at start and end, the f history and a status string."""
+    x = np.array(x0, dtype=np.float64)
+    f, g = fg(x)
+    evals = 1
+    f0, gn0 = f, float(np.linalg.norm(g))
+    S, Y = [], []
+    hist = [f]
+    status = "max_iters"
+    it = 0
+
+    def ev(a, p):
+        nonlocal evals
+        evals += 1
+        try:
+            fa, ga = fg(x + a * p)
+        except ValueError:
+            return np.inf, None, np.nan
+        return fa, ga, float(ga @ p)
+
+    while it < max_iters:
+        if np.linalg.norm(g) <= gtol * gn0:
+            status = "converged"
+            break
+        q = g.copy()
+        al = []
+        for s, y in zip(reversed(S), reversed(Y)):
+            a_ = float(s @ q) / float(y @ s)
+            al.append(a_)
+            q -= a_ * y
+        if S:
+            q *= float(S[-1] @ Y[-1]) / float(Y[-1] @ Y[-1])
+        for (s, y), a_ in zip(zip(S, Y), reversed(al)):
+            b_ = float(y @ q) / float(y @ s)
+            q += (a_ - b_) * s
+        p = -q
+        d0 = float(g @ p)
+        if not S or not d0 < 0.0:
+            S, Y = [], []
+            p = -g
+            d0 = float(g @ p)
+            a_try = first_change * np.max(np.abs(x)) / np.max(np.abs(g))
+        else:
+            a_try = 1.0
+        # bracketing
+        a_prev, f_prev, g_prev, d_prev = 0.0, f, g, d0
+        found = None
+        for i in range(max_evals):
+            fa, ga, da = ev(a_try, p)
+            if fa > f + c1 * a_try * d0 or (i > 0 and fa >= f_prev):
+                lo, hi = (a_prev, f_prev, g_prev, d_prev), (a_try, fa, ga, da)
+                break
+            if abs(da) <= -c2 * d0:
+                found = (a_try, fa, ga)
+                break
+            if da >= 0.0:
+                lo, hi = (a_try, fa, ga, da), (a_prev, f_prev, g_prev, d_prev)
+                break
+            a_prev, f_prev, g_prev, d_prev = a_try, fa, ga, da
+            a_try *= 2.0
+        else:
+            status = "line_search"
+            break
+        # zoom
+        n_left = max_evals - (i + 1)
+        while found is None and n_left > 0:
+            (al_, fl, gl, dl), (ah, fh, gh, dh) = lo, hi
+            w = abs(ah - al_)
+            a_ = _cubic_min(al_, fl, dl, ah, fh, dh) if np.isfinite(fh) else None
+            if a_ is None or not (min(al_, ah) + 0.1 * w <= a_ <= max(al_, ah) - 0.1 * w):
+                a_ = 0.5 * (al_ + ah)
+            fa, ga, da = ev(a_, p)
+            n_left -= 1
+            if fa > f + c1 * a_ * d0 or fa >= fl:
+                hi = (a_, fa, ga, da)
+            else:
+                if abs(da) <= -c2 * d0:
+                    found = (a_, fa, ga)
+                    break
+                if da * (ah - al_) >= 0.0:
+                    hi = lo
+                lo = (a_, fa, ga, da)
+        if found is None:
+            status = "line_search"
+            break
+        a_, fa, ga = found
+        s_ = a_ * p
+        y_ = ga - g
+        x = x + s_
+        f, g = fa, ga
+        if float(s_ @ y_) > 0.0:
+            S.append(s_)
+            Y.append(y_)
+            if len(S) > memory:
+                S.pop(0)
+                Y.pop(0)
+        it += 1
+        hist.append(f)
+    else:
+        if np.linalg.norm(g) <= gtol * gn0:
+            status = "converged"
+    return x, {"iterations": it, "evals": evals, "f0": f0, "f": f, "gnorm0": gn0,
+               "gnorm": float(np.linalg.norm(g)), "history": hist, "status": status}
+
+
+def fwi(g: Grid, m0, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: float = 0.0, **opts):
+    """Lower-level FWI: m_FWI = argmin phi(m) (eq (newphi)) by lbfgs from m0,
+    phi and grad phi from misfit_grad (App. "Optimisation").  Returns (m, info)."""
+    def fg(m):
+        return misfit_grad(g, m, omegas, d_obs, sources, receivers, alpha, mu)
+    return lbfgs(fg, m0, **opts)

@@ -157,3 +157,39 @@ def test_upper_mutation_caught(name):
     old, new = UPPER_MUTATIONS[name]
     ep, ea = upper_fd_errors(b, _mutant_upper(old, new))
     assert max(ep, ea) > 1e-4, (ep, ea)
+
+
+# ------------------------------------------------------------------ L-BFGS --
+
+def _mutant_lbfgs(old, new):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.lbfgs))
+    assert src.count(old) == 1, old
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns["lbfgs"]
+
+
+LBFGS_MUTATIONS = {
+    "first_loop_oldest_first": ("for s, y in zip(reversed(S), reversed(Y)):", "for s, y in zip(S, Y):"),
+    "second_loop_sign": ("q += (a_ - b_) * s", "q += (b_ - a_) * s"),
+    "memory_never_kept": ("S.append(s_)\n            Y.append(y_)", "pass"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LBFGS_MUTATIONS))
+def test_lbfgs_mutation_caught(name):
+    """Each planted mistake breaks the quadratic-termination pin (or stops
+    the run short of the solution)."""
+    import numpy as np
+    old, new = LBFGS_MUTATIONS[name]
+    opt = _mutant_lbfgs(old, new)
+    rng = np.random.default_rng(12)
+    n = 12
+    B = rng.standard_normal((n, n))
+    A = B @ B.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x, info = opt(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.ones(n), memory=n, max_iters=100, gtol=1e-8,
+                  c2=1e-2)
+    assert info["status"] != "converged" or info["iterations"] > n + 1
