@@ -251,6 +251,43 @@ void helm_hess_destroy(helm_hess_t h);
 int helm_gamma_solve(const helm_grid* grid, double alpha, double mu, int32_t n, const double* Y_dev,
                      double* X_dev, void* stream);
 
+/* ---- lower-level FWI ------------------------------------------------------ */
+
+typedef struct {
+    int32_t memory;         /* (s, y) pairs kept */
+    int32_t max_iters;      /* iterations */
+    int32_t max_evals;      /* evaluations per line search */
+    double gtol;            /* stop when ||grad|| <= gtol ||grad_0|| */
+    double c1, c2;          /* strong Wolfe constants, 0 < c1 < c2 < 1 */
+    double first_change;    /* first trial step changes m by first_change * max|m| */
+} helm_lbfgs_opts;
+
+typedef struct {
+    int32_t iterations, evals;
+    int32_t status;         /* 0 converged, 1 iteration limit, 2 line search failed */
+    double phi0, phi, gnorm0, gnorm;
+    int64_t solves;         /* Helmholtz solves of all evaluations */
+} helm_fwi_info;
+
+/* helm_fwi: the lower-level FWI m_FWI = argmin phi(m) (eq (newphi)) by
+ * L-BFGS with a strong-Wolfe line search (App. "Optimisation", after
+ * Nocedal & Wright): two-loop recursion with initial matrix (s.y/y.y) I;
+ * the first step along -grad scaled so that m changes by first_change *
+ * max|m|; trial steps 1, 2, 4, .. until the strong Wolfe conditions hold or
+ * the minimum is bracketed, then zoom by the cubic interpolation of f, f'
+ * at the bracket's ends (bisection when it falls within a tenth of them).
+ * A trial model with some m_k <= 0 counts as phi = +inf.  Each evaluation
+ * is phi and grad phi as helm_misfit_grad computes them, with receiver
+ * nodes rec_host or sensor points rec_xz_host (exactly one non-NULL; see
+ * helm_hess_create_at).  m_dev: the start model on entry, the result on
+ * return.  phi_hist_host (optional): max_iters + 1 doubles, phi at every
+ * iterate.  The statuses are results, not errors.  Synchronises `stream`. */
+int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double* omegas_host,
+             const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr,
+             const int32_t* rec_host, const double* rec_xz_host, double alpha, double mu,
+             int precision, double tol, const helm_lbfgs_opts* opts, void* stream,
+             double* phi_hist_host, helm_fwi_info* info);
+
 /* ---- building blocks exposed for tests and measurement ------------------ */
 
 /* r = B - A(m, w) X (FP64, five-point form of App. A.1) and, per column,

@@ -657,3 +657,17 @@ def fwi(g: Grid, m0, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: 
     def fg(m):
         return misfit_grad(g, m, omegas, d_obs, sources, receivers, alpha, mu)
     return lbfgs(fg, m0, **opts)
+
+
+def fwi_continuation(g: Grid, m0, groups, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: float = 0.0,
+                     **opts):
+    """FWI over frequency groups in turn, each from the previous result (the
+    lower level of the bilevel frequency continuation, App. "Bilevel
+    Frequency Continuation")."""
+    m = np.array(m0, dtype=np.float64)
+    infos = []
+    for grp in groups:
+        idx = [int(i) for i in grp]
+        m, info = fwi(g, m, [omegas[i] for i in idx], np.asarray(d_obs)[idx], sources, receivers, alpha, mu, **opts)
+        infos.append(info)
+    return m, infos

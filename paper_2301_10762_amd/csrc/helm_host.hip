@@ -1347,6 +1347,268 @@ int hess_upper(helm_hess_s* h, const double* rho, const double* dd, hipStream_t 
     return HELM_OK;
 }
 
+// ------------------------------------------------------------ L-BFGS FWI --
+
+// Lower-level FWI: minimise phi(m) (eq (newphi)) by L-BFGS with a
+// strong-Wolfe line search (the optimiser of App. "Optimisation", after
+// Nocedal & Wright): two-loop recursion with initial matrix (s.y / y.y) I;
+// the first step along -g scaled to change m by first_change * max|m|;
+// trial steps 1, 2, 4, .. until the strong Wolfe conditions hold or a
+// bracket is found, then zoom by the safeguarded cubic interpolation
+// (bisection when it falls within a tenth of the bracket's ends).  A trial
+// model with m_k <= 0 counts as phi = +inf.  All vectors live on the device;
+// each evaluation is one hess_build (factor, u, lambda, phi, grad).
+struct Fwi {
+    const helm_grid* grid;
+    int n_omega;
+    const double* omegas;
+    const double* dobs;
+    int S;
+    const int32_t* src;
+    int Nr;
+    const int32_t* rec;
+    const double* rec_xz;
+    double alpha, mu;
+    int precision;
+    double tol;
+    hipStream_t st;
+    int64_t N;
+    double *part, *scal;
+    int evals = 0;
+    helm_info tot{};
+
+    int dot(const double* a, const double* b, double* out) {
+        launch_dot(a, b, N, part, scal, st);
+        g_launches += 2;
+        HIPCHECK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        return HELM_OK;
+    }
+    int absmax(const double* a, double* out) {
+        const int nb = dot_blocks(N);
+        std::vector<double> h(nb);
+        launch_absmax(a, N, part, st);
+        g_launches += 1;
+        HIPCHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        double mx = 0.0;
+        for (double v : h) mx = std::max(mx, v);
+        *out = mx;
+        return HELM_OK;
+    }
+    // phi and grad at x; *f = +inf (grad untouched) where some m_k <= 0
+    int eval(const double* x, double* f, double* g) {
+        ++evals;
+        int rc = check_model(x, N, st);
+        if (rc == HELM_EINVAL) {
+            *f = INFINITY;
+            return HELM_OK;
+        }
+        if (rc) return rc;
+        helm_hess_s* h = nullptr;
+        helm_info inf{};
+        rc = hess_build(grid, x, n_omega, omegas, dobs, S, src, Nr, rec, rec_xz, alpha, mu, precision, tol, st, f, g,
+                        &inf, &h);
+        hess_free(h);
+        if (rc) return rc;
+        merge_info(&tot, inf);
+        return HELM_OK;
+    }
+};
+
+int fwi_run(Fwi& P, double* x, const helm_lbfgs_opts& o, double* hist, helm_fwi_info* out) {
+    const int64_t N = P.N;
+    const size_t vb = sizeof(double) * N;
+    const int mem = o.memory;
+    hipStream_t st = P.st;
+    Scratch sc(st);
+    double *g, *p, *xt, *gt, *q;
+    // mem + 1 slots: the pairs in use plus one for the step being taken
+    std::vector<double*> Sv(mem + 1), Yv(mem + 1);
+    int rc;
+    for (double** b : {&g, &p, &xt, &gt, &q})
+        if ((rc = sc.get(b, vb))) return rc;
+    for (int i = 0; i <= mem; ++i) {
+        if ((rc = sc.get(&Sv[i], vb))) return rc;
+        if ((rc = sc.get(&Yv[i], vb))) return rc;
+    }
+    if ((rc = sc.get(&P.part, sizeof(double) * dot_blocks(N)))) return rc;
+    if ((rc = sc.get(&P.scal, sizeof(double) * 2))) return rc;
+    double f = 0.0;
+    if ((rc = P.eval(x, &f, g))) return rc;
+    if (!std::isfinite(f)) return fail(HELM_EINVAL, "the start model must be positive");
+    double gg;
+    if ((rc = P.dot(g, g, &gg))) return rc;
+    const double gn0 = std::sqrt(gg);
+    out->phi0 = f;
+    out->gnorm0 = gn0;
+    if (hist) hist[0] = f;
+    // pairs in use, oldest first (slot indices), and their s.y
+    std::vector<int> order;
+    std::vector<double> ys(mem + 1, 0.0);
+    int status = 1, it = 0;
+    for (;;) {
+        if (std::sqrt(gg) <= o.gtol * gn0) {
+            status = 0;
+            break;
+        }
+        if (it >= o.max_iters) break;
+        // two-loop recursion: p = -H g
+        launch_lincomb(q, 1.0, g, 0.0, g, N, st);
+        g_launches += 1;
+        std::vector<double> al(order.size());
+        for (int k = (int)order.size() - 1; k >= 0; --k) {
+            const int i = order[k];
+            double sq;
+            if ((rc = P.dot(Sv[i], q, &sq))) return rc;
+            al[k] = sq / ys[i];
+            launch_lincomb(q, 1.0, q, -al[k], Yv[i], N, st);
+            g_launches += 1;
+        }
+        if (!order.empty()) {
+            const int i = order.back();
+            double yy;
+            if ((rc = P.dot(Yv[i], Yv[i], &yy))) return rc;
+            launch_lincomb(q, ys[i] / yy, q, 0.0, q, N, st);
+            g_launches += 1;
+        }
+        for (int k = 0; k < (int)order.size(); ++k) {
+            const int i = order[k];
+            double yq;
+            if ((rc = P.dot(Yv[i], q, &yq))) return rc;
+            launch_lincomb(q, 1.0, q, al[k] - yq / ys[i], Sv[i], N, st);
+            g_launches += 1;
+        }
+        launch_lincomb(p, -1.0, q, 0.0, q, N, st);
+        g_launches += 1;
+        double d0;
+        if ((rc = P.dot(g, p, &d0))) return rc;
+        double a_try = 1.0;
+        if (order.empty() || !(d0 < 0.0)) {
+            order.clear();
+            launch_lincomb(p, -1.0, g, 0.0, g, N, st);
+            g_launches += 1;
+            if ((rc = P.dot(g, p, &d0))) return rc;
+            double mx, mg;
+            if ((rc = P.absmax(x, &mx))) return rc;
+            if ((rc = P.absmax(g, &mg))) return rc;
+            a_try = o.first_change * mx / mg;
+        }
+        // trial point: xt = x + a p, its phi, gradient gt and slope gt.p
+        auto trial = [&](double a, double* fa, double* da) -> int {
+            launch_lincomb(xt, 1.0, x, a, p, N, st);
+            g_launches += 1;
+            int r = P.eval(xt, fa, gt);
+            if (r) return r;
+            *da = NAN;
+            if (std::isfinite(*fa)) r = P.dot(gt, p, da);
+            return r;
+        };
+        double a_prev = 0.0, f_prev = f, d_prev = d0;
+        double lo[3], hi[3];
+        bool found = false, bracket = false;
+        double a_acc = 0.0, f_acc = 0.0;
+        int used = 0;
+        for (int i = 0; i < o.max_evals; ++i) {
+            double fa, da;
+            if ((rc = trial(a_try, &fa, &da))) return rc;
+            used = i + 1;
+            if (fa > f + o.c1 * a_try * d0 || (i > 0 && fa >= f_prev)) {
+                lo[0] = a_prev, lo[1] = f_prev, lo[2] = d_prev;
+                hi[0] = a_try, hi[1] = fa, hi[2] = da;
+                bracket = true;
+                break;
+            }
+            if (std::fabs(da) <= -o.c2 * d0) {
+                found = true;
+                a_acc = a_try, f_acc = fa;
+                break;
+            }
+            if (da >= 0.0) {
+                lo[0] = a_try, lo[1] = fa, lo[2] = da;
+                hi[0] = a_prev, hi[1] = f_prev, hi[2] = d_prev;
+                bracket = true;
+                break;
+            }
+            a_prev = a_try, f_prev = fa, d_prev = da;
+            a_try *= 2.0;
+        }
+        if (!found && !bracket) {
+            status = 2;
+            break;
+        }
+        int left = o.max_evals - used;
+        while (!found && left > 0) {
+            const double w = std::fabs(hi[0] - lo[0]);
+            double a = NAN;
+            bool ok = false;
+            if (std::isfinite(hi[1])) {
+                // minimiser of the cubic matching f, f' at both ends
+                const double d1 = lo[2] + hi[2] - 3.0 * (lo[1] - hi[1]) / (lo[0] - hi[0]);
+                const double disc = d1 * d1 - lo[2] * hi[2];
+                if (std::isfinite(disc) && disc >= 0.0) {
+                    const double d2 = std::copysign(std::sqrt(disc), hi[0] - lo[0]);
+                    const double den = hi[2] - lo[2] + 2.0 * d2;
+                    if (den != 0.0) {
+                        a = hi[0] - (hi[0] - lo[0]) * (hi[2] + d2 - d1) / den;
+                        ok = std::min(lo[0], hi[0]) + 0.1 * w <= a && a <= std::max(lo[0], hi[0]) - 0.1 * w;
+                    }
+                }
+            }
+            if (!ok) a = 0.5 * (lo[0] + hi[0]);
+            double fa, da;
+            if ((rc = trial(a, &fa, &da))) return rc;
+            --left;
+            if (fa > f + o.c1 * a * d0 || fa >= lo[1]) {
+                hi[0] = a, hi[1] = fa, hi[2] = da;
+            } else {
+                if (std::fabs(da) <= -o.c2 * d0) {
+                    found = true;
+                    a_acc = a, f_acc = fa;
+                    break;
+                }
+                if (da * (hi[0] - lo[0]) >= 0.0) {
+                    hi[0] = lo[0], hi[1] = lo[1], hi[2] = lo[2];
+                }
+                lo[0] = a, lo[1] = fa, lo[2] = da;
+            }
+        }
+        if (!found) {
+            status = 2;
+            break;
+        }
+        // accept: s = a p, y = gt - g, x = xt, g = gt
+        int slot = 0;
+        while (std::find(order.begin(), order.end(), slot) != order.end()) ++slot;
+        double* sv = Sv[slot];
+        double* yv = Yv[slot];
+        launch_lincomb(sv, a_acc, p, 0.0, p, N, st);
+        launch_lincomb(yv, 1.0, gt, -1.0, g, N, st);
+        launch_lincomb(x, 1.0, x, 1.0, sv, N, st);
+        launch_lincomb(g, 1.0, gt, 0.0, gt, N, st);
+        g_launches += 4;
+        f = f_acc;
+        double sy;
+        if ((rc = P.dot(sv, yv, &sy))) return rc;
+        if (sy > 0.0) {
+            if ((int)order.size() == mem) order.erase(order.begin());
+            order.push_back(slot);
+            ys[slot] = sy;
+        }
+        ++it;
+        if (hist) hist[it] = f;
+        if ((rc = P.dot(g, g, &gg))) return rc;
+    }
+    out->iterations = it;
+    out->evals = P.evals;
+    out->status = status;
+    out->phi = f;
+    out->gnorm = std::sqrt(gg);
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    return HELM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI ==
@@ -1562,6 +1824,29 @@ int helm_restrict(const helm_grid* grid, int32_t Nr, const double* rec_xz_host, 
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(st));
     return HELM_OK;
+}
+
+int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double* omegas_host,
+             const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
+             const double* rec_xz_host, double alpha, double mu, int precision, double tol,
+             const helm_lbfgs_opts* opts, void* stream, double* phi_hist_host, helm_fwi_info* info) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!m_dev || !dobs_dev || !opts || !info || n_omega <= 0 || S <= 0 || Nr <= 0)
+        return fail(HELM_EINVAL, "bad fwi arguments");
+    if ((rec_host != nullptr) == (rec_xz_host != nullptr))
+        return fail(HELM_EINVAL, "give either receiver nodes or sensor points");
+    const helm_lbfgs_opts& o = *opts;
+    if (o.memory < 1 || o.max_iters < 0 || o.max_evals < 1 || !(o.gtol >= 0.0) || !(o.c1 > 0.0) ||
+        !(o.c1 < o.c2) || !(o.c2 < 1.0) || !(o.first_change > 0.0))
+        return fail(HELM_EINVAL, "bad L-BFGS options (need memory >= 1, 0 < c1 < c2 < 1, first_change > 0)");
+    Fwi P{grid, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, rec_xz_host, alpha, mu, precision, tol,
+          S_(stream), N_of(*grid), nullptr, nullptr};
+    P.tot.bad_block = P.tot.bad_row = -1;
+    *info = helm_fwi_info{};
+    rc = fwi_run(P, m_dev, o, phi_hist_host, info);
+    info->solves = P.tot.solves;
+    return rc;
 }
 
 int helm_hess_apply(helm_hess_t h, int32_t n_dir, const double* mt_dev, double* hv_dev, void* stream,

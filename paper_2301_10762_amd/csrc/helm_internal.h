@@ -165,6 +165,7 @@ void launch_hv_full(const Coef& cf, const double* U, const double* L, int64_t ld
                     const double* Z, int64_t ldz, const double* mt, int n_dir, double* hv, hipStream_t st);
 int dot_blocks(int64_t n);
 void launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t st);
+void launch_absmax(const double* x, int64_t n, double* part, hipStream_t st);   // dot_blocks(n) partial maxima
 void launch_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t st);
 // Gamma(alpha, mu)^{-1} on nvec grid vectors by its eigen-decomposition:
 // Cx (nx x nx) and Cz (nz x nz) orthonormal DCT-II matrices, eig (nz x nx)

@@ -380,6 +380,19 @@ __global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, i
     if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
 }
 
+// per-block maxima of |x|
+__global__ __launch_bounds__(256) void k_absmax(const double* x, int64_t n, double* part) {
+    __shared__ double sq[256];
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    sq[threadIdx.x] = k < n ? fabs(x[k]) : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sq[threadIdx.x] = fmax(sq[threadIdx.x], sq[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
+}
+
 // out = a x + b y (out may be x or y)
 __global__ void k_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -524,6 +537,9 @@ void launch_dot(const double* x, const double* y, int64_t n, double* part, doubl
     const int nb = dot_blocks(n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(256), 0, st, x, y, n, part);
     hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(64), 0, st, part, nb, out);
+}
+void launch_absmax(const double* x, int64_t n, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_absmax, dim3(dot_blocks(n)), dim3(256), 0, st, x, n, part);
 }
 void launch_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_lincomb, grid1(n), dim3(256), 0, st, out, a, x, b, y, n);

@@ -114,6 +114,9 @@ def lib():
                                       I, ctypes.POINTER(_vp)]
     L.helm_upper_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(f64), ctypes.POINTER(f64), I]
     L.helm_restrict.argtypes = [G, i32, ctypes.POINTER(f64), ctypes.c_int, _vp, i32, i64, _vp, _vp]
+    L.helm_fwi.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+                           ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64, ctypes.POINTER(_LbfgsOpts), _vp,
+                           ctypes.POINTER(f64), ctypes.POINTER(_FwiInfo)]
     L.helm_hess_apply.argtypes = [_vp, i32, _vp, _vp, _vp, I]
     L.helm_hess_pcg.argtypes = [_vp, _vp, _vp, f64, f64, f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), I]
     L.helm_hess_destroy.argtypes = [_vp]
@@ -138,7 +141,7 @@ def lib():
     for name in ("helm_factor", "helm_factor_batch", "helm_factor_bytes", "helm_solve", "helm_adjoint_solve",
                  "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
                  "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve",
-                 "helm_hess_create_at", "helm_upper_grad", "helm_restrict"):
+                 "helm_hess_create_at", "helm_upper_grad", "helm_restrict", "helm_fwi"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -357,6 +360,72 @@ def gn_hvp(grid: Grid, m, omegas, sources, receivers, directions, alpha: float =
                              mt.shape[0], _ptr(mt), float(alpha), float(mu), _PREC[precision], float(tol),
                              _stream(stream), _ptr(hv), ctypes.byref(info)))
     return hv, Info.of(info)
+
+
+class _LbfgsOpts(ctypes.Structure):
+    _fields_ = [("memory", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_evals", ctypes.c_int32),
+                ("gtol", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("first_change", ctypes.c_double)]
+
+
+class _FwiInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("evals", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("phi0", ctypes.c_double), ("phi", ctypes.c_double), ("gnorm0", ctypes.c_double),
+                ("gnorm", ctypes.c_double), ("solves", ctypes.c_int64)]
+
+
+_FWI_STATUS = {0: "converged", 1: "max_iters", 2: "line_search"}
+
+
+def fwi(grid: Grid, m0, omegas, d_obs, sources, receivers, alpha: float = 0.0, mu: float = 0.0, precision="fp64",
+        tol: float = 0.0, memory: int = 5, max_iters: int = 50, gtol: float = 1e-6, c1: float = 1e-4,
+        c2: float = 0.9, max_evals: int = 20, first_change: float = 0.01, stream=None):
+    """Lower-level FWI by L-BFGS with a strong-Wolfe line search (helm_fwi).
+    receivers: node indices or [Nr][2] sensor points.  Returns (m, info)
+    with info = {iterations, evals, status, phi0, phi, gnorm0, gnorm,
+    solves, history}."""
+    m = _dev_f64(m0, grid.N).clone()
+    n_omega = len(omegas)
+    src, psrc = _i32(sources)
+    rarr = np.asarray(receivers)
+    if rarr.dtype.kind == "f":
+        rec = np.ascontiguousarray(rarr, dtype=np.float64).reshape(-1, 2)
+        prec_i, prec_xz = None, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    else:
+        rec, prec_i = _i32(receivers)
+        prec_xz = None
+    dd = _dev_c128(d_obs)
+    if tuple(dd.shape) != (n_omega, len(src), len(rec)):
+        raise ValueError("d_obs must be [n_omega][S][Nr]")
+    warr = (ctypes.c_double * n_omega)(*[float(w) for w in omegas])
+    opts = _LbfgsOpts(int(memory), int(max_iters), int(max_evals), float(gtol), float(c1), float(c2),
+                      float(first_change))
+    hist = (ctypes.c_double * (int(max_iters) + 1))()
+    info = _FwiInfo()
+    _check(lib().helm_fwi(ctypes.byref(grid.c()), _ptr(m), n_omega, warr, _ptr(dd), len(src), psrc, len(rec), prec_i,
+                          prec_xz, float(alpha), float(mu), _PREC[precision], float(tol), ctypes.byref(opts),
+                          _stream(stream), hist, ctypes.byref(info)))
+    out = {k: getattr(info, k) for k, _ in _FwiInfo._fields_}
+    out["status"] = _FWI_STATUS.get(info.status, info.status)
+    out["history"] = [hist[i] for i in range(info.iterations + 1)]
+    return m, out
+
+
+def fwi_continuation(grid: Grid, m0, groups, omegas, d_obs, sources, receivers, **kw):
+    """FWI over frequency groups in turn, each started from the previous
+    result (the lower level of the bilevel frequency continuation, App.
+    "Bilevel Frequency Continuation").  groups: lists of frequency indices
+    into omegas / d_obs.  Returns (m, [info per group])."""
+    torch = _torch()
+    dd = _dev_c128(d_obs)
+    m = _dev_f64(m0, grid.N)
+    infos = []
+    for grp in groups:
+        idx = [int(i) for i in grp]
+        m, info = fwi(grid, m, [omegas[i] for i in idx], dd[torch.as_tensor(idx, device=dd.device)].contiguous(),
+                      sources, receivers, **kw)
+        infos.append(info)
+    return m, infos
 
 
 class Hessian:

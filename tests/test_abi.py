@@ -85,3 +85,26 @@ def test_hessian_entry_points_check_arguments_without_gpu():
                               None, None, ctypes.byref(info), ctypes.byref(out)) == helm.EINVAL
     assert not out.value
     helm.lib().helm_hess_destroy(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_fwi_checks_arguments_without_gpu():
+    from paper_2301_10762_amd import helm
+    L = helm.lib()
+    fake = ctypes.c_void_p(16)
+    g = helm._Grid(9, 9, 0.1, 0.1)
+    w = (ctypes.c_double * 1)(1.0)
+    src = (ctypes.c_int32 * 1)(40)
+    rec = (ctypes.c_int32 * 1)(0)
+    xz = (ctypes.c_double * 2)(0.15, 0.05)
+    info = helm._FwiInfo()
+    good = helm._LbfgsOpts(5, 10, 20, 1e-6, 1e-4, 0.9, 0.01)
+    bad = helm._LbfgsOpts(5, 10, 20, 1e-6, 0.5, 0.4, 0.01)
+    # both or neither receiver form
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, rec, xz, 0.0, 0.0, 0, 0.0, ctypes.byref(good),
+                      None, None, ctypes.byref(info)) == helm.EINVAL
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, None, None, 0.0, 0.0, 0, 0.0, ctypes.byref(good),
+                      None, None, ctypes.byref(info)) == helm.EINVAL
+    # c1 >= c2
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, rec, None, 0.0, 0.0, 0, 0.0, ctypes.byref(bad),
+                      None, None, ctypes.byref(info)) == helm.EINVAL

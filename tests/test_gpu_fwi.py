@@ -1,0 +1,116 @@
+"""GPU parity of the lower-level FWI (L-BFGS with a strong-Wolfe line search,
+helm_fwi) against the oracle's own L-BFGS run on the same data.
+
+Both sides take the same decisions (accepted steps, evaluations, status) on
+values that agree to ~1e-12, so the phi histories agree to 1e-9 (FP64
+factors; 1e-8 for complex64 + refinement, whose evaluations carry the
+refinement tolerance) and the final models to 1e-8 (1e-7).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_10762_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def helm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_10762_amd import helm as h
+    h.lib()
+    return h
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _case():
+    w = I.small_layered(21, 4, 4, 10, ppws=(8.0, 12.0))
+    g = oracle.Grid.of(w)
+    d = oracle.synth_data(g, w.m_true, w.omegas, w.sources, w.receivers)
+    return w, g, d
+
+
+def _compare(info, oinfo, m, mo, hist_tol, m_tol):
+    assert info["iterations"] == oinfo["iterations"]
+    assert info["evals"] == oinfo["evals"]
+    assert info["status"] == oinfo["status"]
+    h, ho = np.array(info["history"]), np.array(oinfo["history"])
+    assert np.max(np.abs(h - ho) / np.abs(ho)) <= hist_tol
+    assert rel(m.cpu().numpy(), mo) <= m_tol
+
+
+@pytest.mark.parametrize("precision,hist_tol,m_tol", [("fp64", 1e-9, 1e-8), ("fp32_ir", 1e-8, 1e-7)])
+def test_fwi_matches_oracle(helm, precision, hist_tol, m_tol):
+    print(f"fwi 21x21 {precision}", flush=True)
+    w, g, d = _case()
+    kw = dict(memory=4, max_iters=8, gtol=1e-8)
+    mo, oinfo = oracle.fwi(g, w.m, w.omegas, d, w.sources, w.receivers, 1e-3, 1e-4, **kw)
+    m, info = helm.fwi(helm.Grid.of(w), w.m, w.omegas, d, w.sources, w.receivers, 1e-3, 1e-4,
+                       precision=precision, tol=1e-11 if precision == "fp64" else 1e-10, **kw)
+    _compare(info, oinfo, m, mo, hist_tol, m_tol)
+    assert info["phi"] < 0.5 * info["phi0"]
+
+
+def test_fwi_nonpositive_trials(helm):
+    """A first trial step large enough to make m negative: both sides treat
+    it as phi = +inf and bisect the same way."""
+    print("fwi nonpositive trials", flush=True)
+    w, g, d = _case()
+    kw = dict(memory=3, max_iters=3, gtol=1e-8, first_change=30.0)
+    undefined = [0]
+
+    def fg(m):
+        try:
+            return oracle.misfit_grad(g, m, w.omegas, d, w.sources, w.receivers, 1e-3, 1e-4)
+        except ValueError:
+            undefined[0] += 1
+            raise
+    mo, oinfo = oracle.lbfgs(fg, w.m, **kw)
+    m, info = helm.fwi(helm.Grid.of(w), w.m, w.omegas, d, w.sources, w.receivers, 1e-3, 1e-4, tol=1e-11, **kw)
+    assert undefined[0] >= 2                              # trial models with m_k <= 0 were met
+    _compare(info, oinfo, m, mo, 1e-9, 1e-8)
+
+
+def test_fwi_sensors_at_points_reaches_newton_minimiser(helm):
+    print("fwi sensors at points", flush=True)
+    from tests.test_oracle_upper import _Bilevel
+    b = _Bilevel()
+    m_newton, d, S = b.fwi(b.P, b.alpha, b.m_train)
+    start = b.m_train + 0.05 * (b.w.m - b.m_train)
+    kw = dict(memory=8, max_iters=400, gtol=1e-7)
+    mo, oinfo = oracle.fwi(b.g, start, b.w.omegas, d, b.src, S, b.alpha, b.mu, **kw)
+    m, info = helm.fwi(helm.Grid.of(b.w), start, b.w.omegas, d, b.src, b.P, b.alpha, b.mu, tol=1e-12, **kw)
+    assert info["status"] == "converged"
+    assert rel(m.cpu().numpy(), m_newton) <= 1e-6
+    assert rel(m.cpu().numpy(), mo) <= 1e-6
+
+
+def test_fwi_continuation_matches_oracle(helm):
+    print("fwi continuation", flush=True)
+    w, g, d = _case()
+    groups = [[0], [0, 1]]
+    kw = dict(memory=4, max_iters=4, gtol=1e-8)
+    mo, oinfos = oracle.fwi_continuation(g, w.m, groups, w.omegas, d, w.sources, w.receivers, 1e-3, 1e-4, **kw)
+    m, infos = helm.fwi_continuation(helm.Grid.of(w), w.m, groups, w.omegas, d, w.sources, w.receivers,
+                                     alpha=1e-3, mu=1e-4, tol=1e-11, **kw)
+    for info, oinfo in zip(infos, oinfos):
+        assert info["iterations"] == oinfo["iterations"] and info["evals"] == oinfo["evals"]
+    assert rel(m.cpu().numpy(), mo) <= 1e-8
+
+
+def test_fwi_rejects_bad_input(helm):
+    w, g, d = _case()
+    G = helm.Grid.of(w)
+    with pytest.raises(helm.HelmError):
+        helm.fwi(G, -w.m, w.omegas, d, w.sources, w.receivers)
+    with pytest.raises(helm.HelmError):
+        helm.fwi(G, w.m, w.omegas, d, w.sources, w.receivers, c1=0.5, c2=0.4)
