@@ -36,6 +36,8 @@ What each function follows:
                                                            -> upper_grad
   * lower-level FWI by L-BFGS with a strong-Wolfe line search (App.
     "Optimisation")                                        -> lbfgs, fwi
+  * point sources between nodes, f_j = phi_j(s) (App. "Numerical forward
+    model", computing the wavefield)                       -> point_sources
 
 Readings where the paper is silent (each pinned by a test in tests/):
   * corner mass weight hx*hz/4 (mean of the two triangulation directions);
@@ -44,6 +46,8 @@ Readings where the paper is silent (each pinned by a test in tests/):
   * on-node receivers: R samples u at the node, R^* scatters onto that node;
     off-node sensors: tensor-product cubic through the 4 x 4 nearest nodes,
     the stencil moved inward at the edges;
+  * the triangulation's diagonal is not stated: point-source loads average
+    the two cuts, as the corner mass weights do;
   * dpsi/dp carries the conjugates the derivation gives: -Re[(d tau) conj(du)
     + tau conj(d du)], where the printed a_l shows none;
   * D_n keeps the printed factor (n - 1).
@@ -207,6 +211,48 @@ def band_bytes(g: Grid) -> int:
     return int(_load().or_band_bytes(g.nx, g.nz))
 
 
+def point_sources(g: Grid, positions) -> np.ndarray:
+    """f_j = phi_j(s) for point sources s = (x, z) between nodes (App.
+    "Numerical forward model": f = delta_s in the load integral, f_b = 0),
+    phi_j the P1 hat functions of the rectangles cut into two triangles.
+    The diagonal is not stated, so the two cuts are averaged (the reading
+    used for the corner mass weights too).  At a node this is e_s."""
+    P = np.asarray(positions, dtype=np.float64).reshape(-1, 2)
+    E = np.zeros((len(P), g.N), dtype=np.complex128)
+    X, Z = (g.nx - 1) * g.hx, (g.nz - 1) * g.hz
+    for q, (x, z) in enumerate(P):
+        if not (0.0 <= x <= X and 0.0 <= z <= Z):
+            raise ValueError("source outside the domain")
+        i = min(int(np.floor(x / g.hx)), g.nx - 2)
+        j = min(int(np.floor(z / g.hz)), g.nz - 2)
+        xi, eta = x / g.hx - i, z / g.hz - j
+        k00, k10, k01, k11 = j * g.nx + i, j * g.nx + i + 1, (j + 1) * g.nx + i, (j + 1) * g.nx + i + 1
+        # cut along (i, j)-(i+1, j+1)
+        if xi >= eta:
+            a = {k00: 1 - xi, k10: xi - eta, k11: eta}
+        else:
+            a = {k00: 1 - eta, k01: eta - xi, k11: xi}
+        # cut along (i+1, j)-(i, j+1)
+        if xi + eta <= 1:
+            b = {k00: 1 - xi - eta, k10: xi, k01: eta}
+        else:
+            b = {k11: xi + eta - 1, k10: 1 - eta, k01: 1 - xi}
+        for k, v in a.items():
+            E[q, k] += 0.5 * v
+        for k, v in b.items():
+            E[q, k] += 0.5 * v
+    return E
+
+
+def _sources(g: Grid, sources) -> np.ndarray:
+    """Right-hand sides for sources given as node indices (e_s) or as an
+    [S][2] float array of points (point_sources)."""
+    a = np.asarray(sources)
+    if a.dtype.kind == "f":
+        return point_sources(g, a)
+    return unit_sources(g, a)
+
+
 def unit_sources(g: Grid, nodes) -> np.ndarray:
     """e_s for each grid-point source s (App. A.1, "Computing the wavefield")."""
     E = np.zeros((len(nodes), g.N), dtype=np.complex128)
@@ -308,7 +354,7 @@ def synth_data(g: Grid, m_true, omegas, sources, receivers) -> np.ndarray:
     out = []
     for w in omegas:
         F = Factor(g, m_true, w)
-        out.append(restrict(F.solve(unit_sources(g, sources)), receivers))
+        out.append(restrict(F.solve(_sources(g, sources)), receivers))
         F.close()
     return np.ascontiguousarray(np.array(out))
 
@@ -346,7 +392,7 @@ def misfit_grad(g: Grid, m, omegas, d_obs, sources, receivers, alpha: float = 0.
     fields = []
     for iw, w in enumerate(omegas):
         F = Factor(g, m, w)
-        U = F.solve(unit_sources(g, sources))
+        U = F.solve(_sources(g, sources))
         eps = np.asarray(d_obs[iw]) - restrict(U, receivers)
         phi += 0.5 * float(np.sum(np.abs(eps) ** 2))
         Lam = F.adjoint_solve(restrict_adjoint(eps, receivers, g.N))
@@ -376,7 +422,7 @@ def gn_hvp(g: Grid, m, omegas, sources, receivers, directions, alpha: float = 0.
     out = np.zeros((len(dirs), g.N))
     for w in omegas:
         F = Factor(g, m, w)
-        U = F.solve(unit_sources(g, sources))
+        U = F.solve(_sources(g, sources))
         gt = grad_weight(g, m, w)[None, :] * U
         for a, mt in enumerate(dirs):
             V = F.solve(gt * mt[None, :])
@@ -409,7 +455,7 @@ def hvp(g: Grid, m, omegas, d_obs, sources, receivers, directions, alpha: float 
     _, b = weights(g)
     for iw, w in enumerate(omegas):
         F = Factor(g, m, w)
-        U = F.solve(unit_sources(g, sources))
+        U = F.solve(_sources(g, sources))
         eps = np.asarray(d_obs[iw]) - restrict(U, receivers)
         Lam = F.adjoint_solve(restrict_adjoint(eps, receivers, g.N))
         gk = grad_weight(g, m, w)[None, :]
@@ -497,11 +543,11 @@ def upper_grad(g: Grid, m_fwi, m_train, omegas, sources, sensors: "Sensors", rho
     dp = np.zeros((len(sensors), 2))
     for w in omegas:
         F = Factor(g, m_fwi, w)
-        U = F.solve(unit_sources(g, sources))
+        U = F.solve(_sources(g, sources))
         Tau = F.solve(grad_weight(g, m_fwi, w)[None, :] * rho[None, :] * U)
         F.close()
         Ft = Factor(g, m_train, w)
-        dU = Ft.solve(unit_sources(g, sources)) - U
+        dU = Ft.solve(_sources(g, sources)) - U
         Ft.close()
         du = (R0 @ dU.T).T
         for col, Rl in ((0, Rx), (1, Rz)):

@@ -193,3 +193,20 @@ def test_lbfgs_mutation_caught(name):
     x, info = opt(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.ones(n), memory=n, max_iters=100, gtol=1e-8,
                   c2=1e-2)
     assert info["status"] != "converged" or info["iterations"] > n + 1
+
+
+# ------------------------------------------------------------ point sources --
+
+def test_point_source_swapped_local_coordinates_caught():
+    """Swapping x and z inside one cut breaks second-order convergence of the
+    sensor data."""
+    import inspect
+    import textwrap
+    from tests.test_oracle_offgrid import data_convergence_ratios
+    src = textwrap.dedent(inspect.getsource(oracle.point_sources))
+    old = "a = {k00: 1 - xi, k10: xi - eta, k11: eta}"
+    assert src.count(old) == 1
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, "a = {k00: 1 - eta, k10: eta - xi, k11: xi}"), "<mutant>", "exec"), ns)
+    r1, r2 = data_convergence_ratios(ns["point_sources"])
+    assert not (3.5 <= r1 <= 6.0 and 3.5 <= r2 <= 6.0), (r1, r2)
