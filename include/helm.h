@@ -175,7 +175,9 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
 
 /* helm_hess_create_at: helm_hess_create with the Nr sensors at points of
  * the domain, rec_xz_host = [Nr][2] doubles (x, z) with 0 <= x <= (nx-1) hx,
- * 0 <= z <= (nz-1) hz, and R(P) the sliding cubic of App. "Numerical
+ * 0 <= z <= (nz-1) hz, and the sources either at nodes (src_host) or at
+ * points (src_xz_host, [S][2], loads as helm_point_sources; exactly one of
+ * the two non-NULL); R(P) is the sliding cubic of App. "Numerical
  * restriction operator": (R u)_j is the tensor-product Lagrange cubic through
  * the 4 x 4 nodes nearest to p_j (for p in [x_i, x_{i+1}] the nodes x_{i-1}
  * .. x_{i+2}, moved inward at the edges), so at a node it is the nodal value.
@@ -183,7 +185,8 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
  * products, PCG) is as for helm_hess_create.                               */
 int helm_hess_create_at(const helm_grid* grid, const double* m_dev, int32_t n_omega,
                         const double* omegas_host, const double* dobs_dev, int32_t S,
-                        const int32_t* src_host, int32_t Nr, const double* rec_xz_host,
+                        const int32_t* src_host, const double* src_xz_host, int32_t Nr,
+                        const double* rec_xz_host,
                         double alpha, double mu, int precision, double tol, void* stream,
                         double* phi_host, double* grad_dev, helm_info* info, helm_hess_t* out);
 
@@ -205,6 +208,16 @@ int helm_hess_create_at(const helm_grid* grid, const double* m_dev, int32_t n_om
  * `stream`.                                                               */
 int helm_upper_grad(helm_hess_t h, const double* rho_dev, const double* ddata_dev, void* stream,
                     double* dpsi_dp_host, double* dpsi_dalpha_host, helm_info* info);
+
+/* helm_point_sources: right-hand sides for S point sources between nodes
+ * (App. "Numerical forward model": f = delta_s in the load integral, so
+ * f_j = phi_j(s) for the P1 hat functions).  The rectangles' diagonal is
+ * not stated, so the loads of the two ways of cutting them are averaged
+ * (four nonzeros at the corners of the cell holding s; e_s at a node).
+ * src_xz_host: [S][2] points inside the domain.  B_dev: complex128, column s
+ * at s*ld, overwritten (zero outside the loads).  Synchronises `stream`.   */
+int helm_point_sources(const helm_grid* grid, int32_t S, const double* src_xz_host, double* B_dev,
+                       int64_t ld, void* stream);
 
 /* helm_restrict: out = R(P) U (deriv 0) or its derivative with respect to
  * the sensors' x (1) or z (2) coordinate, for S complex128 fields U_dev
@@ -277,14 +290,15 @@ typedef struct {
  * the minimum is bracketed, then zoom by the cubic interpolation of f, f'
  * at the bracket's ends (bisection when it falls within a tenth of them).
  * A trial model with some m_k <= 0 counts as phi = +inf.  Each evaluation
- * is phi and grad phi as helm_misfit_grad computes them, with receiver
- * nodes rec_host or sensor points rec_xz_host (exactly one non-NULL; see
+ * is phi and grad phi as helm_misfit_grad computes them, with source
+ * nodes src_host or points src_xz_host and receiver nodes rec_host or
+ * sensor points rec_xz_host (exactly one of each pair non-NULL; see
  * helm_hess_create_at).  m_dev: the start model on entry, the result on
  * return.  phi_hist_host (optional): max_iters + 1 doubles, phi at every
  * iterate.  The statuses are results, not errors.  Synchronises `stream`. */
 int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double* omegas_host,
-             const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr,
-             const int32_t* rec_host, const double* rec_xz_host, double alpha, double mu,
+             const double* dobs_dev, int32_t S, const int32_t* src_host, const double* src_xz_host,
+             int32_t Nr, const int32_t* rec_host, const double* rec_xz_host, double alpha, double mu,
              int precision, double tol, const helm_lbfgs_opts* opts, void* stream,
              double* phi_hist_host, helm_fwi_info* info);
 

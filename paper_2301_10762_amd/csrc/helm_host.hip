@@ -981,13 +981,22 @@ int rtab_points(const helm_grid& g, int Nr, const double* xz, HostRTab* t) {
     return HELM_OK;
 }
 
+int check_points(const helm_grid& g, int n, const double* xz, const char* what) {
+    if (n > 0 && !xz) return fail(HELM_EINVAL, std::string(what) + " position list is NULL");
+    const double X = g.hx * (g.nx - 1), Z = g.hz * (g.nz - 1);
+    for (int q = 0; q < n; ++q)
+        if (!(xz[2 * q] >= 0.0 && xz[2 * q] <= X && xz[2 * q + 1] >= 0.0 && xz[2 * q + 1] <= Z))
+            return fail(HELM_EINVAL, std::string(what) + " " + std::to_string(q) + " lies outside the domain");
+    return HELM_OK;
+}
+
 // Factor A(m, w) for every frequency and solve for u (and, with data, for
 // lambda = A^{-*} R^*(d - R u), phi and grad phi when asked for).  The
 // fields stay with the returned context; the stream is synchronised.
 int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const double* omegas_host,
-               const double* dobs_dev, int S, const int32_t* src_host, int Nr, const int32_t* rec_host,
-               const double* rec_xz, double alpha, double mu, int precision, double tol, hipStream_t st,
-               double* phi_host, double* grad_dev, helm_info* info, helm_hess_s** out) {
+               const double* dobs_dev, int S, const int32_t* src_host, const double* src_xz, int Nr,
+               const int32_t* rec_host, const double* rec_xz, double alpha, double mu, int precision, double tol,
+               hipStream_t st, double* phi_host, double* grad_dev, helm_info* info, helm_hess_s** out) {
     *out = nullptr;
     int rc = check_grid(grid);
     if (rc) return rc;
@@ -995,19 +1004,20 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
         return fail(HELM_EINVAL, "bad frequency, source or receiver counts, or NULL pointers");
     if (precision != HELM_FP64 && precision != HELM_FP32_IR) return fail(HELM_EINVAL, "unknown precision");
     const int64_t N = N_of(*grid);
-    if ((rc = check_nodes(src_host, S, N, "source"))) return rc;
+    if ((src_host != nullptr) == (src_xz != nullptr)) return fail(HELM_EINVAL, "give either source nodes or points");
+    if ((rc = src_xz ? check_points(*grid, S, src_xz, "source") : check_nodes(src_host, S, N, "source"))) return rc;
     HostRTab rt;
     if ((rc = rec_xz ? rtab_points(*grid, Nr, rec_xz, &rt) : rtab_nodes(*grid, Nr, rec_host, &rt))) return rc;
     const bool full = dobs_dev != nullptr;
     if (full)
         for (int s = 0; s < S; ++s)
             for (int p = 0; p < Nr; ++p) {
-                const bool same = rec_xz ? (std::fabs(rec_xz[2 * p] - (src_host[s] % grid->nx) * grid->hx) <=
-                                                1e-12 * grid->hx &&
-                                            std::fabs(rec_xz[2 * p + 1] - (src_host[s] / grid->nx) * grid->hz) <=
-                                                1e-12 * grid->hz)
-                                         : src_host[s] == rec_host[p];
-                if (same) return fail(HELM_EINVAL, "a source coincides with a receiver");
+                const double sx = src_xz ? src_xz[2 * s] : (src_host[s] % grid->nx) * grid->hx;
+                const double sz = src_xz ? src_xz[2 * s + 1] : (src_host[s] / grid->nx) * grid->hz;
+                const double rx = rec_xz ? rec_xz[2 * p] : (rec_host[p] % grid->nx) * grid->hx;
+                const double rz = rec_xz ? rec_xz[2 * p + 1] : (rec_host[p] / grid->nx) * grid->hz;
+                if (std::fabs(sx - rx) <= 1e-12 * grid->hx && std::fabs(sz - rz) <= 1e-12 * grid->hz)
+                    return fail(HELM_EINVAL, "a source coincides with a receiver");
             }
     helm_hess_s* h = new helm_hess_s();
     *out = h;
@@ -1027,9 +1037,15 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     if ((rc = factor_many(n_omega, grids.data(), ms.data(), omegas_host, precision, st, h->F.data()))) return rc;
     h->m = h->F[0]->m;
     Scratch sc(st);
-    int* dsrc;
-    if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
-    if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
+    int* dsrc = nullptr;
+    double* dsxz = nullptr;
+    if (src_xz) {
+        if ((rc = sc.get(&dsxz, sizeof(double) * 2 * S))) return rc;
+        if ((rc = upload_sync(dsxz, src_xz, sizeof(double) * 2 * S, st))) return rc;
+    } else {
+        if ((rc = sc.get(&dsrc, sizeof(int) * S))) return rc;
+        if ((rc = upload_sync(dsrc, src_host, sizeof(int) * S, st))) return rc;
+    }
     h->ntap = rt.ntap;
     h->at_points = rt.points;
     h->nt = (int)rt.tnode.size();
@@ -1053,9 +1069,15 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     h->U.assign(n_omega, nullptr);
     for (int w = 0; w < n_omega; ++w)
         if ((rc = hess_own(h, &h->U[w], fb))) return rc;
-    launch_unit_sources(E, N, N, dsrc, S, st);
-    g_launches += 1;
-    // forward wavefields u = A^{-1} e_s, all frequencies in one batch
+    if (src_xz) {
+        launch_zero(E, fb, st);
+        launch_point_sources(E, N, dsxz, S, grid->nx, grid->nz, grid->hx, grid->hz, st);
+        g_launches += 2;
+    } else {
+        launch_unit_sources(E, N, N, dsrc, S, st);
+        g_launches += 1;
+    }
+    // forward wavefields u = A^{-1} f_s, all frequencies in one batch
     std::vector<SolveJob> jobs;
     std::vector<helm_info> infos(n_omega);
     for (int w = 0; w < n_omega; ++w) jobs.push_back({h->F[w], E, h->U[w], S, N, &infos[w]});
@@ -1365,6 +1387,7 @@ struct Fwi {
     const double* dobs;
     int S;
     const int32_t* src;
+    const double* src_xz;
     int Nr;
     const int32_t* rec;
     const double* rec_xz;
@@ -1407,8 +1430,8 @@ struct Fwi {
         if (rc) return rc;
         helm_hess_s* h = nullptr;
         helm_info inf{};
-        rc = hess_build(grid, x, n_omega, omegas, dobs, S, src, Nr, rec, rec_xz, alpha, mu, precision, tol, st, f, g,
-                        &inf, &h);
+        rc = hess_build(grid, x, n_omega, omegas, dobs, S, src, src_xz, Nr, rec, rec_xz, alpha, mu, precision, tol,
+                        st, f, g, &inf, &h);
         hess_free(h);
         if (rc) return rc;
         merge_info(&tot, inf);
@@ -1736,8 +1759,8 @@ int helm_misfit_grad(const helm_grid* grid, const double* m_dev, int32_t n_omega
                      double* grad_dev, helm_info* info) {
     if (!dobs_dev || !phi_host || !grad_dev) return fail(HELM_EINVAL, "bad misfit_grad arguments");
     helm_hess_s* h = nullptr;
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, nullptr, alpha, mu,
-                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, nullptr, Nr, rec_host, nullptr,
+                        alpha, mu, precision, tol, S_(stream), phi_host, grad_dev, info, &h);
     hess_free(h);
     return rc;
 }
@@ -1748,8 +1771,8 @@ int helm_gn_hvp(const helm_grid* grid, const double* m_dev, int32_t n_omega, con
     if (n_dir <= 0 || !mt_dev || !hv_dev) return fail(HELM_EINVAL, "bad gn_hvp arguments");
     helm_hess_s* h = nullptr;
     helm_info i0{};
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, nullptr, S, src_host, Nr, rec_host, nullptr, alpha, mu,
-                        precision, tol, S_(stream), nullptr, nullptr, &i0, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, nullptr, S, src_host, nullptr, Nr, rec_host, nullptr,
+                        alpha, mu, precision, tol, S_(stream), nullptr, nullptr, &i0, &h);
     if (rc == HELM_OK) rc = hess_apply(h, n_dir, mt_dev, hv_dev, S_(stream), info);
     if (rc == HELM_OK && info) {
         info->solves += i0.solves;
@@ -1768,8 +1791,8 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
     *out = nullptr;
     if (!dobs_dev && (phi_host || grad_dev)) return fail(HELM_EINVAL, "phi and grad need data");
     helm_hess_s* h = nullptr;
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, nullptr, alpha, mu,
-                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, nullptr, Nr, rec_host, nullptr,
+                        alpha, mu, precision, tol, S_(stream), phi_host, grad_dev, info, &h);
     if (rc) {
         hess_free(h);
         return rc;
@@ -1779,16 +1802,16 @@ int helm_hess_create(const helm_grid* grid, const double* m_dev, int32_t n_omega
 }
 
 int helm_hess_create_at(const helm_grid* grid, const double* m_dev, int32_t n_omega, const double* omegas_host,
-                        const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr,
-                        const double* rec_xz_host, double alpha, double mu, int precision, double tol, void* stream,
-                        double* phi_host, double* grad_dev, helm_info* info, helm_hess_t* out) {
+                        const double* dobs_dev, int32_t S, const int32_t* src_host, const double* src_xz_host,
+                        int32_t Nr, const double* rec_xz_host, double alpha, double mu, int precision, double tol,
+                        void* stream, double* phi_host, double* grad_dev, helm_info* info, helm_hess_t* out) {
     if (!out) return fail(HELM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!rec_xz_host) return fail(HELM_EINVAL, "sensor position list is NULL");
     if (!dobs_dev && (phi_host || grad_dev)) return fail(HELM_EINVAL, "phi and grad need data");
     helm_hess_s* h = nullptr;
-    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, Nr, nullptr, rec_xz_host, alpha, mu,
-                        precision, tol, S_(stream), phi_host, grad_dev, info, &h);
+    int rc = hess_build(grid, m_dev, n_omega, omegas_host, dobs_dev, S, src_host, src_xz_host, Nr, nullptr,
+                        rec_xz_host, alpha, mu, precision, tol, S_(stream), phi_host, grad_dev, info, &h);
     if (rc) {
         hess_free(h);
         return rc;
@@ -1801,6 +1824,25 @@ int helm_upper_grad(helm_hess_t h, const double* rho_dev, const double* ddata_de
                     double* dpsi_dp_host, double* dpsi_dalpha_host, helm_info* info) {
     if (!h) return fail(HELM_EINVAL, "Hessian handle is NULL");
     return hess_upper(h, rho_dev, ddata_dev, S_(stream), dpsi_dp_host, dpsi_dalpha_host, info);
+}
+
+int helm_point_sources(const helm_grid* grid, int32_t S, const double* src_xz_host, double* B_dev, int64_t ld,
+                       void* stream) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (S <= 0 || !B_dev || ld < N_of(*grid)) return fail(HELM_EINVAL, "bad point_sources arguments");
+    if ((rc = check_points(*grid, S, src_xz_host, "source"))) return rc;
+    hipStream_t st = S_(stream);
+    Scratch sc(st);
+    double* dxz;
+    if ((rc = sc.get(&dxz, sizeof(double) * 2 * S))) return rc;
+    if ((rc = upload_sync(dxz, src_xz_host, sizeof(double) * 2 * S, st))) return rc;
+    launch_zero(B_dev, sizeof(double) * 2 * ((size_t)(S - 1) * ld + N_of(*grid)), st);
+    launch_point_sources(B_dev, ld, dxz, S, grid->nx, grid->nz, grid->hx, grid->hz, st);
+    g_launches += 2;
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
+    return HELM_OK;
 }
 
 int helm_restrict(const helm_grid* grid, int32_t Nr, const double* rec_xz_host, int deriv, const double* U_dev,
@@ -1827,8 +1869,8 @@ int helm_restrict(const helm_grid* grid, int32_t Nr, const double* rec_xz_host, 
 }
 
 int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double* omegas_host,
-             const double* dobs_dev, int32_t S, const int32_t* src_host, int32_t Nr, const int32_t* rec_host,
-             const double* rec_xz_host, double alpha, double mu, int precision, double tol,
+             const double* dobs_dev, int32_t S, const int32_t* src_host, const double* src_xz_host, int32_t Nr,
+             const int32_t* rec_host, const double* rec_xz_host, double alpha, double mu, int precision, double tol,
              const helm_lbfgs_opts* opts, void* stream, double* phi_hist_host, helm_fwi_info* info) {
     int rc = check_grid(grid);
     if (rc) return rc;
@@ -1836,12 +1878,14 @@ int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double
         return fail(HELM_EINVAL, "bad fwi arguments");
     if ((rec_host != nullptr) == (rec_xz_host != nullptr))
         return fail(HELM_EINVAL, "give either receiver nodes or sensor points");
+    if ((src_host != nullptr) == (src_xz_host != nullptr))
+        return fail(HELM_EINVAL, "give either source nodes or points");
     const helm_lbfgs_opts& o = *opts;
     if (o.memory < 1 || o.max_iters < 0 || o.max_evals < 1 || !(o.gtol >= 0.0) || !(o.c1 > 0.0) ||
         !(o.c1 < o.c2) || !(o.c2 < 1.0) || !(o.first_change > 0.0))
         return fail(HELM_EINVAL, "bad L-BFGS options (need memory >= 1, 0 < c1 < c2 < 1, first_change > 0)");
-    Fwi P{grid, n_omega, omegas_host, dobs_dev, S, src_host, Nr, rec_host, rec_xz_host, alpha, mu, precision, tol,
-          S_(stream), N_of(*grid), nullptr, nullptr};
+    Fwi P{grid, n_omega, omegas_host, dobs_dev, S, src_host, src_xz_host, Nr, rec_host, rec_xz_host, alpha, mu,
+          precision, tol, S_(stream), N_of(*grid), nullptr, nullptr};
     P.tot.bad_block = P.tot.bad_row = -1;
     *info = helm_fwi_info{};
     rc = fwi_run(P, m_dev, o, phi_hist_host, info);

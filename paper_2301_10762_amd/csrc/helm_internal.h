@@ -152,6 +152,8 @@ void launch_hv(const Coef& cf, const double* U, int64_t ldu, int S, const double
 constexpr int RTAP = 16;   // taps per sensor of the restriction tables (4 x 4 bicubic)
 void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* node, const double* w, int ntap,
                    int Nr, int S, double* eps, double* phi_part, hipStream_t st);
+void launch_point_sources(double* E, int64_t ld, const double* xz, int S, int nx, int nz, double hx, double hz,
+                          hipStream_t st);   // columns zeroed beforehand
 void launch_restrict(const double* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr, int cols,
                      double* out, int64_t ldo, hipStream_t st);
 void launch_restrict_adj(const double* Z, int64_t ldz, const int* tnode, const int* tptr, const int* tq,

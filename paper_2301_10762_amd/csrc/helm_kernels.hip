@@ -211,6 +211,36 @@ __global__ void k_hv(Coef cf, const double2* U, int64_t ldu, int S, const double
     hv[(size_t)a * N + k] += wk.x * sr - wk.y * si;
 }
 
+// Point sources between nodes: column q of E (zeroed beforehand) receives
+// phi_j(s_q), the P1 hat functions of the rectangles cut into triangles,
+// averaged over the two ways of cutting (at a node: e_s).  One thread per
+// source, so no two threads write one column.
+__global__ void k_point_sources(double2* E, int64_t ld, const double* xz, int S, int nx, int nz, double hx,
+                                double hz) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= S) return;
+    const double u = xz[2 * q] / hx, v = xz[2 * q + 1] / hz;
+    const int i = min((int)floor(u), nx - 2), j = min((int)floor(v), nz - 2);
+    const double xi = u - i, eta = v - j;
+    double w00 = 0.0, w10 = 0.0, w01 = 0.0, w11 = 0.0;
+    if (xi >= eta) {   // cut (i, j)-(i+1, j+1), lower triangle
+        w00 += 1.0 - xi, w10 += xi - eta, w11 += eta;
+    } else {
+        w00 += 1.0 - eta, w01 += eta - xi, w11 += xi;
+    }
+    if (xi + eta <= 1.0) {   // cut (i+1, j)-(i, j+1)
+        w00 += 1.0 - xi - eta, w10 += xi, w01 += eta;
+    } else {
+        w11 += xi + eta - 1.0, w10 += 1.0 - eta, w01 += 1.0 - xi;
+    }
+    double2* col = E + (size_t)q * ld;
+    const int64_t k00 = (int64_t)j * nx + i;
+    col[k00] = make_double2(0.5 * w00, 0.0);
+    col[k00 + 1] = make_double2(0.5 * w10, 0.0);
+    col[k00 + nx] = make_double2(0.5 * w01, 0.0);
+    col[k00 + nx + 1] = make_double2(0.5 * w11, 0.0);
+}
+
 // ---- restriction R(P): per sensor q up to RTAP taps (node[q*RTAP + a],
 // weight w[q*RTAP + a]); ntap = 1 for sensors on nodes, 16 for the sliding
 // bicubic of sensors between nodes.  w may be the value weights or those of
@@ -489,6 +519,10 @@ void launch_misfit(const double* U, int64_t ldu, const double* dobs, const int* 
                    int Nr, int S, double* eps, double* phi_part, hipStream_t st) {
     hipLaunchKernelGGL(k_misfit, dim3(S), dim3(64), 0, st, (const double2*)U, ldu, (const double2*)dobs, node, w,
                        ntap, Nr, (double2*)eps, phi_part);
+}
+void launch_point_sources(double* E, int64_t ld, const double* xz, int S, int nx, int nz, double hx, double hz,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_point_sources, grid1(S, 64), dim3(64), 0, st, (double2*)E, ld, xz, S, nx, nz, hx, hz);
 }
 void launch_restrict(const double* U, int64_t ldu, const int* node, const double* w, int ntap, int Nr, int cols,
                      double* out, int64_t ldo, hipStream_t st) {

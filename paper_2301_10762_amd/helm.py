@@ -109,14 +109,15 @@ def lib():
     L.helm_hess_create.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
                                    ctypes.POINTER(i32), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp,
                                    I, ctypes.POINTER(_vp)]
-    L.helm_hess_create_at.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
-                                      ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64, _vp, ctypes.POINTER(f64), _vp,
-                                      I, ctypes.POINTER(_vp)]
+    L.helm_hess_create_at.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32),
+                                      ctypes.POINTER(f64), i32, ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64, _vp,
+                                      ctypes.POINTER(f64), _vp, I, ctypes.POINTER(_vp)]
+    L.helm_point_sources.argtypes = [G, i32, ctypes.POINTER(f64), _vp, i64, _vp]
     L.helm_upper_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(f64), ctypes.POINTER(f64), I]
     L.helm_restrict.argtypes = [G, i32, ctypes.POINTER(f64), ctypes.c_int, _vp, i32, i64, _vp, _vp]
-    L.helm_fwi.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
-                           ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64, ctypes.POINTER(_LbfgsOpts), _vp,
-                           ctypes.POINTER(f64), ctypes.POINTER(_FwiInfo)]
+    L.helm_fwi.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), ctypes.POINTER(f64), i32,
+                           ctypes.POINTER(i32), ctypes.POINTER(f64), f64, f64, ctypes.c_int, f64,
+                           ctypes.POINTER(_LbfgsOpts), _vp, ctypes.POINTER(f64), ctypes.POINTER(_FwiInfo)]
     L.helm_hess_apply.argtypes = [_vp, i32, _vp, _vp, _vp, I]
     L.helm_hess_pcg.argtypes = [_vp, _vp, _vp, f64, f64, f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), I]
     L.helm_hess_destroy.argtypes = [_vp]
@@ -141,7 +142,8 @@ def lib():
     for name in ("helm_factor", "helm_factor_batch", "helm_factor_bytes", "helm_solve", "helm_adjoint_solve",
                  "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
                  "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve",
-                 "helm_hess_create_at", "helm_upper_grad", "helm_restrict", "helm_fwi"):
+                 "helm_hess_create_at", "helm_upper_grad", "helm_restrict", "helm_fwi",
+                 "helm_point_sources"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -183,6 +185,17 @@ def _dev_c128(x):
     if t.dtype != torch.complex128:
         t = t.to(torch.complex128)
     return t.contiguous()
+
+
+def _src_arg(sources):
+    """(count, node pointer or None, point pointer or None, keep-alive) for
+    sources given as node indices or as an [S][2] float array of points."""
+    a = np.asarray(sources)
+    if a.dtype.kind == "f":
+        pts = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 2)
+        return len(pts), None, pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), pts
+    arr, ptr = _i32(sources)
+    return len(arr), ptr, None, arr
 
 
 def _i32(seq):
@@ -386,7 +399,7 @@ def fwi(grid: Grid, m0, omegas, d_obs, sources, receivers, alpha: float = 0.0, m
     solves, history}."""
     m = _dev_f64(m0, grid.N).clone()
     n_omega = len(omegas)
-    src, psrc = _i32(sources)
+    n_src, psrc, psxz, _keep = _src_arg(sources)
     rarr = np.asarray(receivers)
     if rarr.dtype.kind == "f":
         rec = np.ascontiguousarray(rarr, dtype=np.float64).reshape(-1, 2)
@@ -395,15 +408,15 @@ def fwi(grid: Grid, m0, omegas, d_obs, sources, receivers, alpha: float = 0.0, m
         rec, prec_i = _i32(receivers)
         prec_xz = None
     dd = _dev_c128(d_obs)
-    if tuple(dd.shape) != (n_omega, len(src), len(rec)):
+    if tuple(dd.shape) != (n_omega, n_src, len(rec)):
         raise ValueError("d_obs must be [n_omega][S][Nr]")
     warr = (ctypes.c_double * n_omega)(*[float(w) for w in omegas])
     opts = _LbfgsOpts(int(memory), int(max_iters), int(max_evals), float(gtol), float(c1), float(c2),
                       float(first_change))
     hist = (ctypes.c_double * (int(max_iters) + 1))()
     info = _FwiInfo()
-    _check(lib().helm_fwi(ctypes.byref(grid.c()), _ptr(m), n_omega, warr, _ptr(dd), len(src), psrc, len(rec), prec_i,
-                          prec_xz, float(alpha), float(mu), _PREC[precision], float(tol), ctypes.byref(opts),
+    _check(lib().helm_fwi(ctypes.byref(grid.c()), _ptr(m), n_omega, warr, _ptr(dd), n_src, psrc, psxz, len(rec),
+                          prec_i, prec_xz, float(alpha), float(mu), _PREC[precision], float(tol), ctypes.byref(opts),
                           _stream(stream), hist, ctypes.byref(info)))
     out = {k: getattr(info, k) for k, _ in _FwiInfo._fields_}
     out["status"] = _FWI_STATUS.get(info.status, info.status)
@@ -443,19 +456,24 @@ class Hessian:
         self.h = None
         md = _dev_f64(m, grid.N)
         n_omega = len(omegas)
-        src, psrc = _i32(sources)
+        n_src, psrc, psxz, _keep = _src_arg(sources)
         rarr = np.asarray(receivers)
-        self.at_points = rarr.dtype.kind == "f"
-        if self.at_points:
+        self.at_points = rarr.dtype.kind == "f" or psxz is not None
+        if rarr.dtype.kind == "f":
             rec = np.ascontiguousarray(rarr, dtype=np.float64).reshape(-1, 2)
+            prec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        elif self.at_points:
+            # point sources with node receivers: the receivers as points
+            nodes = np.asarray(receivers, dtype=np.int64)
+            rec = np.ascontiguousarray(np.column_stack([(nodes % grid.nx) * grid.hx, (nodes // grid.nx) * grid.hz]))
             prec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             rec, prec = _i32(receivers)
-        self.n_omega, self.S, self.Nr = n_omega, len(src), len(rec)
+        self.n_omega, self.S, self.Nr = n_omega, n_src, len(rec)
         dd = None
         if d_obs is not None:
             dd = _dev_c128(d_obs)
-            if tuple(dd.shape) != (n_omega, len(src), len(rec)):
+            if tuple(dd.shape) != (n_omega, n_src, len(rec)):
                 raise ValueError("d_obs must be [n_omega][S][Nr]")
         elif with_grad:
             raise ValueError("phi and grad need data")
@@ -464,9 +482,12 @@ class Hessian:
         self.grad = torch.empty(grid.N, dtype=torch.float64, device="cuda") if with_grad else None
         info = _Info()
         h = ctypes.c_void_p()
-        create = lib().helm_hess_create_at if self.at_points else lib().helm_hess_create
+        if self.at_points:
+            create = lambda *a: lib().helm_hess_create_at(*a[:7], psxz, *a[7:])     # noqa: E731
+        else:
+            create = lib().helm_hess_create
         _check(create(ctypes.byref(grid.c()), _ptr(md), n_omega, warr,
-                                      _ptr(dd) if dd is not None else None, len(src), psrc, len(rec), prec,
+                                      _ptr(dd) if dd is not None else None, n_src, psrc, len(rec), prec,
                                       float(alpha), float(mu), _PREC[precision], float(tol), _stream(stream),
                                       ctypes.byref(phi) if with_grad else None,
                                       _ptr(self.grad) if with_grad else None, ctypes.byref(info), ctypes.byref(h)))
@@ -529,6 +550,18 @@ class Hessian:
             self.close()
         except Exception:
             pass
+
+
+def point_sources(grid: Grid, positions, stream=None):
+    """Right-hand sides of point sources between nodes ([S][2] points):
+    helm_point_sources.  Returns complex [S][N]."""
+    torch = _torch()
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    B = torch.empty((len(pos), grid.N), dtype=torch.complex128, device="cuda")
+    _check(lib().helm_point_sources(ctypes.byref(grid.c()), len(pos),
+                                    pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(B), grid.N,
+                                    _stream(stream)))
+    return B
 
 
 def restrict(grid: Grid, positions, U, deriv: int = 0, stream=None):

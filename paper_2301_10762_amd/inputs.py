@@ -257,3 +257,21 @@ def point_sources(N: int, nodes, dtype=np.complex128) -> np.ndarray:
     for s, k in enumerate(nodes):
         B[s, int(k)] = 1.0
     return B
+
+
+def resample(m, src: tuple, dst: tuple) -> np.ndarray:
+    """Bilinear resampling of a nodal model from grid src = (nx, nz, hx, hz)
+    to grid dst over the same domain: the training model on a second grid,
+    for data computed away from the inversion grid."""
+    nx, nz, hx, hz = src
+    mx, mz, gx, gz = dst
+    M = np.asarray(m, dtype=np.float64).reshape(nz, nx)
+    x = np.minimum(np.arange(mx) * gx / hx, nx - 1)
+    z = np.minimum(np.arange(mz) * gz / hz, nz - 1)
+    i = np.minimum(np.floor(x).astype(int), nx - 2)
+    j = np.minimum(np.floor(z).astype(int), nz - 2)
+    a = (x - i)[None, :]
+    b = (z - j)[:, None]
+    out = ((1 - a) * (1 - b) * M[j[:, None], i[None, :]] + a * (1 - b) * M[j[:, None], i[None, :] + 1]
+           + (1 - a) * b * M[j[:, None] + 1, i[None, :]] + a * b * M[j[:, None] + 1, i[None, :] + 1])
+    return np.ascontiguousarray(out.reshape(-1))

@@ -101,10 +101,18 @@ def test_fwi_checks_arguments_without_gpu():
     good = helm._LbfgsOpts(5, 10, 20, 1e-6, 1e-4, 0.9, 0.01)
     bad = helm._LbfgsOpts(5, 10, 20, 1e-6, 0.5, 0.4, 0.01)
     # both or neither receiver form
-    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, rec, xz, 0.0, 0.0, 0, 0.0, ctypes.byref(good),
-                      None, None, ctypes.byref(info)) == helm.EINVAL
-    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, None, None, 0.0, 0.0, 0, 0.0, ctypes.byref(good),
-                      None, None, ctypes.byref(info)) == helm.EINVAL
+    sxz = (ctypes.c_double * 2)(0.35, 0.45)
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, None, 1, rec, xz, 0.0, 0.0, 0, 0.0,
+                      ctypes.byref(good), None, None, ctypes.byref(info)) == helm.EINVAL
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, None, 1, None, None, 0.0, 0.0, 0, 0.0,
+                      ctypes.byref(good), None, None, ctypes.byref(info)) == helm.EINVAL
+    # both or neither source form
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, sxz, 1, rec, None, 0.0, 0.0, 0, 0.0,
+                      ctypes.byref(good), None, None, ctypes.byref(info)) == helm.EINVAL
     # c1 >= c2
-    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, 1, rec, None, 0.0, 0.0, 0, 0.0, ctypes.byref(bad),
-                      None, None, ctypes.byref(info)) == helm.EINVAL
+    assert L.helm_fwi(ctypes.byref(g), fake, 1, w, fake, 1, src, None, 1, rec, None, 0.0, 0.0, 0, 0.0,
+                      ctypes.byref(bad), None, None, ctypes.byref(info)) == helm.EINVAL
+    # a point source outside the domain
+    far = (ctypes.c_double * 2)(0.35, 4.5)
+    B = ctypes.c_void_p(16)
+    assert L.helm_point_sources(ctypes.byref(g), 1, far, B, 81, None) == helm.EINVAL
