@@ -56,7 +56,7 @@ def parse():
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
     p.add_argument("--hessian-only", action="store_true",
-                   help="only run the full-Hessian, PCG and upper-level gradient measurements at 201^2")
+                   help="only run the full-Hessian, PCG, upper-level gradient and FWI measurements at 201^2")
     return p.parse_args()
 
 
@@ -206,6 +206,94 @@ def bilevel_extra(helm, I, w4, G4, alpha=1e-4, mu=1e-8, precision="fp64"):
     return out
 
 
+def pcg_batch_extra(helm, I, w4, G4, alpha=1e-3, mu=1e-8, counts=(1, 2, 4)):
+    """PCG with P2 for several training models in lockstep (one Hessian
+    system each, FP64 contexts), against the same systems one after another."""
+    import numpy as np
+    import torch
+    n_omega = len(w4.omegas)
+    E4 = torch.as_tensor(I.point_sources(G4.N, w4.sources), device="cuda")
+    ridx = torch.as_tensor(np.asarray(w4.receivers, dtype=np.int64), device="cuda")
+    ctx, bs = [], []
+    try:
+        for k in range(max(counts)):
+            wk = I.config_c4(seed=2 + k)
+            Fs = helm.factor_batch([G4] * n_omega, [torch.as_tensor(wk.m_true, device="cuda")] * n_omega,
+                                   wk.omegas, "fp64")
+            Xt, _ = helm.solve_batch(Fs, [E4] * n_omega, tol=TOL)
+            for F in Fs:
+                F.close()
+            d = torch.stack([x[:, ridx] for x in Xt]).contiguous()
+            del Xt
+            m_fwi = wk.m_true + 0.1 * (wk.m - wk.m_true)
+            ctx.append(helm.Hessian(G4, m_fwi, wk.omegas, wk.sources, wk.receivers, d, alpha, mu, precision="fp64",
+                                    tol=TOL))
+            bs.append(wk.m_true - m_fwi)
+        out = {"alpha": alpha, "mu": mu, "pcg_rtol": 1e-6}
+        for K in counts:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, its, _, sts, _ = helm.pcg_batch(ctx[:K], bs[:K], prec_alpha=alpha, prec_mu=mu, rtol=1e-6, maxit=300)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            for c in range(K):
+                helm.pcg_batch(ctx[c:c + 1], bs[c:c + 1], prec_alpha=alpha, prec_mu=mu, rtol=1e-6, maxit=300)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            solves = sum(2 * n_omega * len(w4.sources) * (i + 1) for i in its)
+            out[f"models_{K}"] = {"iterations": its, "status": sts, "lockstep_ms": round(tb * 1e3, 3),
+                                  "one_after_another_ms": round(ts * 1e3, 3), "speedup": round(ts / tb, 3),
+                                  "solves_per_s": round(solves / tb, 2)}
+        return out
+    finally:
+        for H in ctx:
+            H.close()
+
+
+def fwi_extra(helm, I, precision="fp64", max_iters=20, n_data=301):
+    """Lower-level FWI by L-BFGS at the 201^2 configuration (3 frequencies,
+    30 sources, 100 receivers) from the smoothed starting model.  The data
+    come from a second, non-nested grid (n_data^2 over the same domain, the
+    true model resampled onto it), where the sources and receivers fall
+    between nodes: the inverse-crime-free practice of the paper."""
+    import numpy as np
+    import torch
+    w = I.config_c2()
+    G = helm.Grid.of(w)
+    n_omega = len(w.omegas)
+    X = (G.nx - 1) * G.hx
+    Gd = helm.Grid(n_data, n_data, X / (n_data - 1), X / (n_data - 1))
+    m_d = I.resample(w.m_true, (G.nx, G.nz, G.hx, G.hz), (Gd.nx, Gd.nz, Gd.hx, Gd.hz))
+    src = np.array([[(k % G.nx) * G.hx, (k // G.nx) * G.hz] for k in w.sources])
+    rec = np.array([[(k % G.nx) * G.hx, (k // G.nx) * G.hz] for k in w.receivers])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = helm.point_sources(Gd, src)
+    Fs = helm.factor_batch([Gd] * n_omega, [torch.as_tensor(m_d, device="cuda")] * n_omega, w.omegas, "fp64")
+    Xt, _ = helm.solve_batch(Fs, [B] * n_omega, tol=TOL)
+    for F in Fs:
+        F.close()
+    d = torch.stack([helm.restrict(Gd, rec, x, 0) for x in Xt]).contiguous()
+    del Xt, B
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    m, info = helm.fwi(G, w.m, w.omegas, d, w.sources, w.receivers, 1e-6, 1e-8, precision=precision, tol=TOL,
+                       memory=5, max_iters=max_iters, gtol=1e-8)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    err0 = float(np.linalg.norm(w.m - w.m_true))
+    err = float(np.linalg.norm(m.cpu().numpy() - w.m_true))
+    return {"workload": f"c2_layered_201 (3 frequencies, 30 sources, 100 receivers), alpha 1e-6, mu 1e-8; data "
+                        f"from a {n_data}^2 grid (sources and receivers between its nodes)",
+            "precision": precision, "data_ms": round(t_data * 1e3, 3), "iterations": info["iterations"],
+            "evals": info["evals"], "status": info["status"], "phi_ratio": info["phi"] / info["phi0"],
+            "model_error_ratio": err / err0, "ms": round(t * 1e3, 3),
+            "ms_per_eval": round(t * 1e3 / info["evals"], 3), "solves": info["solves"],
+            "solves_per_s": round(info["solves"] / t, 2)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -237,7 +325,9 @@ def main():
         G4 = helm.Grid.of(w4)
         dirs = torch.as_tensor(np.stack(w4.directions), device="cuda")
         print(json.dumps({"hessian_201": hessian_extra(helm, I, w4, G4, dirs),
-                          "upper_grad_201": bilevel_extra(helm, I, w4, G4)}), flush=True)
+                          "upper_grad_201": bilevel_extra(helm, I, w4, G4), "fwi_201": fwi_extra(helm, I),
+                          "pcg_batch_201": pcg_batch_extra(helm, I, w4, G4)}),
+              flush=True)
         return
 
     w = I.config_c3()
@@ -411,6 +501,10 @@ def main():
         # the upper-level gradient of one training model with 100 sensors
         # between nodes (Algorithm "Derivative of psi")
         extras["upper_grad_201"] = bilevel_extra(helm, I, w4, G4)
+        # the lower-level FWI (L-BFGS) at the 201^2 configuration
+        extras["fwi_201"] = fwi_extra(helm, I)
+        # the Hessian systems of several training models in lockstep
+        extras["pcg_batch_201"] = pcg_batch_extra(helm, I, w4, G4)
 
     cpu = None
     if not args.no_cpu_baseline:

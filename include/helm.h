@@ -255,6 +255,20 @@ int helm_hess_pcg(helm_hess_t h, const double* b_dev, double* x_dev, double p_al
                   double rtol, int32_t maxit, void* stream, int32_t* iters, double* relres,
                   helm_info* info);
 
+/* helm_hess_pcg_batch: helm_hess_pcg for `count` independent Hessian
+ * systems H_c x_c = b_c (one per context: for instance one per training
+ * model m', each at its own m_FWI), run in lockstep so that the products
+ * with all the H_c share their sweep launches.  Each system follows exactly
+ * the iteration it would follow alone and leaves the lockstep when it stops.
+ * The contexts must share precision and tol, and be distinct.  Per system:
+ * iters[c], relres[c] (final ||r_n|| / ||r_0||), status[c] (0 converged,
+ * 1 iteration limit, 2 p.Hp <= 0) and infos[c] (each may be NULL).
+ * Returns HELM_OK whatever the statuses (they are results).              */
+int helm_hess_pcg_batch(int32_t count, const helm_hess_t* hs, const double* const* b_devs,
+                        double* const* x_devs, double p_alpha, double p_mu, double rtol,
+                        int32_t maxit, void* stream, int32_t* iters, double* relres,
+                        int32_t* status, helm_info* infos);
+
 void helm_hess_destroy(helm_hess_t h);
 
 /* helm_gamma_solve: X = Gamma(alpha, mu)^{-1} Y for n grid vectors (eq (P2)

@@ -640,6 +640,56 @@ int residual_norms(const helm_factor_s* f, int adjoint, const double* B, int64_t
     return HELM_OK;
 }
 
+// The same for several (factor, B, X) at once: every residual is launched,
+// then one synchronisation brings all norms back.  maxrel[c] per request.
+struct ResidualReq {
+    const helm_factor_s* f;
+    const double* B;
+    int64_t ldb;
+    const double* X;
+    int64_t ldx;
+    double* R;      // r (complex128, ld N) or NULL
+    float* R32;     // conjugated-if-adjoint complex64 copy of r, or NULL
+    int S;
+};
+int residual_norms_batch(const std::vector<ResidualReq>& rq, int adjoint, hipStream_t st, double* maxrel) {
+    const int n = (int)rq.size();
+    if (n == 0) return HELM_OK;
+    Scratch sc(st);
+    std::vector<double*> norms(n);
+    size_t tot = 0;
+    for (auto& r : rq) tot += 2 * (size_t)r.S;
+    std::vector<double> h(tot);
+    size_t off = 0;
+    for (int c = 0; c < n; ++c) {
+        const ResidualReq& r = rq[c];
+        const int64_t N = N_of(r.f->g);
+        const int nblk = (int)((N + 255) / 256);
+        double* partial;
+        int rc = sc.get(&partial, sizeof(double) * 2 * (size_t)nblk * r.S);
+        if (rc) return rc;
+        if ((rc = sc.get(&norms[c], sizeof(double) * 2 * r.S))) return rc;
+        launch_residual(coef_of(r.f), adjoint, r.B, r.ldb, r.X, r.ldx, r.R, N, r.R32, r.S, partial, nblk, st);
+        launch_norms_finish(partial, nblk, r.S, norms[c], st);
+        g_launches += 2;
+        HIPCHECK(hipMemcpyAsync(h.data() + off, norms[c], sizeof(double) * 2 * r.S, hipMemcpyDeviceToHost, st));
+        off += 2 * (size_t)r.S;
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    off = 0;
+    for (int c = 0; c < n; ++c) {
+        double mx = 0.0;
+        for (int s = 0; s < rq[c].S; ++s) {
+            double rr = std::sqrt(h[off + 2 * s]), bb = std::sqrt(h[off + 2 * s + 1]);
+            double rel = bb > 0.0 ? rr / bb : (rr > 0.0 ? INFINITY : 0.0);
+            if (!(rel <= mx)) mx = rel;   // NaN propagates
+        }
+        maxrel[c] = mx;
+        off += 2 * (size_t)rq[c].S;
+    }
+    return HELM_OK;
+}
+
 constexpr int MAX_IR = 10;
 
 // Solve a group of jobs that share one precision.
@@ -683,9 +733,22 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
             if (jobs[c].info) jobs[c].info->solves = jobs[c].S;
         }
         if (tol <= 0.0) return HELM_OK;
-        // measure, and refine in FP64 if the residual is above tol
+        // measure all jobs at once; refine in FP64 those above tol
+        std::vector<ResidualReq> rq;
+        for (auto& jb : jobs) rq.push_back({jb.f, jb.B, jb.ld, jb.X, jb.ld, nullptr, nullptr, jb.S});
+        std::vector<double> first(n);
+        int rc0 = residual_norms_batch(rq, adjoint ? 1 : 0, st, first.data());
+        if (rc0) return rc0;
         for (int c = 0; c < n; ++c) {
             SolveJob& jb = jobs[c];
+            if (first[c] <= tol) {
+                if (jb.info) {
+                    jb.info->ir_iters = 0;
+                    jb.info->max_relres = first[c];
+                    jb.info->solves = jb.S;
+                }
+                continue;
+            }
             const int64_t N = N_of(jb.f->g);
             Scratch sc(st);
             double *R = nullptr, *D = nullptr;
@@ -761,18 +824,23 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
                                  as.data() + c0, false, st);
             if (rc) return rc;
         }
+        // x (+)= conj?(y32); r = b - A x; y32 = conj?(r) for the next correction;
+        // the residuals of all active jobs come back with one synchronisation
+        std::vector<ResidualReq> rq;
         for (int c : idx) {
             const int64_t N = N_of(fs[c]->g);
-            // x (+)= conj?(y32); r = b - A x; y32 = conj?(r) for the next correction
             launch_c64_to_c128(X32[c], N, jobs[c].X, jobs[c].ld, N, jobs[c].S, adjoint ? 1 : 0, first ? 0 : 1, st);
             g_launches += 1;
             if (!first) iters[c] += 1;
-            double rel = 0.0;
-            int rc = residual_norms(fs[c], adjoint, jobs[c].B, jobs[c].ld, jobs[c].X, jobs[c].ld, R64[c], Y32[c],
-                                    jobs[c].S, st, &rel);
-            if (rc) return rc;
-            rels[c] = rel;
-            if (rel <= tol) active[c] = 0;
+            rq.push_back({fs[c], jobs[c].B, jobs[c].ld, jobs[c].X, jobs[c].ld, R64[c], Y32[c], jobs[c].S});
+        }
+        std::vector<double> rel(idx.size());
+        int rc = residual_norms_batch(rq, adjoint ? 1 : 0, st, rel.data());
+        if (rc) return rc;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const int c = idx[q];
+            rels[c] = rel[q];
+            if (rel[q] <= tol) active[c] = 0;
             else if (iters[c] >= MAX_IR) active[c] = 0;
         }
         first = false;
@@ -1142,176 +1210,288 @@ int hess_build(const helm_grid* grid, const double* m_dev, int n_omega, const do
     return HELM_OK;
 }
 
-// hv_a = H mt_a for n_dir directions: per frequency v = A^{-1}(g mt u) for
+// hv_a = H mt_a for n_dir directions, for several contexts at once (one
+// direction block per context): per frequency v = A^{-1}(g mt u) for
 // every source and direction, then
 //   z = A^{-*}(R^* R v - conj(g) mt lambda)   (full) or A^{-*}(R^* R v),
 //   hv += Re g u conj(z) - Re g v conj(lambda) - Re h mt u conj(lambda)  (full)
 //   or    Re g u conj(z),
-// all frequencies of a stage batched into one solve; finally hv += Gamma mt.
-// Synchronises the stream.
-int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStream_t st, helm_info* info) {
-    const int64_t N = N_of(h->g);
-    const int S = h->S, nw = h->n_omega;
-    if ((int64_t)n_dir * S > 65535) return fail(HELM_EINVAL, "n_dir * S must not exceed 65535 (split the directions)");
-    const int cols = n_dir * S;
-    const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
+// the frequencies of all contexts batched into one forward and one adjoint
+// solve (the contexts must share precision and tolerance); finally
+// hv += Gamma mt.  Synchronises the stream.
+int hess_apply_multi(const std::vector<helm_hess_s*>& hs, int n_dir, const std::vector<const double*>& mts,
+                     const std::vector<double*>& hvs, hipStream_t st, std::vector<helm_info>* infos) {
+    const int K = (int)hs.size();
+    for (auto h : hs)
+        if (h->prec != hs[0]->prec || h->tol != hs[0]->tol)
+            return fail(HELM_EINVAL, "batched Hessian products need one precision and tolerance");
     Scratch sc(st);
-    std::vector<double*> W(nw), V(nw), Z(nw);
-    double* RV;
-    int rc;
-    if ((rc = sc.get(&RV, sizeof(double) * 2 * (size_t)h->Nr * cols))) return rc;
-    for (int w = 0; w < nw; ++w) {
-        if ((rc = sc.get(&W[w], vb))) return rc;
-        if ((rc = sc.get(&V[w], vb))) return rc;
-        if ((rc = sc.get(&Z[w], vb))) return rc;
-    }
-    for (int w = 0; w < nw; ++w) launch_gn_rhs(coef_of(h->F[w]), h->U[w], N, S, mt, n_dir, W[w], N, st);
-    g_launches += nw;
+    struct Part {
+        std::vector<double*> W, V, Z;
+        double* RV;
+        std::vector<helm_info> i1, i2;
+    };
+    std::vector<Part> P(K);
     std::vector<SolveJob> j1, j2;
-    std::vector<helm_info> i1(nw), i2(nw);
-    for (int w = 0; w < nw; ++w) j1.push_back({h->F[w], W[w], V[w], cols, N, &i1[w]});
-    if ((rc = solve_jobs(j1, false, h->tol, st))) return rc;
+    int rc;
+    for (int c = 0; c < K; ++c) {
+        helm_hess_s* h = hs[c];
+        const int64_t N = N_of(h->g);
+        const int S = h->S, nw = h->n_omega;
+        if ((int64_t)n_dir * S > 65535)
+            return fail(HELM_EINVAL, "n_dir * S must not exceed 65535 (split the directions)");
+        const int cols = n_dir * S;
+        const size_t vb = sizeof(double) * 2 * (size_t)N * cols;
+        Part& q = P[c];
+        q.W.resize(nw), q.V.resize(nw), q.Z.resize(nw), q.i1.resize(nw), q.i2.resize(nw);
+        if ((rc = sc.get(&q.RV, sizeof(double) * 2 * (size_t)h->Nr * cols))) return rc;
+        for (int w = 0; w < nw; ++w) {
+            if ((rc = sc.get(&q.W[w], vb))) return rc;
+            if ((rc = sc.get(&q.V[w], vb))) return rc;
+            if ((rc = sc.get(&q.Z[w], vb))) return rc;
+            launch_gn_rhs(coef_of(h->F[w]), h->U[w], N, S, mts[c], n_dir, q.W[w], N, st);
+            j1.push_back({h->F[w], q.W[w], q.V[w], cols, N, &q.i1[w]});
+        }
+        g_launches += nw;
+    }
+    if ((rc = solve_jobs(j1, false, hs[0]->tol, st))) return rc;
     // W now holds the right-hand side of the z solve
-    for (int w = 0; w < nw; ++w) {
-        if (h->full) launch_zeta_rhs(coef_of(h->F[w]), h->L[w], N, S, mt, n_dir, W[w], N, st);
-        else launch_zero(W[w], vb, st);
-        // W += R^T R v
-        launch_restrict(V[w], N, h->rnode, h->rw, h->ntap, h->Nr, cols, RV, h->Nr, st);
-        if (h->nt > 0) launch_restrict_adj(RV, h->Nr, h->tnode, h->tptr, h->tq, h->tw, h->nt, cols, W[w], N, st);
-        g_launches += 3;
+    for (int c = 0; c < K; ++c) {
+        helm_hess_s* h = hs[c];
+        const int64_t N = N_of(h->g);
+        const int S = h->S, nw = h->n_omega, cols = n_dir * S;
+        Part& q = P[c];
+        for (int w = 0; w < nw; ++w) {
+            if (h->full) launch_zeta_rhs(coef_of(h->F[w]), h->L[w], N, S, mts[c], n_dir, q.W[w], N, st);
+            else launch_zero(q.W[w], sizeof(double) * 2 * (size_t)N * cols, st);
+            // W += R^T R v
+            launch_restrict(q.V[w], N, h->rnode, h->rw, h->ntap, h->Nr, cols, q.RV, h->Nr, st);
+            if (h->nt > 0)
+                launch_restrict_adj(q.RV, h->Nr, h->tnode, h->tptr, h->tq, h->tw, h->nt, cols, q.W[w], N, st);
+            g_launches += 3;
+            j2.push_back({h->F[w], q.W[w], q.Z[w], cols, N, &q.i2[w]});
+        }
     }
-    for (int w = 0; w < nw; ++w) j2.push_back({h->F[w], W[w], Z[w], cols, N, &i2[w]});
-    if ((rc = solve_jobs(j2, true, h->tol, st))) return rc;
-    launch_zero(hv, sizeof(double) * N * n_dir, st);
-    for (int w = 0; w < nw; ++w) {
-        if (h->full)
-            launch_hv_full(coef_of(h->F[w]), h->U[w], h->L[w], N, S, V[w], Z[w], N, mt, n_dir, hv, st);
-        else
-            launch_hv(coef_of(h->F[w]), h->U[w], N, S, Z[w], N, n_dir, hv, N, st);
-    }
-    g_launches += 1 + nw;
-    if (h->alpha != 0.0 || h->mu != 0.0) {
-        const int nblk = (int)((N + 255) / 256);
-        double* part;
-        if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
-        for (int a = 0; a < n_dir; ++a)
-            launch_gamma(mt + (size_t)a * N, h->g.nx, h->g.nz, h->alpha, h->mu, hv + (size_t)a * N, part, nblk, st);
-        g_launches += n_dir;
+    if ((rc = solve_jobs(j2, true, hs[0]->tol, st))) return rc;
+    for (int c = 0; c < K; ++c) {
+        helm_hess_s* h = hs[c];
+        const int64_t N = N_of(h->g);
+        const int S = h->S, nw = h->n_omega;
+        Part& q = P[c];
+        launch_zero(hvs[c], sizeof(double) * N * n_dir, st);
+        for (int w = 0; w < nw; ++w) {
+            if (h->full)
+                launch_hv_full(coef_of(h->F[w]), h->U[w], h->L[w], N, S, q.V[w], q.Z[w], N, mts[c], n_dir, hvs[c],
+                               st);
+            else
+                launch_hv(coef_of(h->F[w]), h->U[w], N, S, q.Z[w], N, n_dir, hvs[c], N, st);
+        }
+        g_launches += 1 + nw;
+        if (h->alpha != 0.0 || h->mu != 0.0) {
+            const int nblk = (int)((N + 255) / 256);
+            double* part;
+            if ((rc = sc.get(&part, sizeof(double) * nblk))) return rc;
+            for (int a = 0; a < n_dir; ++a)
+                launch_gamma(mts[c] + (size_t)a * N, h->g.nx, h->g.nz, h->alpha, h->mu, hvs[c] + (size_t)a * N, part,
+                             nblk, st);
+            g_launches += n_dir;
+        }
     }
     HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipGetLastError());
-    if (info) {
-        helm_info tot{};
-        tot.bad_block = tot.bad_row = -1;
-        for (int w = 0; w < nw; ++w) {
-            merge_info(&tot, i1[w]);
-            merge_info(&tot, i2[w]);
+    if (infos) {
+        infos->assign(K, helm_info{});
+        for (int c = 0; c < K; ++c) {
+            helm_info& tot = (*infos)[c];
+            tot.bad_block = tot.bad_row = -1;
+            for (size_t w = 0; w < P[c].i1.size(); ++w) {
+                merge_info(&tot, P[c].i1[w]);
+                merge_info(&tot, P[c].i2[w]);
+            }
         }
-        *info = tot;
     }
     return HELM_OK;
 }
 
-// Preconditioned conjugate gradients for H x = b (eq (rho)) with P2 =
-// Gamma(p_alpha, p_mu) (eq (P2); none when p_mu <= 0), stopping once
-// ||r_n|| <= rtol ||r_0||.  x holds the start vector on entry.  The scalars
-// of each iteration come back to the host (three small reads against two
-// batched solves per frequency for the product with H).
-int hess_pcg(helm_hess_s* h, const double* b, double* x, double p_alpha, double p_mu, double rtol, int maxit,
-             hipStream_t st, int32_t* iters, double* relres, helm_info* info) {
-    if (!b || !x || maxit < 0 || !(rtol >= 0.0)) return fail(HELM_EINVAL, "bad pcg arguments");
+int hess_apply(helm_hess_s* h, int n_dir, const double* mt, double* hv, hipStream_t st, helm_info* info) {
+    std::vector<helm_info> infos;
+    int rc = hess_apply_multi({h}, n_dir, {mt}, {hv}, st, &infos);
+    if (rc == HELM_OK && info) *info = infos[0];
+    return rc;
+}
+
+// the P2 = Gamma(p_alpha, p_mu) tables of a context, made on first use
+int hess_p2_tables(helm_hess_s* h, double p_alpha, double p_mu, hipStream_t st) {
+    if (h->Cx && h->p_alpha == p_alpha && h->p_mu == p_mu) return HELM_OK;
+    const int nx = h->g.nx, nz = h->g.nz;
+    int rc;
+    if (!h->Cx) {
+        if ((rc = hess_own(h, &h->Cx, sizeof(double) * nx * nx))) return rc;
+        if ((rc = hess_own(h, &h->Cz, sizeof(double) * nz * nz))) return rc;
+        if ((rc = hess_own(h, &h->eig, sizeof(double) * N_of(h->g)))) return rc;
+    }
+    // the tables were allocated on the creation stream
+    HIPCHECK(hipStreamSynchronize(h->st));
+    if ((rc = gamma_tables(nx, nz, p_alpha, p_mu, h->Cx, h->Cz, h->eig, st))) return rc;
+    h->p_alpha = p_alpha;
+    h->p_mu = p_mu;
+    return HELM_OK;
+}
+
+// Preconditioned conjugate gradients for H_c x_c = b_c (eq (rho)), one
+// system per context, run in lockstep so that the products with all the
+// H_c share their sweep launches; P2 = Gamma(p_alpha, p_mu) (eq (P2); none
+// when p_mu <= 0); each system stops once ||r_n|| <= rtol ||r_0|| (or on
+// p.Hp <= 0, status 2) and leaves the lockstep.  x_c holds the start
+// vector on entry.  The scalars of a step come back to the host together.
+// status[c]: 0 converged, 1 iteration limit, 2 not positive definite.
+int hess_pcg_multi(const std::vector<helm_hess_s*>& hs, const std::vector<const double*>& b,
+                   const std::vector<double*>& x, double p_alpha, double p_mu, double rtol, int maxit,
+                   hipStream_t st, int32_t* iters, double* relres, int32_t* status, std::vector<helm_info>* infos) {
+    const int K = (int)hs.size();
+    for (int c = 0; c < K; ++c)
+        if (!b[c] || !x[c]) return fail(HELM_EINVAL, "bad pcg arguments");
+    if (maxit < 0 || !(rtol >= 0.0)) return fail(HELM_EINVAL, "bad pcg arguments");
     const bool prec = p_mu > 0.0;
     if (!prec && p_alpha != 0.0) return fail(HELM_EINVAL, "P2 = Gamma(alpha, mu) needs mu > 0");
     if (prec && !(p_alpha >= 0.0)) return fail(HELM_EINVAL, "P2 = Gamma(alpha, mu) needs alpha >= 0");
-    const int64_t N = N_of(h->g);
-    const int nx = h->g.nx, nz = h->g.nz;
     Scratch sc(st);
-    double *r, *z, *p, *q, *part, *scal, *T1 = nullptr, *T2 = nullptr;
+    std::vector<double*> r(K), z(K), p(K), q(K), T1(K), T2(K);
+    double *part, *scal;
     int rc;
-    if ((rc = sc.get(&r, sizeof(double) * N))) return rc;
-    if ((rc = sc.get(&p, sizeof(double) * N))) return rc;
-    if ((rc = sc.get(&q, sizeof(double) * N))) return rc;
-    if ((rc = sc.get(&part, sizeof(double) * dot_blocks(N)))) return rc;
-    if ((rc = sc.get(&scal, sizeof(double) * 4))) return rc;
-    z = r;
-    if (prec) {
-        if ((rc = sc.get(&z, sizeof(double) * N))) return rc;
-        if ((rc = sc.get(&T1, sizeof(double) * N))) return rc;
-        if ((rc = sc.get(&T2, sizeof(double) * N))) return rc;
-        if (h->p_alpha != p_alpha || h->p_mu != p_mu || !h->Cx) {
-            if (!h->Cx) {
-                if ((rc = hess_own(h, &h->Cx, sizeof(double) * nx * nx))) return rc;
-                if ((rc = hess_own(h, &h->Cz, sizeof(double) * nz * nz))) return rc;
-                if ((rc = hess_own(h, &h->eig, sizeof(double) * N))) return rc;
-            }
-            // the tables were allocated on the creation stream
-            HIPCHECK(hipStreamSynchronize(h->st));
-            if ((rc = gamma_tables(nx, nz, p_alpha, p_mu, h->Cx, h->Cz, h->eig, st))) return rc;
-            h->p_alpha = p_alpha;
-            h->p_mu = p_mu;
+    int64_t Nmax = 0;
+    for (auto h : hs) Nmax = std::max(Nmax, N_of(h->g));
+    if ((rc = sc.get(&part, sizeof(double) * dot_blocks(Nmax)))) return rc;
+    if ((rc = sc.get(&scal, sizeof(double) * K))) return rc;
+    for (int c = 0; c < K; ++c) {
+        const size_t vb = sizeof(double) * N_of(hs[c]->g);
+        if ((rc = sc.get(&r[c], vb))) return rc;
+        if ((rc = sc.get(&p[c], vb))) return rc;
+        if ((rc = sc.get(&q[c], vb))) return rc;
+        z[c] = r[c];
+        if (prec) {
+            if ((rc = sc.get(&z[c], vb))) return rc;
+            if ((rc = sc.get(&T1[c], vb))) return rc;
+            if ((rc = sc.get(&T2[c], vb))) return rc;
+            if ((rc = hess_p2_tables(hs[c], p_alpha, p_mu, st))) return rc;
         }
     }
-    auto dot = [&](const double* u, const double* v, double* out) -> int {
-        launch_dot(u, v, N, part, scal, st);
-        g_launches += 2;
-        HIPCHECK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    // u.v for the listed systems, one synchronisation
+    auto dots = [&](const std::vector<int>& cs, const std::vector<double*>& u, const std::vector<double*>& v,
+                    std::vector<double>& out) -> int {
+        for (size_t k = 0; k < cs.size(); ++k) {
+            const int c = cs[k];
+            launch_dot(u[c], v[c], N_of(hs[c]->g), part, scal + k, st);
+            g_launches += 2;
+        }
+        std::vector<double> h(cs.size());
+        HIPCHECK(hipMemcpyAsync(h.data(), scal, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
+        for (size_t k = 0; k < cs.size(); ++k) out[cs[k]] = h[k];
         return HELM_OK;
     };
-    auto precondition = [&]() {
-        if (prec) {
-            launch_gamma_solve(h->Cx, h->Cz, h->eig, nx, nz, 1, r, z, T1, T2, st);
+    auto apply = [&](const std::vector<int>& cs, const std::vector<double*>& in) -> int {
+        std::vector<helm_hess_s*> hh;
+        std::vector<const double*> mm;
+        std::vector<double*> oo;
+        for (int c : cs) {
+            hh.push_back(hs[c]);
+            mm.push_back(in[c]);
+            oo.push_back(q[c]);
+        }
+        std::vector<helm_info> ii;
+        int r2 = hess_apply_multi(hh, 1, mm, oo, st, &ii);
+        if (r2) return r2;
+        for (size_t k = 0; k < cs.size(); ++k) merge_info(&(*infos)[cs[k]], ii[k]);
+        return HELM_OK;
+    };
+    auto precondition = [&](const std::vector<int>& cs) {
+        if (!prec) return;
+        for (int c : cs) {
+            launch_gamma_solve(hs[c]->Cx, hs[c]->Cz, hs[c]->eig, hs[c]->g.nx, hs[c]->g.nz, 1, r[c], z[c], T1[c],
+                               T2[c], st);
             g_launches += 4;
         }
     };
-    helm_info tot{}, ia{};
-    tot.bad_block = tot.bad_row = -1;
+    infos->assign(K, helm_info{});
+    for (auto& i0 : *infos) i0.bad_block = i0.bad_row = -1;
+    std::vector<double> rr0(K), rr(K), rz(K), pq(K), rz1(K), rel(K, 0.0);
+    std::vector<int> all(K), it(K, 0), st_(K, 1);
+    for (int c = 0; c < K; ++c) all[c] = c;
     // r = b - H x
-    if ((rc = hess_apply(h, 1, x, q, st, &ia))) return rc;
-    merge_info(&tot, ia);
-    launch_lincomb(r, 1.0, b, -1.0, q, N, st);
-    g_launches += 1;
-    double rr0 = 0.0, rr = 0.0, rz = 0.0, pq = 0.0;
-    if ((rc = dot(r, r, &rr0))) return rc;
-    int it = 0;
-    double rel = rr0 > 0.0 ? 1.0 : 0.0;
-    bool indefinite = false;
-    if (rr0 > 0.0) {
-        precondition();
-        launch_lincomb(p, 1.0, z, 0.0, z, N, st);
-        g_launches += 1;
-        if ((rc = dot(r, z, &rz))) return rc;
-        while (it < maxit) {
-            if ((rc = hess_apply(h, 1, p, q, st, &ia))) return rc;
-            merge_info(&tot, ia);
-            if ((rc = dot(p, q, &pq))) return rc;
-            if (!(pq > 0.0)) {
-                indefinite = true;
-                break;
-            }
-            const double a = rz / pq;
-            launch_lincomb(x, 1.0, x, a, p, N, st);
-            launch_lincomb(r, 1.0, r, -a, q, N, st);
-            g_launches += 2;
-            if ((rc = dot(r, r, &rr))) return rc;
-            ++it;
-            rel = std::sqrt(rr / rr0);
-            if (rel <= rtol) break;
-            precondition();
-            double rz1 = 0.0;
-            if ((rc = dot(r, z, &rz1))) return rc;
-            launch_lincomb(p, 1.0, z, rz1 / rz, p, N, st);
-            g_launches += 1;
-            rz = rz1;
+    if ((rc = apply(all, x))) return rc;
+    for (int c = 0; c < K; ++c) launch_lincomb(r[c], 1.0, b[c], -1.0, q[c], N_of(hs[c]->g), st);
+    g_launches += K;
+    if ((rc = dots(all, r, r, rr0))) return rc;
+    std::vector<int> act;
+    for (int c = 0; c < K; ++c) {
+        if (rr0[c] > 0.0) {
+            rel[c] = 1.0;
+            act.push_back(c);
+        } else {
+            st_[c] = 0;
         }
+    }
+    precondition(act);
+    for (int c : act) launch_lincomb(p[c], 1.0, z[c], 0.0, z[c], N_of(hs[c]->g), st);
+    g_launches += (int)act.size();
+    if ((rc = dots(act, r, z, rz))) return rc;
+    for (int step = 0; step < maxit && !act.empty(); ++step) {
+        if ((rc = apply(act, p))) return rc;
+        if ((rc = dots(act, p, q, pq))) return rc;
+        std::vector<int> nxt;
+        for (int c : act) {
+            if (!(pq[c] > 0.0)) {
+                st_[c] = 2;
+                continue;
+            }
+            const double a = rz[c] / pq[c];
+            const int64_t N = N_of(hs[c]->g);
+            launch_lincomb(x[c], 1.0, x[c], a, p[c], N, st);
+            launch_lincomb(r[c], 1.0, r[c], -a, q[c], N, st);
+            g_launches += 2;
+            nxt.push_back(c);
+        }
+        act = nxt;
+        if ((rc = dots(act, r, r, rr))) return rc;
+        nxt.clear();
+        for (int c : act) {
+            ++it[c];
+            rel[c] = std::sqrt(rr[c] / rr0[c]);
+            if (rel[c] <= rtol) st_[c] = 0;
+            else nxt.push_back(c);
+        }
+        act = nxt;
+        precondition(act);
+        if ((rc = dots(act, r, z, rz1))) return rc;
+        for (int c : act) {
+            launch_lincomb(p[c], 1.0, z[c], rz1[c] / rz[c], p[c], N_of(hs[c]->g), st);
+            rz[c] = rz1[c];
+        }
+        g_launches += (int)act.size();
     }
     HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipGetLastError());
+    for (int c = 0; c < K; ++c) {
+        if (iters) iters[c] = it[c];
+        if (relres) relres[c] = rel[c];
+        if (status) status[c] = st_[c];
+    }
+    return HELM_OK;
+}
+
+int hess_pcg(helm_hess_s* h, const double* b, double* x, double p_alpha, double p_mu, double rtol, int maxit,
+             hipStream_t st, int32_t* iters, double* relres, helm_info* info) {
+    std::vector<helm_info> infos;
+    int32_t it = 0, stc = 1;
+    double rel = 0.0;
+    int rc = hess_pcg_multi({h}, {b}, {x}, p_alpha, p_mu, rtol, maxit, st, &it, &rel, &stc, &infos);
+    if (rc) return rc;
     if (iters) *iters = it;
     if (relres) *relres = rel;
-    if (info) *info = tot;
-    if (indefinite) return fail(HELM_ENOCONV, "p.Hp <= 0: the Hessian is not positive definite along a search direction");
-    if (!(rel <= rtol)) return fail(HELM_ENOCONV, "PCG stopped at relative residual " + std::to_string(rel));
+    if (info) *info = infos[0];
+    if (stc == 2) return fail(HELM_ENOCONV, "p.Hp <= 0: the Hessian is not positive definite along a search direction");
+    if (stc != 0) return fail(HELM_ENOCONV, "PCG stopped at relative residual " + std::to_string(rel));
     return HELM_OK;
 }
 
@@ -1904,6 +2084,28 @@ int helm_hess_pcg(helm_hess_t h, const double* b_dev, double* x_dev, double p_al
                   int32_t maxit, void* stream, int32_t* iters, double* relres, helm_info* info) {
     if (!h) return fail(HELM_EINVAL, "Hessian handle is NULL");
     return hess_pcg(h, b_dev, x_dev, p_alpha, p_mu, rtol, maxit, S_(stream), iters, relres, info);
+}
+
+int helm_hess_pcg_batch(int32_t count, const helm_hess_t* hs, const double* const* b_devs, double* const* x_devs,
+                        double p_alpha, double p_mu, double rtol, int32_t maxit, void* stream, int32_t* iters,
+                        double* relres, int32_t* status, helm_info* infos) {
+    if (count <= 0 || !hs || !b_devs || !x_devs) return fail(HELM_EINVAL, "bad pcg_batch arguments");
+    std::vector<helm_hess_s*> hh(count);
+    std::vector<const double*> bb(count);
+    std::vector<double*> xx(count);
+    for (int c = 0; c < count; ++c) {
+        if (!hs[c]) return fail(HELM_EINVAL, "Hessian handle is NULL");
+        for (int d = 0; d < c; ++d)
+            if (hs[d] == hs[c]) return fail(HELM_EINVAL, "a context appears twice in the batch");
+        hh[c] = hs[c];
+        bb[c] = b_devs[c];
+        xx[c] = x_devs[c];
+    }
+    std::vector<helm_info> ii;
+    int rc = hess_pcg_multi(hh, bb, xx, p_alpha, p_mu, rtol, maxit, S_(stream), iters, relres, status, &ii);
+    if (rc == HELM_OK && infos)
+        for (int c = 0; c < count; ++c) infos[c] = ii[c];
+    return rc;
 }
 
 void helm_hess_destroy(helm_hess_t h) { hess_free(h); }

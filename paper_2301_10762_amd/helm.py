@@ -120,6 +120,8 @@ def lib():
                            ctypes.POINTER(_LbfgsOpts), _vp, ctypes.POINTER(f64), ctypes.POINTER(_FwiInfo)]
     L.helm_hess_apply.argtypes = [_vp, i32, _vp, _vp, _vp, I]
     L.helm_hess_pcg.argtypes = [_vp, _vp, _vp, f64, f64, f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), I]
+    L.helm_hess_pcg_batch.argtypes = [i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), f64, f64,
+                                      f64, i32, _vp, ctypes.POINTER(i32), ctypes.POINTER(f64), ctypes.POINTER(i32), I]
     L.helm_hess_destroy.argtypes = [_vp]
     L.helm_hess_destroy.restype = None
     L.helm_gamma_solve.argtypes = [G, f64, f64, i32, _vp, _vp, _vp]
@@ -143,7 +145,7 @@ def lib():
                  "helm_solve_batch", "helm_misfit_grad", "helm_gn_hvp", "helm_residual", "helm_tile_inverse",
                  "helm_mfma_probe", "helm_hess_create", "helm_hess_apply", "helm_hess_pcg", "helm_gamma_solve",
                  "helm_hess_create_at", "helm_upper_grad", "helm_restrict", "helm_fwi",
-                 "helm_point_sources"):
+                 "helm_point_sources", "helm_hess_pcg_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -574,6 +576,32 @@ def restrict(grid: Grid, positions, U, deriv: int = 0, stream=None):
     _check(lib().helm_restrict(ctypes.byref(grid.c()), len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                int(deriv), _ptr(Ud), Ud.shape[0], grid.N, _ptr(out), _stream(stream)))
     return out
+
+
+_PCG_STATUS = {0: "converged", 1: "max_iters", 2: "indefinite"}
+
+
+def pcg_batch(contexts, bs, x0s=None, prec_alpha: float = 0.0, prec_mu: float = 0.0, rtol: float = 1e-6,
+              maxit: int = 1000, stream=None):
+    """PCG for several Hessian systems in lockstep (helm_hess_pcg_batch):
+    contexts[c] x_c = bs[c].  Returns ([x_c], [iterations], [relres],
+    [status], [Info])."""
+    torch = _torch()
+    K = len(contexts)
+    bd = [_dev_f64(b, H.grid.N).contiguous() for b, H in zip(bs, contexts)]
+    xs = [torch.ones(H.grid.N, dtype=torch.float64, device="cuda") if x0s is None
+          else _dev_f64(x0s[c], H.grid.N).clone() for c, H in enumerate(contexts)]
+    harr = (_vp * K)(*[H.h for H in contexts])
+    barr = (_vp * K)(*[b.data_ptr() for b in bd])
+    xarr = (_vp * K)(*[x.data_ptr() for x in xs])
+    it = (ctypes.c_int32 * K)()
+    rr = (ctypes.c_double * K)()
+    stt = (ctypes.c_int32 * K)()
+    infos = (_Info * K)()
+    _check(lib().helm_hess_pcg_batch(K, harr, barr, xarr, float(prec_alpha), float(prec_mu), float(rtol), int(maxit),
+                                     _stream(stream), it, rr, stt, infos))
+    return (xs, [int(v) for v in it], [float(v) for v in rr], [_PCG_STATUS.get(v, v) for v in stt],
+            [Info.of(infos[c]) for c in range(K)])
 
 
 def gamma_solve(grid: Grid, alpha: float, mu: float, Y, stream=None):

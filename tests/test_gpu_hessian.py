@@ -244,3 +244,28 @@ def test_pcg_reports_nonconvergence(helm):
         assert e.value.code == helm.ENOCONV
     finally:
         Hc.close()
+
+
+def test_pcg_batch_equals_single(helm):
+    """Three systems (different models and grids) in lockstep: each follows
+    exactly the iteration it follows alone (bitwise), whatever the others."""
+    print("pcg batch", flush=True)
+    cases = []
+    for n, seed in ((15, 7), (17, 3), (15, 11)):
+        w = I.small_layered(n, seed, 3, 5, ppws=(8.0, 12.0))
+        g, d_obs = _fwi(w)
+        cases.append((w, d_obs))
+    alpha, mu = 0.05, 1e-3
+    ctx = [helm.Hessian(helm.Grid.of(w), w.m, w.omegas, w.sources, w.receivers, d, alpha, mu, tol=1e-11)
+           for w, d in cases]
+    try:
+        bs = [w.m_true - w.m for w, _ in cases]
+        xs, its, rrs, sts, _ = helm.pcg_batch(ctx, bs, prec_alpha=alpha, prec_mu=mu, rtol=1e-9)
+        for c, H in enumerate(ctx):
+            x1, it1, rr1, _ = H.pcg(bs[c], prec_alpha=alpha, prec_mu=mu, rtol=1e-9)
+            assert sts[c] == "converged"
+            assert its[c] == it1 and rrs[c] == rr1
+            assert torch.equal(xs[c], x1)
+    finally:
+        for H in ctx:
+            H.close()
