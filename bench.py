@@ -43,8 +43,8 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2301_10762_amd", "csrc", f)
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     p.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 comparison (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -55,6 +55,8 @@ def parse():
                    help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
+    p.add_argument("--misfit-only", action="store_true",
+                   help="only run phi + grad phi (forward + adjoint + gradient assembly) at the 401^2 workload")
     p.add_argument("--hessian-only", action="store_true",
                    help="only run the full-Hessian, PCG, upper-level gradient and FWI measurements at 201^2")
     return p.parse_args()
@@ -96,6 +98,33 @@ def read_traffic(prec):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def misfit_extra(helm, I, w, G, m_dev, E, prec, reps=2):
+    """phi and grad phi (forward + adjoint solves, gradient assembly) at the
+    401^2 workload with 200 receivers on the surface; the observations are
+    this library's own forward data at the true model (an input for timing,
+    not a check)."""
+    import numpy as np
+    import torch
+    n_omega, S = len(w.omegas), len(w.sources)
+    rec = w.receivers
+    Fs = helm.factor_batch([G] * n_omega, [torch.as_tensor(w.m_true, device="cuda")] * n_omega, w.omegas, "fp64")
+    Xt, _ = helm.solve_batch(Fs, [E] * n_omega, tol=TOL)
+    for F in Fs:
+        F.close()
+    ridx = torch.as_tensor(np.asarray(rec, dtype=np.int64), device="cuda")
+    d_obs = torch.stack([x[:, ridx] for x in Xt]).contiguous()
+    del Xt
+    helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        phi, grad, ginfo = helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / reps
+    return {"ms": round(tg * 1e3, 3), "solves_per_s": round(2 * n_omega * S / tg, 2), "solves": 2 * n_omega * S,
+            "max_relres": ginfo.max_relres}
 
 
 def hessian_extra(helm, I, w4, G4, dirs, alpha=1e-4, mu=1e-8, precisions=("fp64", "fp32_ir")):
@@ -335,6 +364,9 @@ def main():
     n_omega, S = len(w.omegas), len(w.sources)
     m_dev = torch.as_tensor(w.m, dtype=torch.float64, device="cuda")
     E = torch.as_tensor(I.point_sources(G.N, w.sources), device="cuda")
+    if args.misfit_only:
+        print(json.dumps({"misfit_grad": misfit_extra(helm, I, w, G, m_dev, E, args.precision)}), flush=True)
+        return
     X = [torch.empty_like(E) for _ in range(n_omega)]
     torch.cuda.synchronize()
 
@@ -454,28 +486,8 @@ def main():
             for F in Fs:
                 F.close()
         extras["factor_ms"] = round(min(tf) * 1e3, 3)
-        # forward + adjoint: phi and grad phi at the same workload (200
-        # receivers on the surface); the observations are this library's own
-        # forward data at the true model (an input for timing, not a check)
-        rec = w.receivers
-        Fs = helm.factor_batch([G] * n_omega, [torch.as_tensor(w.m_true, device="cuda")] * n_omega, w.omegas,
-                               "fp64")
-        Xt, _ = helm.solve_batch(Fs, [E] * n_omega, tol=TOL)
-        for F in Fs:
-            F.close()
-        ridx = torch.as_tensor(np.asarray(rec, dtype=np.int64), device="cuda")
-        d_obs = torch.stack([x[:, ridx] for x in Xt]).contiguous()
-        del Xt
-        helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = 2
-        for _ in range(reps):
-            phi, grad, ginfo = helm.misfit_grad(G, m_dev, w.omegas, d_obs, w.sources, rec, precision=prec, tol=TOL)
-        torch.cuda.synchronize()
-        tg = (time.perf_counter() - t0) / reps
-        extras["misfit_grad"] = {"ms": round(tg * 1e3, 3), "solves_per_s": round(2 * n_omega * S / tg, 2),
-                                 "solves": 2 * n_omega * S, "max_relres": ginfo.max_relres}
+        # forward + adjoint: phi and grad phi at the same workload
+        extras["misfit_grad"] = misfit_extra(helm, I, w, G, m_dev, E, prec)
         # Gauss-Newton Hessian-vector products: 201^2, 4 frequencies, 32
         # sources, 100 receivers, 8 directions
         w4 = I.config_c4()
