@@ -100,6 +100,29 @@ def read_traffic(prec):
         return None
 
 
+def per_omega_latency(helm, w, G, m_dev, E, prec, reps=20, warm=3):
+    """Latency of one frequency alone (factor + all S solves to the
+    tolerance) at the 401^2 workload: p50 / p99 over `reps` repeats after
+    `warm` warm-ups, per frequency."""
+    import torch
+    out = {}
+    for om in w.omegas:
+        lat = []
+        for r in range(warm + reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = helm.factor(G, m_dev, om, prec)
+            _, info = F.solve(E, tol=TOL)
+            F.close()
+            torch.cuda.synchronize()
+            if r >= warm:
+                lat.append(time.perf_counter() - t0)
+        f_hz = om / (2 * math.pi)
+        out[f"{f_hz:.2f}Hz"] = {"p50_ms": round(percentile(lat, 0.5) * 1e3, 3),
+                               "p99_ms": round(percentile(lat, 0.99) * 1e3, 3), "max_relres": info.max_relres}
+    return out
+
+
 def misfit_extra(helm, I, w, G, m_dev, E, prec, reps=2):
     """phi and grad phi (forward + adjoint solves, gradient assembly) at the
     401^2 workload with 200 receivers on the surface; the observations are
@@ -486,6 +509,8 @@ def main():
             for F in Fs:
                 F.close()
         extras["factor_ms"] = round(min(tf) * 1e3, 3)
+        # one frequency alone: factor + 64 solves, p50 / p99 over 20 repeats
+        extras["per_omega_latency"] = per_omega_latency(helm, w, G, m_dev, E, prec)
         # forward + adjoint: phi and grad phi at the same workload
         extras["misfit_grad"] = misfit_extra(helm, I, w, G, m_dev, E, prec)
         # Gauss-Newton Hessian-vector products: 201^2, 4 frequencies, 32

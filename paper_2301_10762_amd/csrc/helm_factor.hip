@@ -19,6 +19,7 @@
 // and inverts it, so the sequential pivoting of the next step runs
 // concurrently with this step's matrix-core update.
 #include "helm_device.h"
+#include "helm_launch.h"
 
 namespace helm {
 

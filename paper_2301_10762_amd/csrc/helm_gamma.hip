@@ -15,7 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "helm_device.h"
-#include "helm_internal.h"
+#include "helm_launch.h"
 
 namespace helm {
 

@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "helm.h"
-#include "helm_internal.h"
+#include "helm_launch.h"
 
 using namespace helm;
 

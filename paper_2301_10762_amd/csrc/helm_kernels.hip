@@ -26,6 +26,7 @@
 // its row/column (64 contiguous bytes) and feeds them to four successive
 // instructions, so every operand load is a contiguous vector load.
 #include "helm_device.h"
+#include "helm_launch.h"
 
 namespace helm {
 // ------------------------------------------------------ elementwise / FP64 --

@@ -10,6 +10,7 @@
 // fixed order) and, for the same rows, the coupling vector the next step
 // needs, so each step reads one operand vector instead of two.
 #include "helm_device.h"
+#include "helm_launch.h"
 
 namespace helm {
 
