@@ -1,4 +1,4 @@
-"""Two batches in flight: the factorisation of batch k+1 runs while batch k
+"""Batches in flight: the factorisation of later batches runs while batch k
 is solved.
 
 Both phases of one batch are latency-bound chains of small launches (one
@@ -6,14 +6,15 @@ launch per panel step of the block factorisation, one per block row of a
 sweep), and neither fills the GPU: a factor step keeps about two
 workgroups per compute unit busy, a sweep step four.  Independent batches
 (the frequencies of different models, or successive requests) can therefore
-share the GPU: batch k+1 is factored on one stream while batch k is solved
-on another, each driven by its own host thread (the library holds no
+share the GPU: batch k+1 (and with factor_streams = f > 1, batches up to
+k+f, side by side) is factored while batch k is solved on another stream,
+each stream driven by its own host thread (the library holds no
 global lock, and ctypes releases the interpreter lock for the duration of
 a call).  Every batch is still factored and solved completely,
 with the same kernels and arithmetic as the serial schedule, so the results
 are bitwise those of solve_batch(factor_batch(...)).
 
-    pipe = Pipeline()
+    pipe = Pipeline(factor_streams=1)
     results = pipe.run(batches)   # [(X list, info list)] per batch
 """
 from __future__ import annotations
@@ -36,13 +37,22 @@ class Batch:
 
 
 class Pipeline:
-    def __init__(self):
+    """factor_streams factorisations run side by side (each on its own
+    stream and host thread; batch k goes to worker k mod factor_streams)
+    while the batches already factored are solved in order on one more
+    stream.  At most factor_streams + 1 batches hold factors at a time: a
+    worker starts batch k once batch k - factor_streams - 1 is solved."""
+
+    def __init__(self, factor_streams: int = 1):
         torch = helm._torch()
-        self.s_factor = torch.cuda.Stream()
+        if factor_streams < 1:
+            raise ValueError("factor_streams must be >= 1")
+        self.nf = int(factor_streams)
+        self.s_factor = [torch.cuda.Stream() for _ in range(self.nf)]
         self.s_solve = torch.cuda.Stream()
 
-    def _factor(self, b: Batch):
-        return helm.factor_batch(b.grids, b.ms, b.omegas, b.precision, stream=self.s_factor)
+    def _factor(self, b: Batch, j: int):
+        return helm.factor_batch(b.grids, b.ms, b.omegas, b.precision, stream=self.s_factor[j])
 
     def _solve(self, b: Batch, Fs):
         return helm.solve_batch(Fs, b.Bs, tol=b.tol, stream=self.s_solve, out=b.out)
@@ -51,36 +61,55 @@ class Pipeline:
         """Factor and solve every batch; returns [(Xs, infos)] in order."""
         torch = helm._torch()
         torch.cuda.current_stream().synchronize()   # inputs written on the caller's stream
-        results = [None] * len(batches)
-        if not batches:
+        n = len(batches)
+        results = [None] * n
+        if not n:
             return results
-        Fs = self._factor(batches[0])
-        for k in range(len(batches)):
-            nxt, err = {}, []
+        facs = [None] * n
+        ready = [threading.Event() for _ in range(n)]
+        solved = [threading.Event() for _ in range(n)]
+        stop = threading.Event()
+        err = []
 
-            def factor_next():
+        def worker(j):
+            for k in range(j, n, self.nf):
+                if k - self.nf - 1 >= 0:
+                    solved[k - self.nf - 1].wait()
+                if stop.is_set():
+                    ready[k].set()
+                    continue
                 try:
-                    if k + 1 < len(batches):
-                        nxt["F"] = self._factor(batches[k + 1])
+                    facs[k] = self._factor(batches[k], j)
                 except BaseException as e:   # re-raised on the calling thread
                     err.append(e)
+                    stop.set()
+                ready[k].set()
 
-            def solve_this():
-                try:
-                    results[k] = self._solve(batches[k], Fs)
-                except BaseException as e:
-                    err.append(e)
-
-            ta = threading.Thread(target=factor_next)
-            ta.start()
-            solve_this()
-            ta.join()
-            self.s_solve.synchronize()
-            for F in Fs:
-                F.close()
-            if err:
-                for F in nxt.get("F", []):
+        threads = [threading.Thread(target=worker, args=(j,)) for j in range(self.nf)]
+        for t in threads:
+            t.start()
+        try:
+            for k in range(n):
+                ready[k].wait()
+                if err or facs[k] is None:
+                    break
+                results[k] = self._solve(batches[k], facs[k])
+                self.s_solve.synchronize()
+                for F in facs[k]:
                     F.close()
-                raise err[0]
-            Fs = nxt.get("F")
+                facs[k] = None
+                solved[k].set()
+        except BaseException as e:
+            err.append(e)
+        finally:
+            stop.set()
+            for ev in solved:
+                ev.set()
+            for t in threads:
+                t.join()
+            for Fs in facs:
+                for F in Fs or []:
+                    F.close()
+        if err:
+            raise err[0]
         return results

@@ -1,8 +1,9 @@
-"""GPU: two batches in flight give bitwise the serial results.
+"""GPU: batches in flight give bitwise the serial results.
 
-The pipeline factors batch k+1 on one stream while batch k is solved on
-another; the arithmetic of each batch is unchanged, so every solution must
-equal the one from factor_batch + solve_batch, and match the oracle."""
+The pipeline factors later batches (one or several side by side, each on
+its own stream) while batch k is solved on another; the arithmetic of each
+batch is unchanged, so every solution must equal the one from factor_batch +
+solve_batch, and match the oracle."""
 import numpy as np
 import pytest
 
@@ -22,8 +23,8 @@ def helm():
     return h
 
 
-@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
-def test_pipeline_equals_serial(helm, precision):
+@pytest.mark.parametrize("precision,factor_streams", [("fp32_ir", 1), ("fp64", 1), ("fp32_ir", 2), ("fp64", 3)])
+def test_pipeline_equals_serial(helm, precision, factor_streams):
     from paper_2301_10762_amd.pipeline import Batch, Pipeline
     rng = np.random.default_rng(5)
     nx, nz, hx, hz = 70, 37, 0.03, 0.03
@@ -40,8 +41,8 @@ def test_pipeline_equals_serial(helm, precision):
         for F in Fs:
             F.close()
         refs.append([X.cpu().numpy() for X in Xs])
-    print(f"pipeline {precision}: 4 batches of 3 systems {nx}x{nz}", flush=True)
-    out = Pipeline().run(batches)
+    print(f"pipeline {precision}, {factor_streams} factor streams: 4 batches of 3 systems {nx}x{nz}", flush=True)
+    out = Pipeline(factor_streams).run(batches)
     og = oracle.Grid(nx, nz, hx, hz)
     for k, (Xs, infos) in enumerate(out):
         for q, (X, info) in enumerate(zip(Xs, infos)):
