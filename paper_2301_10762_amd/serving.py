@@ -130,11 +130,27 @@ class HelmBackend:
         torch.cuda.synchronize()
 
 
+def _grid_key(grid):
+    return tuple(getattr(grid, a, None) for a in ("nx", "nz", "hx", "hz"))
+
+
 class Server:
+    """Continuous batching.  A batch holds requests on one grid: the oldest
+    queued request leads it and later requests on the same grid join it in
+    arrival order, passing requests on other grids (a batch's launch chain
+    is as long as its largest system, so a mixed batch makes every request
+    wait for the largest).  A request passed max_overtakes times is not
+    passed again (max_overtakes = 0: first in, first out, one grid per
+    batch; None: first in, first out with grids mixed in a batch)."""
+
     def __init__(self, backend, hbm_budget: int, max_chains: int = MAX_CHAINS, resident: bool = False,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, max_overtakes=4):
         if max_chains < 1 or max_chains > MAX_CHAINS:
             raise ValueError(f"max_chains must be in [1, {MAX_CHAINS}]")
+        if max_overtakes is not None and max_overtakes < 0:
+            raise ValueError("max_overtakes must be >= 0 or None")
+        self.max_overtakes = None if max_overtakes is None else int(max_overtakes)
+        self.overtaken = {}              # rid -> times passed by a later request
         self.be = backend
         self.budget = int(hbm_budget)
         self.max_chains = max_chains
@@ -177,13 +193,25 @@ class Server:
         self.queue.append(req)
 
     def admit(self):
-        """Requests of the next batch, FIFO, within the chain and memory
-        limits (memory of a batch still in flight counts against the budget,
-        and the resident factors it uses are not evicted)."""
+        """Requests of the next batch: the oldest request and the later ones
+        on its grid, in arrival order, within the chain and memory limits
+        (memory of a batch still in flight counts against the budget, and
+        the resident factors it uses are not evicted).  The scan stops at the
+        first request that does not fit, and at a request on another grid
+        that has been passed max_overtakes times."""
         batch, chains, used = [], 0, self.inflight_bytes
         keep = set(self.inflight_keys)
-        while self.queue:
-            req = self.queue[0]
+        if not self.queue:
+            return batch
+        gk = _grid_key(self.queue[0].grid)
+        taken = []
+        for idx, req in enumerate(self.queue):
+            if self.max_overtakes is None:
+                pass
+            elif _grid_key(req.grid) != gk:
+                if self.overtaken.get(req.rid, 0) >= self.max_overtakes:
+                    break
+                continue
             if chains + len(req.omegas) > self.max_chains:
                 break
             keys = {(req.model_key, float(w)) for w in req.omegas} if req.model_key is not None else set()
@@ -191,11 +219,20 @@ class Server:
             need = self._need(req, hit)
             if not self._evict(used + need, keep | hit):
                 break
-            self.queue.popleft()
             keep |= hit
             batch.append(req)
+            taken.append(idx)
             chains += len(req.omegas)
             used += need
+        if taken:
+            tset = set(taken)
+            for idx in range(taken[-1]):
+                if idx not in tset:
+                    rid = self.queue[idx].rid
+                    self.overtaken[rid] = self.overtaken.get(rid, 0) + 1
+            self.queue = collections.deque(r for i, r in enumerate(self.queue) if i not in tset)
+            for r in batch:
+                self.overtaken.pop(r.rid, None)
         return batch
 
     def _begin(self, batch) -> "_Prepared":
@@ -368,6 +405,9 @@ def main(argv=None):
     p.add_argument("--budget-gb", type=float, default=64.0)
     p.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     p.add_argument("--max-chains", type=int, default=MAX_CHAINS)
+    p.add_argument("--max-overtakes", type=int, default=4,
+                   help="times a request may be passed by later requests on the batch's grid (-1: grids mixed, "
+                        "first in, first out)")
     p.add_argument("--serial", action="store_true",
                    help="one batch at a time (default: the next batch is factored while the current is solved)")
     args = p.parse_args(argv)
@@ -387,7 +427,8 @@ def main(argv=None):
     # warm-up: one small request through the whole path
     warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",
                         dtype=torch.float64), [1.0], [5])
-    srv = Server(be, int(args.budget_gb * 2**30), args.max_chains)
+    srv = Server(be, int(args.budget_gb * 2**30), args.max_chains,
+                 max_overtakes=None if args.max_overtakes < 0 else args.max_overtakes)
     srv.submit(warm)
     srv.step()
     torch.cuda.synchronize()
@@ -396,6 +437,8 @@ def main(argv=None):
     out = summary(res, reqs)
     out.update({"precision": args.precision, "max_relres": worst, "budget_gb": args.budget_gb,
                 "schedule": "serial" if args.serial else "pipelined",
+                "admission": "mixed grids, first in first out" if args.max_overtakes < 0 else
+                             f"one grid per batch, a request passed at most {args.max_overtakes} times",
                 "rate": args.rate, "sizes": sorted({q.n for q in stream})})
     print(json.dumps(out), flush=True)
     srv.close()

@@ -57,7 +57,7 @@ def test_serving_alone_equals_mixed_and_matches_oracle(helm, precision):
         assert len(res) == 1
         alone[rid] = [x.clone() for x in res[0].X]
     be = SV.HelmBackend(precision, 1e-10)
-    srv = SV.Server(be, 1 << 36)
+    srv = SV.Server(be, 1 << 36, max_overtakes=None)       # every grid in one batch
     models = {}
     for rid, spec in enumerate(SPECS):
         req, models[rid] = make_request(SV, helm, rid, *spec)

@@ -118,15 +118,53 @@ def test_memory_budget_limits_batches_and_rejects_oversize():
 
 
 def test_head_of_line_request_is_not_overtaken():
+    """Strict first in, first out (max_overtakes = 0)."""
     be = FakeBackend()
     small, big = per_request_bytes(10, 4), per_request_bytes(20, 4)
-    srv = SV.Server(be, big + small // 2, max_chains=16)
+    srv = SV.Server(be, big + small // 2, max_chains=16, max_overtakes=0)
     srv.submit(req(0, n=10))
     srv.submit(req(1, n=20))
     srv.submit(req(2, n=10))
     assert [x.rid for x in srv.step()] == [0]       # 1 does not fit beside 0; 2 must wait behind 1
     assert [x.rid for x in srv.step()] == [1]
     assert [x.rid for x in srv.step()] == [2]
+
+
+def test_batches_hold_one_grid_and_pass_other_grids():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16)
+    for rid, n in enumerate((10, 20, 10, 20, 10)):
+        srv.submit(req(rid, n=n))
+    assert [x.rid for x in srv.step()] == [0, 2, 4]
+    assert [x.rid for x in srv.step()] == [1, 3]
+    assert srv.step() == [] and be.live() == 0
+
+
+def test_passing_is_bounded():
+    """A request already passed max_overtakes times stops the scan; the
+    count grows each time a later request joins a batch ahead of it."""
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16, max_overtakes=2)
+    for rid, n in enumerate((10, 20, 10)):
+        srv.submit(req(rid, n=n))
+    srv.overtaken[1] = 2
+    assert [x.rid for x in srv.step()] == [0]
+    assert [x.rid for x in srv.step()] == [1]
+    assert [x.rid for x in srv.step()] == [2]
+    srv2 = SV.Server(FakeBackend(), 1 << 40, max_chains=16, max_overtakes=2)
+    for rid, n in enumerate((10, 20, 10)):
+        srv2.submit(req(rid, n=n))
+    assert [x.rid for x in srv2.step()] == [0, 2]
+    assert srv2.overtaken == {1: 1}
+    assert [x.rid for x in srv2.step()] == [1] and srv2.overtaken == {}
+
+
+def test_mixed_grid_fifo_mode():
+    be = FakeBackend()
+    srv = SV.Server(be, 1 << 40, max_chains=16, max_overtakes=None)
+    for rid, n in enumerate((10, 20, 10)):
+        srv.submit(req(rid, n=n))
+    assert [x.rid for x in srv.step()] == [0, 1, 2]
 
 
 def test_resident_factors_are_reused_and_evicted_lru():
