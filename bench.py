@@ -542,6 +542,9 @@ def main():
         extras["fwi_201"] = fwi_extra(helm, I)
         # the Hessian systems of several training models in lockstep
         extras["pcg_batch_201"] = pcg_batch_extra(helm, I, w4, G4)
+        # the serving workload: 96 Poisson arrivals at 200 requests/s
+        from paper_2301_10762_amd import serving as SV
+        extras["serving_c5"] = SV.run_c5(requests=96, rate=200.0, precision=prec)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -397,6 +397,42 @@ def summary(results, requests) -> dict:
             "batches": len({r.batch for r in results})}
 
 
+def run_c5(requests: int = 32, rate: float = 200.0, seed: int = 0, budget_gb: float = 64.0,
+           precision: str = "fp32_ir", max_chains: int = MAX_CHAINS, serial: bool = False, max_overtakes=4) -> dict:
+    """The serving workload (Poisson arrivals of single-frequency requests,
+    n in {101, 201, 301, 401}, 8 to 128 sources, each with its own seeded
+    layered model) through the server; returns the summary."""
+    import torch
+    from . import helm
+    from . import inputs as I
+
+    stream = I.serving_stream(requests, rate, seed)
+    reqs = []
+    for q in stream:
+        m, omega, src = I.request_inputs(q)
+        g = helm.Grid(q.n, q.n, I.H_KM, I.H_KM)
+        reqs.append(ServeRequest(q.rid, g, torch.as_tensor(m.reshape(-1), device="cuda"), [omega], list(src),
+                                 arrival=q.t_arrival))
+    be = HelmBackend(precision, 1e-10, stream=torch.cuda.Stream(), solve_stream=torch.cuda.Stream())
+    srv = Server(be, int(budget_gb * 2**30), max_chains, max_overtakes=max_overtakes)
+    # warm-up: one small request through the whole path
+    warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",
+                        dtype=torch.float64), [1.0], [5])
+    srv.submit(warm)
+    srv.step()
+    torch.cuda.synchronize()
+    res = run_stream(srv, reqs, pipelined=not serial)
+    worst = max(i.max_relres for r in res for i in r.infos)
+    out = summary(res, reqs)
+    out.update({"precision": precision, "max_relres": worst, "budget_gb": budget_gb,
+                "schedule": "serial" if serial else "pipelined",
+                "admission": "mixed grids, first in first out" if max_overtakes is None else
+                             f"one grid per batch, a request passed at most {max_overtakes} times",
+                "rate": rate, "sizes": sorted({q.n for q in stream})})
+    srv.close()
+    return out
+
+
 def main(argv=None):
     p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     p.add_argument("--requests", type=int, default=32)
@@ -411,37 +447,9 @@ def main(argv=None):
     p.add_argument("--serial", action="store_true",
                    help="one batch at a time (default: the next batch is factored while the current is solved)")
     args = p.parse_args(argv)
-
-    import torch
-    from . import helm
-    from . import inputs as I
-
-    stream = I.serving_stream(args.requests, args.rate, args.seed)
-    reqs = []
-    for q in stream:
-        m, omega, src = I.request_inputs(q)
-        g = helm.Grid(q.n, q.n, I.H_KM, I.H_KM)
-        reqs.append(ServeRequest(q.rid, g, torch.as_tensor(m.reshape(-1), device="cuda"), [omega], list(src),
-                                 arrival=q.t_arrival))
-    be = HelmBackend(args.precision, 1e-10, stream=torch.cuda.Stream(), solve_stream=torch.cuda.Stream())
-    # warm-up: one small request through the whole path
-    warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",
-                        dtype=torch.float64), [1.0], [5])
-    srv = Server(be, int(args.budget_gb * 2**30), args.max_chains,
-                 max_overtakes=None if args.max_overtakes < 0 else args.max_overtakes)
-    srv.submit(warm)
-    srv.step()
-    torch.cuda.synchronize()
-    res = run_stream(srv, reqs, pipelined=not args.serial)
-    worst = max(i.max_relres for r in res for i in r.infos)
-    out = summary(res, reqs)
-    out.update({"precision": args.precision, "max_relres": worst, "budget_gb": args.budget_gb,
-                "schedule": "serial" if args.serial else "pipelined",
-                "admission": "mixed grids, first in first out" if args.max_overtakes < 0 else
-                             f"one grid per batch, a request passed at most {args.max_overtakes} times",
-                "rate": args.rate, "sizes": sorted({q.n for q in stream})})
+    out = run_c5(args.requests, args.rate, args.seed, args.budget_gb, args.precision, args.max_chains, args.serial,
+                 None if args.max_overtakes < 0 else args.max_overtakes)
     print(json.dumps(out), flush=True)
-    srv.close()
     return 0
 
 
