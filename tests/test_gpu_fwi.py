@@ -114,3 +114,18 @@ def test_fwi_rejects_bad_input(helm):
         helm.fwi(G, -w.m, w.omegas, d, w.sources, w.receivers)
     with pytest.raises(helm.HelmError):
         helm.fwi(G, w.m, w.omegas, d, w.sources, w.receivers, c1=0.5, c2=0.4)
+
+
+@pytest.mark.slow
+def test_fwi_c2_size_matches_oracle(helm):
+    """201^2, 3 frequencies, 30 sources, 100 receivers (the benchmark's FWI
+    configuration): four L-BFGS iterations, step by step against the
+    oracle's own run."""
+    print("fwi 201^2 x 3 frequencies x 30 sources", flush=True)
+    w = I.config_c2()
+    g = oracle.Grid.of(w)
+    d = oracle.synth_data(g, w.m_true, w.omegas, w.sources, w.receivers)
+    kw = dict(memory=5, max_iters=4, gtol=1e-8)
+    mo, oinfo = oracle.fwi(g, w.m, w.omegas, d, w.sources, w.receivers, 1e-6, 1e-8, **kw)
+    m, info = helm.fwi(helm.Grid.of(w), w.m, w.omegas, d, w.sources, w.receivers, 1e-6, 1e-8, tol=1e-11, **kw)
+    _compare(info, oinfo, m, mo, 1e-9, 1e-8)

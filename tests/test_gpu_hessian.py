@@ -269,3 +269,27 @@ def test_pcg_batch_equals_single(helm):
     finally:
         for H in ctx:
             H.close()
+
+
+@pytest.mark.slow
+def test_pcg_c4_size_true_residual(helm):
+    """The benchmark's Hessian system (201^2, 4 frequencies, 32 sources, P2,
+    rtol 1e-6, FP64 context): the oracle's own product with the returned rho
+    leaves a residual within the tolerance."""
+    print("pcg 201^2 true residual", flush=True)
+    w = I.config_c4()
+    g = oracle.Grid.of(w)
+    d = oracle.synth_data(g, w.m_true, w.omegas, w.sources, w.receivers)
+    m_fwi = w.m_true + 0.1 * (w.m - w.m_true)
+    b = w.m_true - m_fwi
+    alpha, mu = 1e-4, 1e-8
+    Hc = helm.Hessian(helm.Grid.of(w), m_fwi, w.omegas, w.sources, w.receivers, d, alpha, mu, tol=1e-10)
+    try:
+        rho, it, rr, _ = Hc.pcg(b, prec_alpha=alpha, prec_mu=mu, rtol=1e-6, maxit=300)
+    finally:
+        Hc.close()
+    rho = rho.cpu().numpy()
+    H = lambda x: oracle.hvp(g, m_fwi, w.omegas, d, w.sources, w.receivers, [x], alpha, mu)[0]
+    r0 = np.linalg.norm(b - H(np.ones(g.N)))
+    assert rr <= 1e-6
+    assert np.linalg.norm(b - H(rho)) <= 2e-6 * r0
