@@ -378,6 +378,7 @@ def main():
         dirs = torch.as_tensor(np.stack(w4.directions), device="cuda")
         print(json.dumps({"hessian_201": hessian_extra(helm, I, w4, G4, dirs),
                           "upper_grad_201": bilevel_extra(helm, I, w4, G4), "fwi_201": fwi_extra(helm, I),
+                          "fwi_201_fp32ir": fwi_extra(helm, I, precision="fp32_ir"),
                           "pcg_batch_201": pcg_batch_extra(helm, I, w4, G4)}),
               flush=True)
         return
@@ -538,8 +539,10 @@ def main():
         # the upper-level gradient of one training model with 100 sensors
         # between nodes (Algorithm "Derivative of psi")
         extras["upper_grad_201"] = bilevel_extra(helm, I, w4, G4)
-        # the lower-level FWI (L-BFGS) at the 201^2 configuration
+        # the lower-level FWI (L-BFGS) at the 201^2 configuration, both
+        # precisions of the factors
         extras["fwi_201"] = fwi_extra(helm, I)
+        extras["fwi_201_fp32ir"] = fwi_extra(helm, I, precision="fp32_ir")
         # the Hessian systems of several training models in lockstep
         extras["pcg_batch_201"] = pcg_batch_extra(helm, I, w4, G4)
         # the serving workload: 96 Poisson arrivals at 200 requests/s
