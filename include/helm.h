@@ -308,7 +308,7 @@ typedef struct {
  * nodes src_host or points src_xz_host and receiver nodes rec_host or
  * sensor points rec_xz_host (exactly one of each pair non-NULL; see
  * helm_hess_create_at).  m_dev: the start model on entry, the result on
- * return.  phi_hist_host (optional): max_iters + 1 doubles, phi at every
+ * return (after an error return, the last accepted iterate).  phi_hist_host (optional): max_iters + 1 doubles, phi at every
  * iterate.  The statuses are results, not errors.  Synchronises `stream`. */
 int helm_fwi(const helm_grid* grid, double* m_dev, int32_t n_omega, const double* omegas_host,
              const double* dobs_dev, int32_t S, const int32_t* src_host, const double* src_xz_host,

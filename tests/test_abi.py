@@ -20,7 +20,10 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("helm_factor", "helm_solve", "helm_adjoint_solve", "helm_misfit_grad", "helm_gn_hvp",
-                     "helm_factor_destroy", "helm_factor_bytes", "helm_last_error"):
+                     "helm_factor_destroy", "helm_factor_bytes", "helm_last_error", "helm_hess_create",
+                     "helm_hess_create_at", "helm_hess_apply", "helm_hess_pcg", "helm_hess_pcg_batch",
+                     "helm_hess_destroy", "helm_gamma_solve", "helm_upper_grad", "helm_restrict",
+                     "helm_point_sources", "helm_fwi"):
         assert required in names
 
 
