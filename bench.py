@@ -545,9 +545,13 @@ def main():
         extras["fwi_201_fp32ir"] = fwi_extra(helm, I, precision="fp32_ir")
         # the Hessian systems of several training models in lockstep
         extras["pcg_batch_201"] = pcg_batch_extra(helm, I, w4, G4)
-        # the serving workload: 96 Poisson arrivals at 200 requests/s
+        # the serving workload: 192 Poisson arrivals at 200 requests/s, three
+        # batches side by side (lanes) and, for comparison, two in flight
+        # (pipelined); and the lanes at 150 requests/s
         from paper_2301_10762_amd import serving as SV
-        extras["serving_c5"] = SV.run_c5(requests=96, rate=200.0, precision=prec)
+        extras["serving_c5"] = SV.run_c5(requests=192, rate=200.0, precision=prec, lanes=3)
+        extras["serving_c5_pipelined"] = SV.run_c5(requests=192, rate=200.0, precision=prec)
+        extras["serving_150"] = SV.run_c5(requests=192, rate=150.0, precision=prec, lanes=3)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -9,7 +9,11 @@ factored together (one set of launches for all their chains) and solved
 together, so requests that arrive while a batch runs join the next one.
 By default the next batch is admitted and factored while the current one is
 solved (two batches in flight, on two streams); its memory then counts
-against the budget together with the batch in flight.
+against the budget together with the batch in flight.  With lanes = L > 1
+(`run_lanes`), L host threads each admit a batch, factor it and solve it on
+a stream of their own, so batches on different grids run side by side and
+a lane that finishes admits the next batch at once; the memory of every
+batch in flight counts against the budget.
 This is the paper's observation that the solves for different models are
 independent (Appendix, "Parallelisation"), applied to a request stream.
 
@@ -81,6 +85,7 @@ class _Prepared:
     keys: set = dataclasses.field(default_factory=set)      # resident factors used
     bytes: int = 0
     Bs: dict = None
+    be: object = None                                        # backend (lane) that runs the batch
 
 
 class HelmBackend:
@@ -96,6 +101,24 @@ class HelmBackend:
         self.stream = stream
         self.solve_stream = solve_stream if solve_stream is not None else stream
         self.factorisations = 0
+        self.own = None          # a lane's stream: sync() waits for it alone
+
+    def lane(self):
+        """A backend for one lane of run_lanes: factors, solves and its
+        right-hand sides on one stream of its own, and sync() waiting for
+        that stream only (a device-wide synchronisation would make a lane
+        wait for the others' batches)."""
+        import torch
+        s = torch.cuda.Stream()
+        b = HelmBackend(self.precision, self.tol, stream=s, solve_stream=s)
+        b.own = s
+        return b
+
+    def stream_context(self):
+        """Context in which the lane's tensors are made on its stream."""
+        import contextlib
+        import torch
+        return torch.cuda.stream(self.own) if self.own is not None else contextlib.nullcontext()
 
     def factor_bytes(self, grid) -> int:
         return self.helm.factor_bytes(grid, self.precision)
@@ -127,7 +150,10 @@ class HelmBackend:
 
     def sync(self):
         import torch
-        torch.cuda.synchronize()
+        if self.own is not None:
+            self.own.synchronize()
+        else:
+            torch.cuda.synchronize()
 
 
 def _grid_key(grid):
@@ -161,8 +187,9 @@ class Server:
         self.cache_bytes = 0
         self.batches = 0
         self.rejected = []
-        self.inflight_bytes = 0          # a factored batch waiting for its solves (pipelined runs)
+        self.inflight_bytes = 0          # batches admitted and not finished (pipelined and lane runs)
         self.inflight_keys = set()
+        self._inflight = []              # lane runs: the batches in flight
 
     # -- memory accounting --------------------------------------------------
     def _need(self, req: ServeRequest, reuse) -> int:
@@ -235,12 +262,24 @@ class Server:
                 self.overtaken.pop(r.rid, None)
         return batch
 
-    def _begin(self, batch) -> "_Prepared":
+    def _track(self, prep: "_Prepared", add: bool):
+        """Count a lane's batch in flight (or no longer): its memory and the
+        resident factors it uses are protected until it finishes."""
+        if add:
+            self._inflight.append(prep)
+        else:
+            self._inflight.remove(prep)
+        self.inflight_bytes = sum(p.bytes for p in self._inflight)
+        self.inflight_keys = set().union(*[p.keys for p in self._inflight])
+
+    def _begin(self, batch, be=None) -> "_Prepared":
         """Bookkeeping of an admitted batch: resident factors it reuses, the
-        systems to factor, its right-hand sides (host thread of the caller)."""
+        systems to factor, its right-hand sides (host thread of the caller;
+        `be`: the lane that runs it, by default the server's backend)."""
         prep = _Prepared(batch, self.clock())
+        prep.be = be if be is not None else self.be
         for r, req in enumerate(batch):
-            m = self.be.model(req)
+            m = prep.be.model(req)
             for q, w in enumerate(req.omegas):
                 key = (req.model_key, float(w))
                 if req.model_key is not None and key in self.cache:
@@ -253,19 +292,19 @@ class Server:
                     prep.oms.append(float(w))
                     prep.slots.append((r, q))
             prep.bytes += self._need(req, prep.keys)
-        prep.Bs = {r: self.be.rhs(req) for r, req in enumerate(batch)}
-        self.be.sync()
+        prep.Bs = {r: prep.be.rhs(req) for r, req in enumerate(batch)}
+        prep.be.sync()
         return prep
 
     def _factor(self, prep: "_Prepared"):
         if prep.grids:
-            for slot, F in zip(prep.slots, self.be.factor(prep.grids, prep.ms, prep.oms)):
+            for slot, F in zip(prep.slots, prep.be.factor(prep.grids, prep.ms, prep.oms)):
                 prep.Fs[slot] = F
 
     def _solve(self, prep: "_Prepared"):
         order = [(r, q) for r, req in enumerate(prep.batch) for q in range(len(req.omegas))]
-        X, infos = self.be.solve([prep.Fs[k] for k in order], [prep.Bs[k[0]] for k in order])
-        self.be.sync()
+        X, infos = prep.be.solve([prep.Fs[k] for k in order], [prep.Bs[k[0]] for k in order])
+        prep.be.sync()
         return X, infos
 
     def _finish(self, prep: "_Prepared", X, infos):
@@ -376,6 +415,87 @@ def run_stream(server: Server, requests, realtime: bool = True, pipelined: bool 
     return results
 
 
+def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
+    """Feed `requests` (sorted by arrival) to the server and run `lanes`
+    batches side by side until all are done; results in completion order.
+
+    Each lane is a host thread with a backend of its own (backend.lane():
+    one stream).  A free lane admits the next batch (the server's admission
+    rules, with the memory of every batch in flight counted against the
+    budget), factors and solves it, and hands the results back.  Admission,
+    the resident-factor cache and the results are shared under one lock; the
+    factorisations and solves run outside it (the library calls release the
+    interpreter lock).  A lane with nothing to admit waits until a batch
+    finishes or the next request arrives; it stops when no request is
+    pending or queued."""
+    if lanes < 1:
+        raise ValueError("lanes must be >= 1")
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    results, err = [], []
+    cv = threading.Condition()
+    t0 = server.clock()
+    backends = [server.be.lane() for _ in range(lanes)]
+
+    def arrivals():
+        now = server.clock() - t0 if realtime else math.inf
+        while pending and pending[0].arrival <= now:
+            server.submit(pending.popleft())
+
+    def lane(be):
+        ctx = be.stream_context() if hasattr(be, "stream_context") else None
+        if ctx is not None:
+            ctx.__enter__()
+        try:
+            while True:
+                with cv:
+                    while True:
+                        if err:
+                            return
+                        arrivals()
+                        batch = server.admit() if server.queue else []
+                        if batch:
+                            prep = server._begin(batch, be)
+                            server._track(prep, True)
+                            break
+                        if not pending and not server.queue:
+                            return
+                        wait = None
+                        if pending and realtime:
+                            wait = max(0.0, pending[0].arrival - (server.clock() - t0))
+                        cv.wait(wait)
+                try:
+                    server._factor(prep)
+                    X, infos = server._solve(prep)
+                except BaseException as e:      # re-raised on the calling thread
+                    with cv:
+                        err.append(e)
+                        server._track(prep, False)
+                        for F in prep.Fs.values():
+                            if not any(F is c[0] for c in server.cache.values()):
+                                server.be.release(F)
+                        cv.notify_all()
+                    return
+                with cv:
+                    server._track(prep, False)
+                    for res in server._finish(prep, X, infos):
+                        res.start -= t0
+                        res.done -= t0
+                        results.append(res)
+                    cv.notify_all()
+        finally:
+            if ctx is not None:
+                ctx.__exit__(None, None, None)
+
+    threads = [threading.Thread(target=lane, args=(be,)) for be in backends]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if err:
+        raise err[0]
+    return results
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -386,22 +506,37 @@ def percentile(xs, q):
 
 
 def summary(results, requests) -> dict:
+    """Latency percentiles and rates of a finished stream.  The offered and
+    served rates count the same n - 1 intervals: between the first and last
+    arrival, and between the first and last completion, so the drain of the
+    last requests does not count against a server that keeps up.  The queue
+    is stable when the service keeps pace (served >= 0.95 offered);
+    latency_growth (median latency of the last quarter of arrivals over that
+    of the first quarter) shows a queue that builds up."""
     lat = [r.latency for r in results]
+    n = len(results)
     span = max(r.done for r in results) - min(q.arrival for q in requests)
     solves = sum(q.S * len(q.omegas) for q in requests)
-    offered = len(requests) / max(1e-12, max(q.arrival for q in requests))
-    served = len(results) / span
-    return {"requests": len(results), "p50_ms": percentile(lat, 0.5) * 1e3, "p99_ms": percentile(lat, 0.99) * 1e3,
+    arr = sorted(q.arrival for q in requests)
+    done = sorted(r.done for r in results)
+    offered = (len(arr) - 1) / max(1e-12, arr[-1] - arr[0]) if len(arr) > 1 else 0.0
+    served = (n - 1) / max(1e-12, done[-1] - done[0]) if n > 1 else 0.0
+    by_arrival = [r.latency for r in sorted(results, key=lambda r: r.arrival)]
+    q = max(1, n // 4)
+    growth = percentile(by_arrival[-q:], 0.5) / max(1e-12, percentile(by_arrival[:q], 0.5))
+    return {"requests": n, "p50_ms": percentile(lat, 0.5) * 1e3, "p99_ms": percentile(lat, 0.99) * 1e3,
             "max_ms": max(lat) * 1e3, "solves_per_s": solves / span, "offered_req_per_s": offered,
-            "served_req_per_s": served, "stable": served >= 0.95 * offered,
+            "served_req_per_s": served, "stable": served >= 0.95 * offered, "latency_growth": growth,
             "batches": len({r.batch for r in results})}
 
 
 def run_c5(requests: int = 32, rate: float = 200.0, seed: int = 0, budget_gb: float = 64.0,
-           precision: str = "fp32_ir", max_chains: int = MAX_CHAINS, serial: bool = False, max_overtakes=4) -> dict:
+           precision: str = "fp32_ir", max_chains: int = MAX_CHAINS, serial: bool = False, max_overtakes=4,
+           lanes: int = 0) -> dict:
     """The serving workload (Poisson arrivals of single-frequency requests,
     n in {101, 201, 301, 401}, 8 to 128 sources, each with its own seeded
-    layered model) through the server; returns the summary."""
+    layered model) through the server; returns the summary.  lanes > 0:
+    run_lanes with that many lanes (else the pipelined or serial loop)."""
     import torch
     from . import helm
     from . import inputs as I
@@ -421,11 +556,16 @@ def run_c5(requests: int = 32, rate: float = 200.0, seed: int = 0, budget_gb: fl
     srv.submit(warm)
     srv.step()
     torch.cuda.synchronize()
-    res = run_stream(srv, reqs, pipelined=not serial)
+    if lanes > 0:
+        res = run_lanes(srv, reqs, lanes)
+        sched = f"{lanes} lanes"
+    else:
+        res = run_stream(srv, reqs, pipelined=not serial)
+        sched = "serial" if serial else "pipelined"
     worst = max(i.max_relres for r in res for i in r.infos)
     out = summary(res, reqs)
     out.update({"precision": precision, "max_relres": worst, "budget_gb": budget_gb,
-                "schedule": "serial" if serial else "pipelined",
+                "schedule": sched,
                 "admission": "mixed grids, first in first out" if max_overtakes is None else
                              f"one grid per batch, a request passed at most {max_overtakes} times",
                 "rate": rate, "sizes": sorted({q.n for q in stream})})
@@ -446,9 +586,12 @@ def main(argv=None):
                         "first in, first out)")
     p.add_argument("--serial", action="store_true",
                    help="one batch at a time (default: the next batch is factored while the current is solved)")
+    p.add_argument("--lanes", type=int, default=0,
+                   help="batches run side by side, each factored and solved on a stream of its own (0: the "
+                        "pipelined or serial loop)")
     args = p.parse_args(argv)
     out = run_c5(args.requests, args.rate, args.seed, args.budget_gb, args.precision, args.max_chains, args.serial,
-                 None if args.max_overtakes < 0 else args.max_overtakes)
+                 None if args.max_overtakes < 0 else args.max_overtakes, args.lanes)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -151,3 +151,31 @@ def test_pipelined_serving_equals_serial(helm):
         assert max(i.max_relres for i in r.infos) <= 1e-10
         for x, y in zip(r.X, ser[r.rid].X):
             assert torch.equal(x, y), r.rid
+
+
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_lane_serving_equals_serial(helm, lanes):
+    """Batches run side by side on lanes (one stream and host thread each)
+    give bitwise the results of the serial schedule, with resident factors
+    reused across lanes."""
+    from paper_2301_10762_amd import serving as SV
+
+    def reqs():
+        out = [make_request(SV, helm, rid, *spec, key=("m", rid))[0] for rid, spec in enumerate(SPECS)]
+        # the same models again: resident factors made by one lane serve another
+        out += [make_request(SV, helm, 10 + rid, *spec, key=("m", rid))[0] for rid, spec in enumerate(SPECS)]
+        return out
+    srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36, max_chains=3)
+    ser = {r.rid: r for r in SV.run_stream(srv, reqs(), realtime=False)}
+    srv.close()
+    srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36, max_chains=3, resident=True)
+    print(f"lane serving, {lanes} lanes", flush=True)
+    got = SV.run_lanes(srv, reqs(), lanes=lanes, realtime=False)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in got) == sorted(ser) and srv.batches >= 2
+    assert srv.inflight_bytes == 0 and not srv.inflight_keys
+    for r in got:
+        assert max(i.max_relres for i in r.infos) <= 1e-10
+        for x, y in zip(r.X, ser[r.rid].X):
+            assert torch.equal(x, y), r.rid
+    srv.close()

@@ -239,3 +239,113 @@ def test_pipelined_admission_counts_the_batch_in_flight():
     assert sum(sizes) == 5 and max(sizes) <= 2
     assert be.max_live <= 2                         # never a second batch beside the one in flight
     assert be.live() == 0
+
+
+class LaneFake(FakeBackend):
+    """Stand-in whose solves take a little time and record how many run at
+    once; every lane shares it."""
+
+    def __init__(self, delay=0.03):
+        super().__init__()
+        import threading
+        self.delay, self.busy, self.max_busy = delay, 0, 0
+        self.lock = threading.Lock()
+
+    def lane(self):
+        return self
+
+    def solve(self, Fs, Bs):
+        import time
+        with self.lock:
+            self.busy += 1
+            self.max_busy = max(self.max_busy, self.busy)
+        time.sleep(self.delay)
+        with self.lock:
+            self.busy -= 1
+        return super().solve(Fs, Bs)
+
+
+def test_lanes_run_batches_side_by_side():
+    """Two grids queued at once and two lanes: the two batches (one grid
+    each) are solved at the same time."""
+    be = LaneFake()
+    srv = SV.Server(be, 1 << 40, max_chains=16)
+    reqs = [req(r, n=10 + 5 * (r % 2), arrival=0.0) for r in range(8)]
+    res = SV.run_lanes(srv, reqs, lanes=2, realtime=False)
+    assert sorted(x.rid for x in res) == list(range(8))
+    assert be.max_busy == 2
+    for b in {x.batch for x in res}:
+        assert len({x.rid % 2 for x in res if x.batch == b}) == 1     # one grid per batch
+    assert srv.inflight_bytes == 0 and not srv.inflight_keys
+    assert be.live() == 0
+
+
+def test_lanes_serve_everything_without_leaks():
+    """Three lanes with resident factors: every request is served once,
+    factors are reused, and none is leaked or released twice."""
+    be = LaneFake(delay=0.005)
+    srv = SV.Server(be, 1 << 40, max_chains=4, resident=True)
+    reqs = [req(r, key=("k", r % 3), arrival=0.001 * r) for r in range(15)]
+    res = SV.run_lanes(srv, reqs, lanes=3, realtime=False)
+    assert sorted(x.rid for x in res) == list(range(15))
+    assert all(x.X[0][1] == ("B", x.rid) for x in res)
+    assert srv.inflight_bytes == 0 and not srv.inflight_keys
+    assert be.live() == len(srv.cache) == 3
+    srv.close()
+    assert be.live() == 0
+
+
+def test_lanes_admission_counts_every_batch_in_flight():
+    """With room for two requests in all, three lanes never hold more than
+    two requests' factors at once."""
+    be = LaneFake(delay=0.01)
+    one = per_request_bytes(10, 4)
+    srv = SV.Server(be, 2 * one + one // 2, max_chains=16)
+    reqs = [req(r, arrival=0.0) for r in range(7)]
+    res = SV.run_lanes(srv, reqs, lanes=3, realtime=False)
+    assert sorted(x.rid for x in res) == list(range(7))
+    assert be.max_live <= 2
+    assert be.live() == 0
+
+
+def test_lanes_realtime_waits_for_arrivals():
+    """Requests arriving over time are all served; none starts before it
+    arrives."""
+    be = LaneFake(delay=0.002)
+    srv = SV.Server(be, 1 << 40, max_chains=4)
+    reqs = [req(r, n=10 + 5 * (r % 3), arrival=0.004 * r) for r in range(10)]
+    res = SV.run_lanes(srv, reqs, lanes=2, realtime=True)
+    assert sorted(x.rid for x in res) == list(range(10))
+    assert all(x.start >= x.arrival - 1e-9 for x in res)
+    assert be.live() == 0
+
+
+def test_lanes_reraise_backend_errors_without_leaks():
+    class Failing(LaneFake):
+        def solve(self, Fs, Bs):
+            raise RuntimeError("device error")
+
+    be = Failing()
+    srv = SV.Server(be, 1 << 40, max_chains=2)
+    with pytest.raises(RuntimeError, match="device error"):
+        SV.run_lanes(srv, [req(r) for r in range(4)], lanes=2, realtime=False)
+    assert be.live() == 0
+    assert srv.inflight_bytes == 0
+
+
+def _res(rid, arrival, done):
+    return SV.ServeResult(rid, [], [], arrival, arrival, done, rid)
+
+
+def test_summary_rates_keep_pace_and_growing_queue():
+    """A server that finishes every request a fixed 50 ms after it arrives
+    keeps pace (served = offered, no latency growth); one that finishes a
+    request every 20 ms against arrivals every 10 ms does not."""
+    reqs = [req(r, arrival=0.01 * r) for r in range(40)]
+    s = SV.summary([_res(r, 0.01 * r, 0.01 * r + 0.05) for r in range(40)], reqs)
+    assert s["offered_req_per_s"] == pytest.approx(100.0)
+    assert s["served_req_per_s"] == pytest.approx(100.0)
+    assert s["stable"] and s["latency_growth"] == pytest.approx(1.0)
+    s = SV.summary([_res(r, 0.01 * r, 0.05 + 0.02 * r) for r in range(40)], reqs)
+    assert s["served_req_per_s"] == pytest.approx(50.0)
+    assert not s["stable"] and s["latency_growth"] > 3.0
