@@ -44,13 +44,22 @@ __global__ void k_zero(uint32_t* p, size_t n32) {
 }
 
 // r = B - A X (or A^*), FP64; per-block partial sums of |r|^2 and |B|^2
+//
+// Workgroups go to the eight XCDs in turn, so the (column, 256-node block)
+// pairs are numbered to give each XCD one contiguous range of them: the rows
+// above and below a block, which the stencil reads, then belong to blocks
+// on the same XCD and come from its L2 instead of being fetched again by
+// every neighbour's XCD.  The grid has 8 * per_xcd workgroups; numbers past
+// the nblk * S pairs return at once.
 __global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const double2* B, int64_t ldb,
                                                   const double2* X, int64_t ldx, double2* R, int64_t ldr,
-                                                  float2* R32, int S, double* partial, int nblk) {
+                                                  float2* R32, int S, double* partial, int nblk, int per_xcd) {
     __shared__ double sr[256], sb[256];
-    const int s = blockIdx.y;
+    const int pair = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
+    if ((int64_t)pair >= (int64_t)nblk * S) return;
+    const int s = pair / nblk, kb = pair - s * nblk;
     const int64_t N = (int64_t)cf.nx * cf.nz;
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t k = (int64_t)kb * 256 + threadIdx.x;
     double rr = 0.0, bb = 0.0;
     if (k < N) {
         const int i = (int)(k % cf.nx), j = (int)(k / cf.nx);
@@ -79,8 +88,8 @@ __global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const do
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        partial[((size_t)s * nblk + blockIdx.x) * 2 + 0] = sr[0];
-        partial[((size_t)s * nblk + blockIdx.x) * 2 + 1] = sb[0];
+        partial[((size_t)s * nblk + kb) * 2 + 0] = sr[0];
+        partial[((size_t)s * nblk + kb) * 2 + 1] = sb[0];
     }
 }
 
@@ -491,8 +500,9 @@ void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st) {
 }
 void launch_residual(const Coef& cf, int adjoint, const double* B, int64_t ldb, const double* X, int64_t ldx,
                      double* R, int64_t ldr, float* R32, int S, double* partial, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk, S), dim3(256), 0, st, cf, adjoint, (const double2*)B, ldb,
-                       (const double2*)X, ldx, (double2*)R, ldr, (float2*)R32, S, partial, nblk);
+    const int per_xcd = (int)(((int64_t)nblk * S + 7) / 8);
+    hipLaunchKernelGGL(k_residual, dim3(8 * per_xcd), dim3(256), 0, st, cf, adjoint, (const double2*)B, ldb,
+                       (const double2*)X, ldx, (double2*)R, ldr, (float2*)R32, S, partial, nblk, per_xcd);
 }
 void launch_norms_finish(const double* partial, int nblk, int S, double* norms, hipStream_t st) {
     hipLaunchKernelGGL(k_norms_finish, dim3(S), dim3(256), 0, st, partial, nblk, S, norms);
