@@ -784,18 +784,18 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
         }
         return HELM_OK;
     }
-    // FP32 factor: solve in complex64, refine in FP64
+    // FP32 factor: solve in complex64, refine in FP64.  The FP64 residual
+    // is needed only as the complex64 right-hand side of the next correction
+    // (and for its norm), so it is not stored in complex128.
     if (tol <= 0.0) tol = 1e-10;
     Scratch sc(st);
     std::vector<float*> Y32(n), X32(n);
-    std::vector<double*> R64(n);
     for (int c = 0; c < n; ++c) {
         const int64_t N = N_of(jobs[c].f->g);
         size_t bytes32 = sizeof(float) * 2 * (size_t)N * jobs[c].S;
         int rc = sc.get(&Y32[c], bytes32);
         if (rc) return rc;
         if ((rc = sc.get(&X32[c], bytes32))) return rc;
-        if ((rc = sc.get(&R64[c], sizeof(double) * 2 * (size_t)N * jobs[c].S))) return rc;
         launch_c128_to_c64(jobs[c].B, jobs[c].ld, Y32[c], N, N, jobs[c].S, adjoint ? 1 : 0, st);
         g_launches += 1;
     }
@@ -832,7 +832,7 @@ int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_
             launch_c64_to_c128(X32[c], N, jobs[c].X, jobs[c].ld, N, jobs[c].S, adjoint ? 1 : 0, first ? 0 : 1, st);
             g_launches += 1;
             if (!first) iters[c] += 1;
-            rq.push_back({fs[c], jobs[c].B, jobs[c].ld, jobs[c].X, jobs[c].ld, R64[c], Y32[c], jobs[c].S});
+            rq.push_back({fs[c], jobs[c].B, jobs[c].ld, jobs[c].X, jobs[c].ld, nullptr, Y32[c], jobs[c].S});
         }
         std::vector<double> rel(idx.size());
         int rc = residual_norms_batch(rq, adjoint ? 1 : 0, st, rel.data());
