@@ -294,3 +294,37 @@ def test_c3_size_residual_and_sampled_parity(helm, precision):
     pick = [0, 31, 63]
     Uo = oracle.Factor(g, w.m, omega).solve(oracle.unit_sources(g, w.sources[pick]))
     assert rel(U[pick].cpu().numpy(), Uo) < 1e-9
+
+
+@pytest.mark.slow
+def test_c3_bench_configuration_pipelined_parity(helm):
+    """The benchmark's own configuration: the five 401^2 systems factored in
+    one batch (ten fronts per launch) with complex64 factors, two batches in
+    flight (the second factored while the first is solved), every one of the
+    5 x 64 solutions at relative residual <= 1e-10 in both batches, and
+    sampled wavefields of the batch solved under overlap equal to the
+    oracle's at the lowest and the highest frequency."""
+    from paper_2301_10762_amd.pipeline import Batch, Pipeline
+    w = I.config_c3()
+    G = helm.Grid.of(w)
+    n_omega = len(w.omegas)
+    m_dev = torch.as_tensor(w.m, dtype=torch.float64, device="cuda")
+    E = torch.as_tensor(I.point_sources(G.N, w.sources), device="cuda")
+    print("401^2 x 5 frequencies x 64 sources, two batches in flight", flush=True)
+    res = Pipeline().run([Batch([G] * n_omega, [m_dev] * n_omega, w.omegas, [E] * n_omega, "fp32_ir", 1e-10)
+                          for _ in range(2)])
+    torch.cuda.synchronize()
+    for Xs, infos in res:
+        assert len(Xs) == n_omega
+        assert max(i.max_relres for i in infos) <= 1e-10
+    g = oracle.Grid.of(w)
+    pick = [5, 40]
+    for iw in (0, n_omega - 1):
+        print(f"oracle at omega {w.omegas[iw]:.3f}", flush=True)
+        F = oracle.Factor(g, w.m, w.omegas[iw])
+        Uo = F.solve(oracle.unit_sources(g, w.sources[pick]))
+        F.close()
+        U = res[1][0][iw][pick].cpu().numpy()
+        assert rel(U, Uo) < 1e-9, iw
+        # the two batches ran the same kernels on the same data
+        assert torch.equal(res[0][0][iw], res[1][0][iw])
