@@ -430,6 +430,8 @@ def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
     pending or queued."""
     if lanes < 1:
         raise ValueError("lanes must be >= 1")
+    if not callable(getattr(server.be, "lane", None)):
+        raise TypeError("run_lanes needs a backend with lane() (a backend per lane, on a stream of its own)")
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     results, err = [], []
     cv = threading.Condition()

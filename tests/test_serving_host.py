@@ -349,3 +349,11 @@ def test_summary_rates_keep_pace_and_growing_queue():
     s = SV.summary([_res(r, 0.01 * r, 0.05 + 0.02 * r) for r in range(40)], reqs)
     assert s["served_req_per_s"] == pytest.approx(50.0)
     assert not s["stable"] and s["latency_growth"] > 3.0
+
+
+def test_lanes_need_a_backend_with_lanes():
+    srv = SV.Server(FakeBackend(), 1 << 40)
+    with pytest.raises(TypeError, match="lane"):
+        SV.run_lanes(srv, [req(0)], lanes=2, realtime=False)
+    with pytest.raises(ValueError):
+        SV.run_lanes(SV.Server(LaneFake(), 1 << 40), [req(0)], lanes=0, realtime=False)
