@@ -12,10 +12,11 @@ Metric: right-hand-side solves per second (5 x 64 per step / step time),
 with p50/p99 step latency.  Inputs are seeded synthetic layered models
 resident in HBM before the timed region.
 
-Schedule: the K timed steps run with two batches in flight (the
-factorisation of step k+1 on one stream while step k is solved on another;
-paper_2301_10762_amd.pipeline); every step is still factored and solved in
-full.  The serial schedule (one step at a time) is timed first and reported
+Schedule: the K timed steps run as a pipeline of independent batches
+(paper_2301_10762_amd.pipeline): the factorisations of the next F steps run
+side by side, each on a stream of its own (F = --factor-streams, default 1:
+two batches in flight), while step k is solved on another stream; every step
+is still factored and solved in full, with the same kernels.  The serial schedule (one step at a time) is timed first and reported
 beside it, with the per-step latency percentiles and the per-kernel timings
 that the roofline figure uses.
 
@@ -49,8 +50,10 @@ def parse():
     p.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 comparison (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--schedule", default="both", choices=["both", "serial"],
-                   help="both: serial steps (kernel timings, latency) then the headline with two batches in "
+                   help="both: serial steps (kernel timings, latency) then the headline with batches in "
                         "flight; serial: the serial steps only (value = their throughput)")
+    p.add_argument("--factor-streams", type=int, default=1,
+                   help="factorisations side by side in the pipelined schedule (1: two batches in flight)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
@@ -427,17 +430,19 @@ def main():
         return total, lat, infos, kt
 
     def run_pipelined(precision, warmup, steps):
-        """The same steps with two batches in flight: batch k+1 is factored
-        while batch k is solved (paper_2301_10762_amd.pipeline)."""
+        """The same steps as a pipeline: the next F batches are factored side
+        by side (one stream each) while batch k is solved
+        (paper_2301_10762_amd.pipeline); at most F + 1 batches hold factors."""
         from paper_2301_10762_amd.pipeline import Batch, Pipeline
-        pipe = Pipeline()
-        outs = [[torch.empty_like(E) for _ in range(n_omega)] for _ in range(2)]
+        nf = max(1, args.factor_streams)
+        pipe = Pipeline(factor_streams=nf)
+        outs = [[torch.empty_like(E) for _ in range(n_omega)] for _ in range(nf + 1)]
 
         def batches(k):
-            return [Batch([G] * n_omega, [m_dev] * n_omega, w.omegas, [E] * n_omega, precision, TOL, outs[q & 1])
-                    for q in range(k)]
+            return [Batch([G] * n_omega, [m_dev] * n_omega, w.omegas, [E] * n_omega, precision, TOL,
+                          outs[q % (nf + 1)]) for q in range(k)]
         if warmup:
-            pipe.run(batches(warmup + 1))
+            pipe.run(batches(max(warmup + 1, nf + 1)))   # every factor stream and output set used once
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = pipe.run(batches(steps))
@@ -454,7 +459,7 @@ def main():
     solves = n_omega * S * args.steps
     serial = {"value": round(solves / total_s, 2), "ms_per_step": round(total_s / args.steps * 1e3, 3),
               "p50_ms": round(percentile(lat, 0.5), 3), "p99_ms": round(percentile(lat, 0.99), 3)}
-    # headline: two batches in flight
+    # headline: the pipelined schedule
     if args.schedule == "both":
         total, infos_p = run_pipelined(prec, args.warmup, args.steps)
     else:
@@ -578,8 +583,9 @@ def main():
                                "per frequency, all solved to rel. residual <= 1e-10",
                    "grid": [nx, nz], "n_omega": n_omega, "sources": S, "parallelism": "single GPU",
                    "precision": prec},
-        "schedule": ("two batches in flight: the factorisation of batch k+1 overlaps the solves of batch k "
-                     "(each batch = the five systems factored and all 5 x 64 right-hand sides solved)")
+        "schedule": (f"pipelined: the factorisations of the next {max(1, args.factor_streams)} batches run side by "
+                     "side (one stream each) while batch k is solved on another stream (each batch = the five "
+                     "systems factored and all 5 x 64 right-hand sides solved)")
                     if args.schedule == "both" else "serial: one batch at a time",
         "serial": serial,
         "p50_ms": serial["p50_ms"], "p99_ms": serial["p99_ms"],
