@@ -468,12 +468,14 @@ __global__ __launch_bounds__(256) void k_gamma(const double* m, int nx, int nz, 
     if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
 }
 
+// sum of n partials by one wavefront (64 threads): lane l adds part[l],
+// part[l + 64], ... in order, then a fixed-order tree across the lanes
 __global__ void k_sum_scalar(const double* part, int n, double* out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double a = 0.0;
-        for (int q = 0; q < n; ++q) a += part[q];
-        *out = a;
-    }
+    const int l = threadIdx.x;
+    double a = 0.0;
+    for (int q = l; q < n; q += 64) a += part[q];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if (l == 0) *out = a;
 }
 
 // one wavefront: D = A(16x4) B(4x16) with the operand layout the kernels assume
