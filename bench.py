@@ -354,7 +354,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the systems of this workload are independent per "
-              "frequency and each factorisation fits one MI355X; multi-GPU runs are not part of this build.",
+              "frequency and each factorisation fits one MI355X; running on several GPUs is not supported.",
               file=sys.stderr)
         sys.exit(2)
 
