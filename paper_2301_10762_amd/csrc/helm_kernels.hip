@@ -54,7 +54,7 @@ __global__ void k_zero(uint32_t* p, size_t n32) {
 __global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const double2* B, int64_t ldb,
                                                   const double2* X, int64_t ldx, double2* R, int64_t ldr,
                                                   float2* R32, int S, double* partial, int nblk, int per_xcd) {
-    __shared__ double sr[256], sb[256];
+    __shared__ double sr[4], sb[4];
     const int pair = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
     if ((int64_t)pair >= (int64_t)nblk * S) return;
     const int s = pair / nblk, kb = pair - s * nblk;
@@ -80,16 +80,21 @@ __global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const do
         rr = r.x * r.x + r.y * r.y;
         bb = bk.x * bk.x + bk.y * bk.y;
     }
-    sr[threadIdx.x] = rr;
-    sb[threadIdx.x] = bb;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) { sr[threadIdx.x] += sr[threadIdx.x + h]; sb[threadIdx.x] += sb[threadIdx.x + h]; }
-        __syncthreads();
+    // fixed-order sums: a shuffle tree within each wavefront, then the four
+    // wavefront sums in order
+    for (int o = 32; o > 0; o >>= 1) {
+        rr += __shfl_down(rr, o, 64);
+        bb += __shfl_down(bb, o, 64);
     }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[w] = rr;
+        sb[w] = bb;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partial[((size_t)s * nblk + kb) * 2 + 0] = sr[0];
-        partial[((size_t)s * nblk + kb) * 2 + 1] = sb[0];
+        partial[((size_t)s * nblk + kb) * 2 + 0] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+        partial[((size_t)s * nblk + kb) * 2 + 1] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
     }
 }
 
