@@ -338,17 +338,6 @@ int helm_tile_inverse(int32_t count, int32_t kb, int pivot, const double* A_dev,
  * start for every later factorisation (process-wide).                      */
 void helm_set_tile_pivoting(int always);
 
-/* Factorisation schedule (process-wide).  persistent = 0 (default): one
- * launch per panel step.  persistent = 1: one launch per group of systems in
- * which every workgroup stays resident, keeps its tile in registers and
- * exchanges panel data with the other workgroups of its front through
- * memory (device-scope accesses), used when the device can hold all of them
- * at once (else, or if a workgroup's wait ever times out, the group is
- * factored with one launch per panel step).  Both give bitwise the same
- * factors; on MI355X the per-step launches are faster at 401^2 (the
- * exchanged panels cannot stay in the non-coherent L2). */
-void helm_set_factor_path(int persistent);
-
 /* Device memory of factors and scratch is recycled through a cache of freed
  * blocks: helm_factor_destroy and the end of every call return their blocks
  * to it (with an event marking their last use on the stream), and a later
@@ -377,11 +366,8 @@ void helm_kernel_timing(int enable);
 int helm_kernel_time(int kind, double* total_ms, int64_t* count);
 
 /* Counters since load: 0 = kernel launches, 1 = right-hand-side solves,
- * 2 = persistent factorisations redone one launch per step because a wait
- * timed out, 3 = the code of the last such wait (bit 30 set; bit 20: the
- * next-tile workgroup; bit 16: the merge-block wait; low 16 bits: the step),
- * 4 = bytes of device memory held in the block cache (below),
- * -1 for an unknown index. */
+ * 4 = bytes of device memory held in the block cache (above); -1 for any
+ * other index. */
 int64_t helm_counter(int which);
 
 const char* helm_last_error(void);

@@ -373,28 +373,8 @@ __device__ __forceinline__ bool gj_pairs(typename CT<T>::c (&a)[4], typename CT<
     return sh.small != 0;
 }
 
-// Data exchanged between the workgroups of a front (panels, T, the merge
-// block) is written and read with relaxed device-scope atomic accesses, which
-// are coherent at the device level without cache write-back or
-// invalidation; a workgroup-scope release (its stores complete) orders them
-// before the counter increment.
-__device__ __forceinline__ double2 cld(const double2* p) {
-    const unsigned long long* q = (const unsigned long long*)p;
-    const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
-}
-__device__ __forceinline__ float2 cld(const float2* p) {
-    const unsigned long long v = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-    return make_float2(__uint_as_float((unsigned)(v & 0xffffffffull)), __uint_as_float((unsigned)(v >> 32)));
-}
-__device__ __forceinline__ void cst(double2* p, double2 v) {
-    unsigned long long* q = (unsigned long long*)p;
-    __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
+// Device-coherent store of one complex64 value: a relaxed agent-scope atomic
+// store, which writes through the XCD's L2 to memory.
 __device__ __forceinline__ void cst(float2* p, float2 v) {
     const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
                                  ((unsigned long long)__float_as_uint(v.y) << 32);
@@ -423,7 +403,7 @@ constexpr float TAU2 = 1e-4f;
 // (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
 // (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted complex64 path).  Returns the first zero-pivot step (pivoted path) or -1;
 // *small is set when the unpivoted path met a pivot below the tolerance.
-template <typename T, bool COH = false>
+template <typename T>
 __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, int pivot, GJScratch<T>& sh,
                                                 typename CT<T>::c (*M)[33], typename CT<T>::c* L2,
                                                 typename CT<T>::c* Tt, bool* small) {
@@ -440,8 +420,7 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
         if (act) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if constexpr (COH) cst(Tt + (4 * cg + e) * KB + r, a[e]);
-                else Tt[(4 * cg + e) * KB + r] = a[e];
+                Tt[(4 * cg + e) * KB + r] = a[e];
             }
         }
         return -1;
@@ -457,8 +436,7 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            if constexpr (COH) cst(Tt + c * KB + r, M[sh.rowOf[r]][sh.stepOf[c]]);
-            else Tt[c * KB + r] = M[sh.rowOf[r]][sh.stepOf[c]];
+            Tt[c * KB + r] = M[sh.rowOf[r]][sh.stepOf[c]];
         }
     }
     return zero;
@@ -890,481 +868,6 @@ __global__ __launch_bounds__(256, 2) void k_factor_step(int n, int tstep, int un
     } else {
         update_tile<T>(d, ps, u - d.ftile0, X, Y, Tcur, smem);
     }
-}
-
-// ------------------------------------------------- persistent factorisation --
-// The whole factorisation of a group in one launch.  Every update workgroup
-// keeps its 64 x 64 tile of its front's matrix in registers from the first
-// block to the last: per panel step it needs only the panel column of its
-// rows, the panel row of its columns and T, which the owners publish through
-// small ping-pong buffers (PC, PR, DB) after each step, and at the end of a
-// block it writes G_j and forms its tile of D_next = A_next - E G_j E in
-// place.  The next-tile workgroup of a front inverts the next diagonal tile
-// from the same published data, so it overlaps the updates of the step.
-// Workgroups of a front proceed in rounds: round 0 builds D_row0 and T_0,
-// round t + 1 is panel step t; a workgroup starts step t once the front's
-// counter shows every workgroup done with round t.  All workgroups must be
-// resident at once (the host checks the occupancy), and every wait gives up
-// after about a second, setting *err, so the grid always drains.
-constexpr long long SPIN_TICKS = 100000000;   // 1 s of the 100 MHz counter
-
-// `where` identifies the wait in *err (the first failure wins): bit 30,
-// then the workgroup's role (bit 20: next tile) and the round it waited for.
-__device__ __forceinline__ bool front_wait(const int* ctr, int target, int* err, int where) {
-    __shared__ int ok;
-    if (threadIdx.x == 0) {
-        int good = 1;
-        const long long t0 = wall_clock64();
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                wall_clock64() - t0 > SPIN_TICKS) {
-                int expect = 0;
-                __hip_atomic_compare_exchange_strong(err, &expect, (1 << 30) | where, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                good = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        ok = good;
-    }
-    __syncthreads();
-    const bool good = ok != 0;
-    __syncthreads();
-    return good;
-}
-
-__device__ __forceinline__ void front_signal(int* ctr) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The panel column and panel row that step t2 reads, and the next diagonal
-// block it inverts, from this workgroup's tile (in LDS, sX[row][col]).
-template <typename T>
-__device__ __forceinline__ void persist_publish(const ChainInfo& d, int t2, int I0, int J0,
-                                                const typename CT<T>::c (*sX)[65]) {
-    using C = typename CT<T>::c;
-    const int np = d.np, t = threadIdx.x;
-    const PanelStep q = panel_step(d, t2);
-    const int k2 = q.k0, kb2 = q.kb;
-    const int k3 = q.p + 1 < d.npan ? q.k0 + q.kb : 0, kb3 = min(KB, np - k3);
-    const int hi = min(np, I0 + TILE), hj = min(np, J0 + TILE);
-    if (k2 >= J0 && k2 < hj) {
-        C* PCn = (C*)d.PC + (size_t)(t2 & 1) * np * KB;
-#pragma unroll 1
-        for (int i = t; i < TILE * KB; i += 256) {
-            const int rl = i >> 5, c = i & 31;
-            if (I0 + rl < hi && c < kb2) cst(PCn + (size_t)(I0 + rl) * KB + c, sX[rl][k2 - J0 + c]);
-        }
-    }
-    if (k2 >= I0 && k2 < hi) {
-        C* PRn = (C*)d.PR + (size_t)(t2 & 1) * KB * np;
-#pragma unroll 1
-        for (int i = t; i < KB * TILE; i += 256) {
-            const int r = i >> 6, cl = i & 63;
-            if (r < kb2 && J0 + cl < hj) cst(PRn + (size_t)r * np + J0 + cl, sX[k2 - I0 + r][cl]);
-        }
-    }
-    if (k3 >= I0 && k3 < hi && k3 >= J0 && k3 < hj) {
-        C* DBn = (C*)d.DB + (size_t)(t2 & 1) * KB * KB;
-#pragma unroll 1
-        for (int i = t; i < KB * KB; i += 256) {
-            const int r = i >> 5, c = i & 31;
-            if (r < kb3 && c < kb3) cst(DBn + r * KB + c, sX[k3 - I0 + r][k3 - J0 + c]);
-        }
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void persist_update(const ChainInfo& d, int ti, char* smem, int* err) {
-    constexpr bool GAUSS = sizeof(T) == 8;   // as in update_tile
-    using C = typename CT<T>::c;
-    using V = typename CT<T>::v4;
-    const int np = d.np;
-    const size_t n2 = (size_t)np * np;
-    const int tiles_x = (np + TILE - 1) / TILE;
-    const int I0 = (ti / tiles_x) * TILE, J0 = (ti % tiles_x) * TILE;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const int wr = w >> 1, wc = w & 1;
-    const int nwg = step_blocks(np);
-    C (*sW)[33] = (C(*)[33])smem;
-    C (*sV)[33] = (C(*)[33])(smem + 64 * 33 * sizeof(C));
-    C (*sT)[33] = sV;
-    int R[2], Cc[2];
-    bool vr[2], vc[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        R[q] = I0 + 32 * wr + 16 * q;
-        Cc[q] = J0 + 32 * wc + 16 * q;
-        vr[q] = R[q] < np;
-        vc[q] = Cc[q] < np;
-    }
-    // the tile in LDS for element-wise work (the W and V buffers, free
-    // outside the update)
-    C (*sX)[65] = (C(*)[65])smem;
-    static_assert(64 * 65 * sizeof(C) <= 2 * 64 * 33 * sizeof(C), "tile buffer exceeds the W and V buffers");
-    auto tile_to_lds = [&](const V (&ar)[2][2], const V (&ai)[2][2]) {
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    sX[32 * wr + 16 * bi + acc_row<T>(lg, e)][32 * wc + 16 * bj + lr] = mk<C>(ar[bi][bj][e], ai[bi][bj][e]);
-    };
-    V xr[2][2], xi[2][2];
-    auto tile_from_lds = [&]() {
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const C v = sX[32 * wr + 16 * bi + acc_row<T>(lg, e)][32 * wc + 16 * bj + lr];
-                    xr[bi][bj][e] = v.x;
-                    xi[bi][bj][e] = v.y;
-                }
-    };
-    // round 0: this tile of D = A_row0
-#pragma unroll 1
-    for (int i = t; i < TILE * TILE; i += 256) {
-        const int rl = i >> 6, cl = i & 63, row = I0 + rl, col = J0 + cl;
-        const double2 a = (row < np && col < np) ? block_entry(d.cf, d.row0, row, col) : make_double2(0.0, 0.0);
-        sX[rl][cl] = mk<C>(a.x, a.y);
-    }
-    __syncthreads();
-    tile_from_lds();
-    persist_publish<T>(d, 0, I0, J0, sX);
-    front_signal(d.ctr);
-    for (int ts = 0; ts < d.T; ++ts) {
-        if (!front_wait(d.ctr, nwg * (ts + 1), err, ts & 0xFFFF)) return;
-        const PanelStep ps = panel_step(d, ts);
-        const int kb = ps.kb, k0 = ps.k0;
-        const C* PCt = (const C*)d.PC + (size_t)(ts & 1) * np * KB;
-        const C* PRt = (const C*)d.PR + (size_t)(ts & 1) * KB * np;
-        const C* Tcur = (const C*)d.Tb + (size_t)(ts & 1) * KB * KB;
-        // X_{I,K} and T into LDS; the panel columns of the tile become the
-        // identity (the tile is the accumulator of the update)
-        {
-            C xik[8], tv[4];
-            const int rr = t >> 2, c8 = 8 * (t & 3), row = I0 + rr;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int c = c8 + q;
-                xik[q] = (row < np && c < kb) ? cld(PCt + (size_t)row * KB + c) : mk<C>(0.0, 0.0);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tv[q] = cld(Tcur + t + 256 * q);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = xik[q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = t + 256 * q, c = i >> 5, k = i & 31;
-                sT[k][c] = (k < kb && c < kb) ? tv[q] : mk<C>(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                const int col = Cc[bj] + lr;
-                if (col >= k0 && col < k0 + kb) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int row = R[bi] + acc_row<T>(lg, e);
-                        xr[bi][bj][e] = row == col ? (T)1 : (T)0;
-                        xi[bi][bj][e] = 0;
-                    }
-                }
-            }
-        __syncthreads();
-        {
-            V wre[2], wim[2];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                V q1, q2, q3;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) { q1[e] = 0; q2[e] = 0; q3[e] = 0; }
-#pragma unroll
-                for (int s8 = 0; s8 < 8; ++s8) {
-                    const int k = 4 * s8 + lg;
-                    const C av = sW[16 * w + lr][k], bv = sT[k][cb * 16 + lr];
-                    cacc<GAUSS, T, V>(q1, q2, q3, av.x, av.y, bv.x, bv.y);
-                }
-                cacc_final<GAUSS, V>(q1, q2, q3, wre[cb], wim[cb]);
-            }
-            C tk[2][4];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = I0 + 16 * w + acc_row<T>(lg, e), c = cb * 16 + lr;
-                    tk[cb][e] = (row >= k0 && row < k0 + kb) ? sT[row - k0][c] : mk<C>(0.0, 0.0);
-                }
-            __syncthreads();
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int rl = 16 * w + acc_row<T>(lg, e), row = I0 + rl, c = cb * 16 + lr;
-                    C v;
-                    if (row >= k0 && row < k0 + kb) {
-                        v = tk[cb][e];
-                        if (row - k0 == c) v.x -= (T)1;
-                    } else {
-                        v = mk<C>(-wre[cb][e], -wim[cb][e]);
-                    }
-                    sW[rl][c] = v;
-                }
-            }
-        }
-        // V_J = X_{K,J} into LDS, transposed (V_KK = I)
-#pragma unroll 2
-        for (int q = 0; q < 8; ++q) {
-            const int i = t + 256 * q, k = i >> 6, cc = i & 63, col = J0 + cc;
-            C v = mk<C>(0.0, 0.0);
-            if (k < kb && col < np)
-                v = (col >= k0 && col < k0 + kb) ? mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0)
-                                                 : cld(PRt + (size_t)k * np + col);
-            sV[cc][k] = v;
-        }
-        __syncthreads();
-        // the same accumulation as the step launches, xr and xi serving as
-        // the first and third accumulators
-        V x2[2][2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                cacc_seed<GAUSS, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], xr[bi][bj], xi[bi][bj]);
-        for (int kk = 0; kk < kb; kk += 16) {
-            C av[2][4], bv[2][4];
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    av[q][s4] = sW[32 * wr + 16 * q + lr][kk + 4 * lg + s4];
-                    bv[q][s4] = sV[32 * wc + 16 * q + lr][kk + 4 * lg + s4];
-                }
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 2; ++bj)
-                        if (vr[bi] && vc[bj])
-                            cacc<GAUSS, T, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], av[bi][s4].x, av[bi][s4].y,
-                                              bv[bj][s4].x, bv[bj][s4].y);
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                cacc_final<GAUSS, V>(xr[bi][bj], x2[bi][bj], xi[bi][bj], xr[bi][bj], xi[bi][bj]);
-        const bool more = ts + 1 < d.T;
-        if (ps.last_panel || more) {
-            __syncthreads();   // every wave is done with sW, sV
-            tile_to_lds(xr, xi);
-            __syncthreads();
-        }
-        if (ps.last_panel) {
-            // G_j to the sweeps' layout; then this tile of the next block
-            const int row_b = d.row0 + d.dir * ps.j, rn = row_b + d.dir;
-            C* Gb = (C*)d.G + (size_t)row_b * n2;
-            C* An = nullptr;
-            const C* Asrc = nullptr;
-            bool keep = false;
-            if (ps.j + 1 < d.nblk) {
-                keep = true;
-                Asrc = next_a_source<C>(d, ps.j);
-                if (Asrc && !front_wait(d.peer, d.peer_target, err, (1 << 16) | (ts & 0xFFFF))) return;
-            } else if (d.Aout) {
-                An = (C*)d.Aout;
-            }
-#pragma unroll 1
-            for (int i = t; i < TILE * TILE; i += 256) {
-                const int rl = i >> 6, cl = i & 63, row = I0 + rl, col = J0 + cl;
-                if (row >= np || col >= np) continue;
-                const C g = sX[rl][cl];
-                gst(Gb + a_tiled(row, col, np), g);
-                if (keep || An) {
-                    double2 a1;
-                    if (Asrc) {
-                        const C v = cld(Asrc + (size_t)row * np + col);
-                        a1 = make_double2(v.x, v.y);
-                    } else {
-                        a1 = block_entry(d.cf, rn, row, col);
-                    }
-                    const double sc = row_coupling(d.cf, row) * row_coupling(d.cf, col);
-                    const C dn = mk<C>(a1.x - sc * (double)g.x, a1.y - sc * (double)g.y);
-                    if (An) cst(An + (size_t)row * np + col, dn);
-                    sX[rl][cl] = dn;
-                }
-            }
-            __syncthreads();
-            if (keep) tile_from_lds();
-        }
-        if (more) persist_publish<T>(d, ts + 1, I0, J0, sX);
-        front_signal(d.ctr);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void persist_next(const ChainInfo& d, char* smem, int* err) {
-    using C = typename CT<T>::c;
-    using V = typename CT<T>::v4;
-    const int np = d.np;
-    const int nwg = step_blocks(np);
-    C (*sXa)[33] = (C(*)[33])smem;
-    C (*sT)[33] = (C(*)[33])(smem + 1 * 32 * 33 * sizeof(C));
-    C (*sXb)[33] = (C(*)[33])(smem + 2 * 32 * 33 * sizeof(C));
-    C (*sP)[33] = (C(*)[33])(smem + 3 * 32 * 33 * sizeof(C));
-    GJScratch<T>& sh = *(GJScratch<T>*)(smem + 4 * 32 * 33 * sizeof(C));
-    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
-    const int w = t >> 6, l = t & 63, lr = l & 15, lg = l >> 4;
-    const int wr = w >> 1, wc = w & 1;
-    {
-        // round 0: T_0 = inverse of the first diagonal tile of A_row0
-        const int kb = min(KB, np);
-        C a[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = 4 * cg + e;
-            const double2 v = (r < kb && c < kb) ? block_entry(d.cf, d.row0, r, c) : make_double2(0.0, 0.0);
-            a[e] = mk<C>(v.x, v.y);
-        }
-        bool small;
-        const int zero = invert_and_store<T, true>(a, kb, d.pivot, sh, sXa, &sT[0][0], (C*)d.Tb, &small);
-        if (zero >= 0 && t == 0) report_zero_pivot(d.status, d.row0, zero);
-        if (small && t == 0) d.status[3] = 1;
-        front_signal(d.ctr);
-    }
-    for (int ts = 0; ts < d.T; ++ts) {
-        if (!front_wait(d.ctr, nwg * (ts + 1), err, (1 << 20) | (ts & 0xFFFF))) return;
-        const PanelStep ps = panel_step(d, ts);
-        const int kb = ps.kb, k0 = ps.k0;
-        const int row = d.row0 + d.dir * ps.j;
-        int jn, kn0;
-        const C* Asrc = nullptr;
-        if (!ps.last_panel) {
-            jn = row;
-            kn0 = k0 + kb;
-        } else {
-            if (ps.j + 1 >= d.nblk) {
-                front_signal(d.ctr);
-                continue;
-            }
-            jn = row + d.dir;
-            kn0 = 0;
-            Asrc = next_a_source<C>(d, ps.j);
-        }
-        const int kbn = min(KB, np - kn0);
-        const C* PCt = (const C*)d.PC + (size_t)(ts & 1) * np * KB;
-        const C* PRt = (const C*)d.PR + (size_t)(ts & 1) * KB * np;
-        const C* DBt = (const C*)d.DB + (size_t)(ts & 1) * KB * KB;
-        const C* Tcur = (const C*)d.Tb + (size_t)(ts & 1) * KB * KB;
-        C* Tnext = (C*)d.Tb + (size_t)((ts + 1) & 1) * KB * KB;
-        const bool single = ps.last_panel && d.npan == 1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = t + 256 * i;
-            const int hi = idx >> 5, lo = idx & 31;
-            sT[lo][hi] = (hi < kb && lo < kb) ? cld(Tcur + idx) : mk<C>(0.0, 0.0);
-            if (!single) {
-                sXa[hi][lo] = (hi < kbn && lo < kb) ? cld(PCt + (size_t)(kn0 + hi) * KB + lo) : mk<C>(0.0, 0.0);
-                sXb[hi][lo] = (hi < kb && lo < kbn) ? cld(PRt + (size_t)hi * np + kn0 + lo) : mk<C>(0.0, 0.0);
-            }
-        }
-        V zr, zi;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
-            const C v = (!single && rr < kbn && cc < kbn) ? cld(DBt + rr * KB + cc) : mk<C>(0.0, 0.0);
-            zr[e] = v.x;
-            zi[e] = v.y;
-        }
-        C a[4];
-        const bool act = (r < kbn) && (4 * cg < kbn);
-        __syncthreads();
-        if (single) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = act ? sT[r][4 * cg + e] : mk<C>(0.0, 0.0);
-        } else {
-            V pr, pim;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) { pr[e] = 0; pim[e] = 0; }
-#pragma unroll
-            for (int s8 = 0; s8 < 8; ++s8) {
-                const C x = sXa[16 * wr + lr][4 * s8 + lg], y = sT[4 * s8 + lg][16 * wc + lr];
-                cmfma<T, V>(pr, pim, x.x, x.y, y.x, y.y);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sP[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(-pr[e], -pim[e]);
-            __syncthreads();
-#pragma unroll
-            for (int s8 = 0; s8 < 8; ++s8) {
-                const C x = sP[16 * wr + lr][4 * s8 + lg], y = sXb[4 * s8 + lg][16 * wc + lr];
-                cmfma<T, V>(zr, zi, x.x, x.y, y.x, y.y);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sXa[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(zr[e], zi[e]);
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = act ? sXa[r][4 * cg + e] : mk<C>(0.0, 0.0);
-        }
-        if (ps.last_panel) {
-            if (Asrc && !front_wait(d.peer, d.peer_target, err, (1 << 20) | (1 << 16) | (ts & 0xFFFF))) return;
-            if (act) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int c = 4 * cg + e;
-                    double2 a1;
-                    if (Asrc) {
-                        const C v = cld(Asrc + (size_t)r * np + c);
-                        a1 = make_double2(v.x, v.y);
-                    } else {
-                        a1 = block_entry(d.cf, jn, r, c);
-                    }
-                    const double sc = row_coupling(d.cf, r) * row_coupling(d.cf, c);
-                    a[e] = mk<C>(a1.x - sc * (double)a[e].x, a1.y - sc * (double)a[e].y);
-                }
-            }
-        }
-        __syncthreads();   // sXa is reused as the inversion buffer
-        bool small;
-        const int zero = invert_and_store<T, true>(a, kbn, d.pivot, sh, sXa, &sT[0][0], Tnext, &small);
-        if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
-        if (small && t == 0) d.status[3] = 1;
-        front_signal(d.ctr);
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_factor_persist(const ChainTab tab, int n, int* err) {
-    __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
-    const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.utile0; });
-    const ChainInfo d = tab.c[ci];
-    const int ti = blockIdx.x - d.utile0;
-    if (ti == step_blocks(d.np) - 1) persist_next<T>(d, smem, err);
-    else persist_update<T>(d, ti, smem, err);
-}
-
-void launch_factor_persist(const ChainTab& tab, int n, int total, bool fp32, int* err, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_factor_persist<float>, dim3(total), dim3(256), 0, st, tab, n, err);
-    else hipLaunchKernelGGL(k_factor_persist<double>, dim3(total), dim3(256), 0, st, tab, n, err);
-}
-
-int factor_persist_capacity(bool fp32) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_factor_persist<float>, 256, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_factor_persist<double>, 256, 0);
-    if (e != hipSuccess) return 0;
-    return per_cu * prop.multiProcessorCount;
 }
 
 // standalone tile inverses (the building block above, for tests)

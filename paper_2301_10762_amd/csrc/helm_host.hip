@@ -61,7 +61,6 @@ namespace {
 
 thread_local std::string g_err;
 std::atomic<int64_t> g_launches{0}, g_solves{0};
-std::atomic<int64_t> g_persist_fallbacks{0}, g_persist_last_err{0};
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -275,7 +274,6 @@ struct KernelTimer {
 };
 KernelTimer g_timer;
 int g_force_pivot = 0;   // 1: always invert diagonal tiles with partial pivoting
-int g_persist = 0;       // 1: one persistent launch per factorisation when every workgroup fits
 
 Coef coef_of(const helm_factor_s* f) {
     Coef c;
@@ -322,25 +320,21 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     ChainTab ctab;
     std::memset(&ctab, 0, sizeof(ctab));
     ChainInfo* tab = ctab.c;
-    for (int c = 0; c < MAXB; ++c) tab[c].utile0 = tab[c].itile0 = tab[c].ftile0 = INT32_MAX;
+    for (int c = 0; c < MAXB; ++c) tab[c].itile0 = tab[c].ftile0 = INT32_MAX;
     int utot = 0, itot = 0, Tmax = 0, nf = 0;
     size_t buf = 0;
-    int wgs = 0;
     for (int c = 0; c < n; ++c) {
-        const size_t n2 = (size_t)fs[c]->np * fs[c]->np, npk = (size_t)fs[c]->np * KB;
-        buf += 2 * (2 * n2 + 2 * (size_t)KB * KB + 4 * npk + 2 * (size_t)KB * KB) * es + n2 * es + 14 * 256;
-        wgs += 2 * factor_step_blocks(fs[c]->np);
+        // per system: two fronts of (P0, P1, two tile slots) and the merge
+        // block, each rounded up to 256 bytes
+        const size_t n2 = (size_t)fs[c]->np * fs[c]->np;
+        buf += 2 * (2 * n2 + 2 * (size_t)KB * KB) * es + n2 * es + 8 * 256;
     }
-    // one persistent launch when every workgroup of the group can be resident
-    const bool persist = g_persist && wgs <= factor_persist_capacity(fp32);
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
     int* status;
-    if ((rc = sc.get(&status, sizeof(int) * (4 * 2 * n + 2 * n + 1)))) return rc;
-    launch_zero(status, sizeof(int) * (4 * 2 * n + 2 * n + 1), st);
-    int* ctrs = status + 4 * 2 * n;     // per-front round counters (persistent path)
-    int* err = ctrs + 2 * n;
+    if ((rc = sc.get(&status, sizeof(int) * 4 * 2 * n))) return rc;
+    launch_zero(status, sizeof(int) * 4 * 2 * n, st);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void* p = arena + off;
@@ -379,17 +373,6 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             }
             ci.T = ci.npan * ci.nblk;
             ci.pivot = pivot;
-            ci.PC = take(2 * (size_t)f->np * KB * es);
-            ci.PR = take(2 * (size_t)f->np * KB * es);
-            ci.DB = take(2 * (size_t)KB * KB * es);
-            ci.ctr = ctrs + nf;
-            if (side == 1) {
-                // the top front waits for the bottom front's last round before its merge block
-                ChainInfo& top = tab[nf - 1];
-                top.peer = ci.ctr;
-                top.peer_target = factor_step_blocks(f->np) * (ci.T + 1);
-            }
-            ci.utile0 = utot;
             ci.ftile0 = utot - nf;   // update workgroups of the fronts before this one
             utot += factor_step_blocks(f->np);
             ci.itile0 = itot;
@@ -399,40 +382,21 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             ++nf;
         }
     }
-    if (persist) {
-        KernelTimer::Pair pu;
-        const bool tu = g_timer.begin(0, st, &pu);
-        launch_factor_persist(ctab, nf, utot, fp32, err, st);
-        if (tu) g_timer.end(pu, 1, st);
-        g_launches += 1;
-    } else {
-        {
-            KernelTimer::Pair pi;
-            const bool ti = g_timer.begin(1, st, &pi);
-            launch_factor_init(ctab, nf, itot, fp32, st);
-            if (ti) g_timer.end(pi, 1, st);
-        }
-        KernelTimer::Pair pu;
-        const bool tu = g_timer.begin(0, st, &pu);
-        for (int t = 0; t < Tmax; ++t) launch_factor_step(ctab, nf, t, utot, fp32, st);
-        if (tu) g_timer.end(pu, Tmax, st);
-        g_launches += 1 + (int64_t)Tmax;
+    {
+        KernelTimer::Pair pi;
+        const bool ti = g_timer.begin(1, st, &pi);
+        launch_factor_init(ctab, nf, itot, fp32, st);
+        if (ti) g_timer.end(pi, 1, st);
     }
+    KernelTimer::Pair pu;
+    const bool tu = g_timer.begin(0, st, &pu);
+    for (int t = 0; t < Tmax; ++t) launch_factor_step(ctab, nf, t, utot, fp32, st);
+    if (tu) g_timer.end(pu, Tmax, st);
+    g_launches += 1 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
-    std::vector<int> hs(4 * 2 * n + 2 * n + 1);   // statuses (room for 2 fronts per system), counters, error word
+    std::vector<int> hs(4 * 2 * n);   // statuses (room for 2 fronts per system)
     HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    if (persist && hs[4 * 2 * n + 2 * n]) {
-        // a wait timed out (some workgroup never became resident): redo the
-        // group with one launch per step
-        g_persist_fallbacks += 1;
-        g_persist_last_err = hs[4 * 2 * n + 2 * n];
-        const int keep = g_persist;
-        g_persist = 0;
-        const int rc2 = factor_group(fs, n, pivot, st, needs_pivot);
-        g_persist = keep;
-        return rc2;
-    }
     for (int c = 0; c < nf; ++c)
         if (hs[4 * c])
             return fail(HELM_ESINGULAR, "zero pivot in a diagonal tile: system " + std::to_string(owner[c]) +
@@ -1823,16 +1787,12 @@ int64_t helm_counter(int which) {
     switch (which) {
         case 0: return g_launches.load();
         case 1: return g_solves.load();
-        case 2: return g_persist_fallbacks.load();
-        case 3: return g_persist_last_err.load();
         case 4: return (int64_t)g_cache.cached();
         default: return -1;
     }
 }
 
 void helm_set_tile_pivoting(int always) { g_force_pivot = always ? 1 : 0; }
-
-void helm_set_factor_path(int persistent) { g_persist = persistent ? 1 : 0; }
 
 size_t helm_set_cache_limit(size_t bytes) { return g_cache.set_limit(bytes); }
 

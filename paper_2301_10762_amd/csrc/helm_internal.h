@@ -37,18 +37,10 @@ struct ChainInfo {
     int* status;    // [0] zero-pivot flag, [1] block, [2] row, [3] small-pivot flag
     void* Aout;     // bottom front: receives A_next - E G E after its last block
     const void* Ain;   // top front: replaces A of its last block (the merge block)
-    // persistent path: the exchange between the front's workgroups
-    void* PC;       // panel columns, 2 x (np x 32)
-    void* PR;       // panel rows, 2 x (32 x np)
-    void* DB;       // next diagonal blocks, 2 x (32 x 32)
-    int* ctr;       // rounds completed by the front's workgroups
-    const int* peer;   // top front: the bottom front's counter (merge block ready at peer_target)
-    int peer_target;
     Coef cf;
     int np, npan, T;        // padded size, panels per block, steps (nblk * npan)
     int row0, dir, nblk;    // first grid row, +1 (down) or -1 (up), blocks of this front
     int pivot;              // 0: diagonal pivots (flagged if small), 1: partial pivoting in tiles
-    int utile0;             // first workgroup of this front in a persistent launch
     int ftile0;             // first update workgroup of this front in a step launch, counted
                             // after the one next-tile workgroup per front that leads the grid
     int itile0;             // first workgroup in the initial launch

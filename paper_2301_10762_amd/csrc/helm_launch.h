@@ -10,10 +10,6 @@ int factor_init_blocks(int np);
 int factor_step_blocks(int np);
 void launch_factor_init(const ChainTab& tab, int n, int total_blocks, bool fp32, hipStream_t st);
 void launch_factor_step(const ChainTab& tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
-// the whole factorisation in one launch (every workgroup resident; see
-// factor_persist_capacity); *err is set if a workgroup's wait timed out
-void launch_factor_persist(const ChainTab& tab, int n, int total_blocks, bool fp32, int* err, hipStream_t st);
-int factor_persist_capacity(bool fp32);   // resident workgroups of the persistent kernel, 0 if unknown
 // y = b_{row0} (conjugated for adjoint solves) into Y0 of every front
 void launch_sweep_init(const SweepTab& tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
 // forward step t: row row0 + dir * t of each front; backward step t: row

@@ -129,8 +129,6 @@ def lib():
     L.helm_tile_inverse.argtypes = [i32, i32, ctypes.c_int, _vp, _vp, _vp]
     L.helm_set_tile_pivoting.argtypes = [ctypes.c_int]
     L.helm_set_tile_pivoting.restype = None
-    L.helm_set_factor_path.argtypes = [ctypes.c_int]
-    L.helm_set_factor_path.restype = None
     L.helm_set_cache_limit.argtypes = [ctypes.c_size_t]
     L.helm_set_cache_limit.restype = ctypes.c_size_t
     L.helm_mfma_probe.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
@@ -208,7 +206,6 @@ def _i32(seq):
 def counters() -> dict:
     L = lib()
     return {"launches": int(L.helm_counter(0)), "solves": int(L.helm_counter(1)),
-            "persist_fallbacks": int(L.helm_counter(2)), "persist_last_err": int(L.helm_counter(3)),
             "cached_bytes": int(L.helm_counter(4))}
 
 
@@ -640,12 +637,6 @@ def tile_inverse(A, pivot: bool = True):
 def set_tile_pivoting(always: bool):
     """Always invert diagonal tiles with partial pivoting (process-wide)."""
     lib().helm_set_tile_pivoting(int(always))
-
-
-def set_factor_path(persistent: bool):
-    """One launch per panel step (default) or one persistent launch per
-    factorisation (process-wide)."""
-    lib().helm_set_factor_path(int(persistent))
 
 
 def set_cache_limit(nbytes: int) -> int:

@@ -1,18 +1,19 @@
-"""GPU: the two factorisation schedules give the same factors.
+"""GPU: the launch-per-panel-step factorisation on awkward shapes.
 
-The persistent schedule (one launch per group, every workgroup resident,
-panel data exchanged through memory between the workgroups of a front) and
-the launch-per-panel-step schedule perform the same arithmetic in the same
-order on every element, so their solutions must agree bitwise; both are also
-checked against the FP64 oracle, including ragged grids, both fronts of the
-twisted factorisation, the merge row, complex64 factors with refinement and
-forced tile pivoting.
+Grids with ragged tiles, short and tall grids, the smallest grids with and
+without a bottom front (the two-ended elimination and its merge row), fronts
+of different widths in one launch (the scanned front lookup), complex64
+factors with refinement and forced tile pivoting: every solution column is
+compared with the FP64 oracle, and the number of launches is the schedule's
+(one initial launch, then one per panel step of the longest front).  The
+device block cache is checked to give bitwise the result computed on fresh
+memory.
 """
 import numpy as np
 import pytest
 
 import oracle
-from paper_2301_10762_amd import inputs as I
+from tests.parity import assert_cols
 
 pytestmark = pytest.mark.gpu
 
@@ -26,13 +27,7 @@ def helm():
     from paper_2301_10762_amd import helm as h
     h.lib()
     yield h
-    h.set_factor_path(False)
     h.set_tile_pivoting(False)
-
-
-def rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 # (nx, nz, hx, hz): several tiles with tails, short and tall grids, the
@@ -49,42 +44,47 @@ def _system(nx, nz, hx, hz, seed, S=7):
     return m, w, B
 
 
-def _solve(helm, grid, m, w, B, precision, persistent):
-    helm.set_factor_path(persistent)
+def _steps(nx, nz):
+    """Panel-step launches of one system: the top front's blocks (rows 0..k,
+    k = ceil((nz + 1) / 2) when a bottom front exists) times panels per block."""
+    np_ = (nx + 15) // 16 * 16
+    npan = (np_ + 31) // 32
+    k = (nz + 1) // 2
+    if nz - 1 - k < 1:
+        k = nz - 1
+    return npan * (k + 1)
+
+
+def _oracle(nx, nz, hx, hz, m, w, B):
+    Fo = oracle.Factor(oracle.Grid(nx, nz, hx, hz), m, w)
+    Xo = Fo.solve(B)
+    Fo.close()
+    return Xo
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("nx,nz,hx,hz", GRIDS)
+def test_step_schedule_matches_oracle(helm, nx, nz, hx, hz, precision):
+    m, w, B = _system(nx, nz, hx, hz, seed=nx * 100 + nz)
+    grid = helm.Grid(nx, nz, hx, hz)
+    print(f"grid {nx}x{nz} {precision}", flush=True)
     before = helm.counters()["launches"]
     F = helm.factor(grid, torch.as_tensor(m, device="cuda"), w, precision)
     launches = helm.counters()["launches"] - before
     X, info = helm.solve(F, torch.as_tensor(B, device="cuda"), tol=1e-10)
     F.close()
-    return X.cpu().numpy(), info, launches
+    # zeroing + model check, then the initial launch and the panel steps; a
+    # group whose unpivoted tiles met a small pivot is factored again with
+    # pivoting inside the tiles
+    T = _steps(nx, nz)
+    assert launches in (3 + T, 4 + 2 * T), (launches, T)
+    assert_cols(X.cpu().numpy(), _oracle(nx, nz, hx, hz, m, w, B), 1e-9, what=f"{nx}x{nz} {precision}")
+    assert info.max_relres <= 1e-10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-@pytest.mark.parametrize("nx,nz,hx,hz", GRIDS)
-def test_paths_agree_and_match_oracle(helm, nx, nz, hx, hz, precision):
-    m, w, B = _system(nx, nz, hx, hz, seed=nx * 100 + nz)
-    grid = helm.Grid(nx, nz, hx, hz)
-    print(f"grid {nx}x{nz} {precision}", flush=True)
-    Xp, ip, lp = _solve(helm, grid, m, w, B, precision, True)
-    Xs, is_, ls = _solve(helm, grid, m, w, B, precision, False)
-    assert lp < ls                      # the persistent schedule was used
-    assert helm.counters()["persist_fallbacks"] == 0
-    if precision == "fp64":
-        assert np.array_equal(Xp, Xs)
-    g = oracle.Grid(nx, nz, hx, hz)
-    Fo = oracle.Factor(g, m, w)
-    Xo = Fo.solve(B)
-    Fo.close()
-    assert rel(Xp, Xo) < 1e-9 and rel(Xs, Xo) < 1e-9
-    assert ip.max_relres <= 1e-10 and is_.max_relres <= 1e-10
-
-
-@pytest.mark.parametrize("persistent,precision", [(True, "fp64"), (False, "fp64"), (False, "fp32_ir")])
-def test_batch_of_mixed_grids(helm, persistent, precision):
-    """Fronts of different widths in one launch: the persistent schedule, and
-    the step launches with their scanned front lookup."""
-    helm.set_factor_path(persistent)
-    before = helm.counters()["persist_fallbacks"]
+def test_batch_of_mixed_grids(helm, precision):
+    """Fronts of different widths in one launch (the scanned front lookup)."""
     specs = [GRIDS[0], GRIDS[1], GRIDS[3], GRIDS[5]]
     grids, ms, ws, Bs = [], [], [], []
     for k, (nx, nz, hx, hz) in enumerate(specs):
@@ -96,32 +96,26 @@ def test_batch_of_mixed_grids(helm, persistent, precision):
     Fs = helm.factor_batch(grids, ms, ws, precision)
     Xs, infos = helm.solve_batch(Fs, Bs, tol=1e-10)
     for F, X, B, m, w, g, info in zip(Fs, Xs, Bs, ms, ws, grids, infos):
-        og = oracle.Grid(g.nx, g.nz, g.hx, g.hz)
-        Fo = oracle.Factor(og, m.cpu().numpy(), w)
-        assert rel(X.cpu().numpy(), Fo.solve(B.cpu().numpy())) < 1e-9
-        Fo.close()
+        Xo = _oracle(g.nx, g.nz, g.hx, g.hz, m.cpu().numpy(), w, B.cpu().numpy())
+        assert_cols(X.cpu().numpy(), Xo, 1e-9, what=f"{g.nx}x{g.nz} in a mixed batch")
         F.close()
         assert info.max_relres <= 1e-10
-    assert helm.counters()["persist_fallbacks"] == before
-    helm.set_factor_path(False)
 
 
-def test_persistent_with_forced_tile_pivoting(helm):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_forced_tile_pivoting(helm, precision):
     nx, nz, hx, hz = GRIDS[0]
     m, w, B = _system(nx, nz, hx, hz, seed=3)
     grid = helm.Grid(nx, nz, hx, hz)
     helm.set_tile_pivoting(True)
     try:
-        Xp, ip, _ = _solve(helm, grid, m, w, B, "fp64", True)
-        Xs, _, _ = _solve(helm, grid, m, w, B, "fp64", False)
+        F = helm.factor(grid, torch.as_tensor(m, device="cuda"), w, precision)
+        X, info = helm.solve(F, torch.as_tensor(B, device="cuda"), tol=1e-10)
+        F.close()
     finally:
         helm.set_tile_pivoting(False)
-        helm.set_factor_path(False)
-    assert np.array_equal(Xp, Xs)
-    g = oracle.Grid(nx, nz, hx, hz)
-    Fo = oracle.Factor(g, m, w)
-    assert rel(Xp, Fo.solve(B)) < 1e-9
-    Fo.close()
+    assert_cols(X.cpu().numpy(), _oracle(nx, nz, hx, hz, m, w, B), 1e-9, what="forced pivoting")
+    assert info.max_relres <= 1e-10
 
 
 def test_block_cache_reuses_freed_factor_memory(helm):
