@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_cols, rel
 from paper_2301_10762_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -31,12 +32,6 @@ def helm():
     from paper_2301_10762_amd import helm as h
     h.lib()
     return h
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _kappa(nx, nz, alpha, mu):

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_2301_10762_amd import inputs as I
+from tests.parity import assert_cols, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -27,12 +28,6 @@ def helm():
     from paper_2301_10762_amd import helm as h
     h.lib()
     return h
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 # --------------------------------------------------------- building blocks --
@@ -55,8 +50,7 @@ def test_tile_inverse_pivots_inside_tile(helm, kb):
     A[1, :, 3] *= 1e-6          # badly scaled column
     T = helm.tile_inverse(A, pivot=True).cpu().numpy()
     for c in range(A.shape[0]):
-        ref = np.linalg.inv(A[c])
-        assert rel(T[c], ref) < 1e-10, c
+        assert_cols(T[c], np.linalg.inv(A[c]), 1e-10, what=f"tile {c}")
 
 
 @pytest.mark.parametrize("kb", [16, 32])
@@ -67,13 +61,13 @@ def test_tile_inverse_diagonal_pivots(helm, kb):
     A += 4.0 * np.eye(kb)[None]
     T = helm.tile_inverse(A, pivot=False).cpu().numpy()
     for c in range(A.shape[0]):
-        assert rel(T[c], np.linalg.inv(A[c])) < 1e-12, c
+        assert_cols(T[c], np.linalg.inv(A[c]), 1e-12, what=f"tile {c}")
     A[2, 0, 0] = 1e-3        # first pivot far below 1e-2 * max|tile|
     with pytest.raises(helm.HelmError) as e:
         helm.tile_inverse(A, pivot=False)
     assert e.value.code == helm.ESINGULAR
     T = helm.tile_inverse(A, pivot=True).cpu().numpy()
-    assert rel(T[2], np.linalg.inv(A[2])) < 1e-10
+    assert_cols(T[2], np.linalg.inv(A[2]), 1e-10, what="pivoted tile")
 
 
 def test_forced_tile_pivoting_matches(helm):
@@ -88,7 +82,8 @@ def test_forced_tile_pivoting_matches(helm):
         X, info = helm.factor(G, m, omega).solve(B, tol=1e-10)
     finally:
         helm.set_tile_pivoting(False)
-    assert rel(X.cpu().numpy(), Xo) < 1e-10 and info.max_relres <= 1e-10
+    assert_cols(X.cpu().numpy(), Xo, 1e-10, what="forced tile pivoting")
+    assert info.max_relres <= 1e-10
 
 
 def test_tile_inverse_reports_singular(helm):
@@ -132,8 +127,8 @@ def test_solve_matches_oracle_small(helm, nx, nz, hx, hz):
     F = helm.factor(G, m, omega, "fp64")
     X, info = F.solve(B, tol=1e-10)
     L, ainfo = F.adjoint_solve(B, tol=1e-10)
-    assert rel(X.cpu().numpy(), Xo) < 1e-10
-    assert rel(L.cpu().numpy(), Lo) < 1e-10
+    assert_cols(X.cpu().numpy(), Xo, 1e-10, what="forward")
+    assert_cols(L.cpu().numpy(), Lo, 1e-10, what="adjoint")
     assert info.max_relres <= 1e-10 and ainfo.max_relres <= 1e-10
     assert info.ir_iters == 0
 
@@ -150,8 +145,8 @@ def test_fp32_refined_solve_small(helm, nx, nz, hx, hz):
     L, ainfo = F.adjoint_solve(B, tol=1e-10)
     assert info.max_relres <= 1e-10 and ainfo.max_relres <= 1e-10
     assert 1 <= info.ir_iters <= 4
-    assert rel(X.cpu().numpy(), Xo) < 1e-8
-    assert rel(L.cpu().numpy(), Lo) < 1e-8
+    assert_cols(X.cpu().numpy(), Xo, 1e-8, what="forward")
+    assert_cols(L.cpu().numpy(), Lo, 1e-8, what="adjoint")
 
 
 def test_point_sources_c1(helm):
@@ -162,7 +157,7 @@ def test_point_sources_c1(helm):
     Uo = oracle.Factor(g, w.m, w.omegas[0]).solve(E)
     F = helm.factor(helm.Grid.of(w), w.m, w.omegas[0])
     U, info = F.solve(E, tol=1e-10)
-    assert rel(U.cpu().numpy(), Uo) < 1e-11
+    assert_cols(U.cpu().numpy(), Uo, 1e-11, what="C1 wavefields")
     assert info.max_relres < 1e-12
 
 
@@ -175,7 +170,7 @@ def test_residual_kernel_matches_oracle(helm):
     for adj in (False, True):
         r, norms = helm.residual(helm.Grid.of(w), w.m, w.omegas[0], B, X, adjoint=adj)
         ro = B - oracle.apply(g, w.m, w.omegas[0], X, adjoint=adj)
-        assert rel(r.cpu().numpy(), ro) < 1e-14
+        assert_cols(r.cpu().numpy(), ro, 1e-14, what="residual")
         n = norms.cpu().numpy()
         np.testing.assert_allclose(n[:, 0], np.sum(np.abs(ro) ** 2, axis=1), rtol=1e-12)
         np.testing.assert_allclose(n[:, 1], np.sum(np.abs(B) ** 2, axis=1), rtol=1e-12)
@@ -269,62 +264,8 @@ def test_gn_hvp_matches_oracle(helm, precision):
     hv_o, hvr_o = oracle.gn_hvp(g, w.m, w.omegas, w.sources, w.receivers, w.directions, alpha=1e-3, mu=1e-6)
     hv, info = helm.gn_hvp(helm.Grid.of(w), w.m, w.omegas, w.sources, w.receivers, np.array(w.directions),
                            alpha=1e-3, mu=1e-6, precision=precision, tol=1e-10)
-    assert rel(hv.cpu().numpy(), hvr_o) < 1e-8
+    for a in range(len(w.directions)):
+        assert rel(hv.cpu().numpy()[a], hvr_o[a]) < 1e-8, a
     # u, v and z solves: S + 2 * S * n_dir per frequency
     S, D = len(w.sources), len(w.directions)
     assert info.solves >= len(w.omegas) * (S + 2 * S * D)
-
-
-# --------------------------------------------------------- full-size checks --
-
-@pytest.mark.slow
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-def test_c3_size_residual_and_sampled_parity(helm, precision):
-    """401^2 at the highest frequency (10 PPW), in the launch configuration the
-    benchmark uses: relative residual <= 1e-10 for all 64 sources, and the
-    wavefield of three sources equal to the oracle's."""
-    w = I.config_c3()
-    omega = w.omegas[-1]
-    G = helm.Grid.of(w)
-    E = I.point_sources(G.N, w.sources)
-    F = helm.factor(G, w.m, omega, precision)
-    U, info = F.solve(E, tol=1e-10)
-    assert info.max_relres <= 1e-10
-    g = oracle.Grid.of(w)
-    pick = [0, 31, 63]
-    Uo = oracle.Factor(g, w.m, omega).solve(oracle.unit_sources(g, w.sources[pick]))
-    assert rel(U[pick].cpu().numpy(), Uo) < 1e-9
-
-
-@pytest.mark.slow
-def test_c3_bench_configuration_pipelined_parity(helm):
-    """The benchmark's own configuration: the five 401^2 systems factored in
-    one batch (ten fronts per launch) with complex64 factors, two batches in
-    flight (the second factored while the first is solved), every one of the
-    5 x 64 solutions at relative residual <= 1e-10 in both batches, and
-    sampled wavefields of the batch solved under overlap equal to the
-    oracle's at the lowest and the highest frequency."""
-    from paper_2301_10762_amd.pipeline import Batch, Pipeline
-    w = I.config_c3()
-    G = helm.Grid.of(w)
-    n_omega = len(w.omegas)
-    m_dev = torch.as_tensor(w.m, dtype=torch.float64, device="cuda")
-    E = torch.as_tensor(I.point_sources(G.N, w.sources), device="cuda")
-    print("401^2 x 5 frequencies x 64 sources, two batches in flight", flush=True)
-    res = Pipeline().run([Batch([G] * n_omega, [m_dev] * n_omega, w.omegas, [E] * n_omega, "fp32_ir", 1e-10)
-                          for _ in range(2)])
-    torch.cuda.synchronize()
-    for Xs, infos in res:
-        assert len(Xs) == n_omega
-        assert max(i.max_relres for i in infos) <= 1e-10
-    g = oracle.Grid.of(w)
-    pick = [5, 40]
-    for iw in (0, n_omega - 1):
-        print(f"oracle at omega {w.omegas[iw]:.3f}", flush=True)
-        F = oracle.Factor(g, w.m, w.omegas[iw])
-        Uo = F.solve(oracle.unit_sources(g, w.sources[pick]))
-        F.close()
-        U = res[1][0][iw][pick].cpu().numpy()
-        assert rel(U, Uo) < 1e-9, iw
-        # the two batches ran the same kernels on the same data
-        assert torch.equal(res[0][0][iw], res[1][0][iw])

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_cols, rel
 from paper_2301_10762_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -24,11 +25,6 @@ def helm():
     from paper_2301_10762_amd import helm as h
     h.lib()
     return h
-
-
-def rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 # (n, model seed, points per wavelength of each frequency, sources)
@@ -77,7 +73,7 @@ def test_serving_alone_equals_mixed_and_matches_oracle(helm, precision):
             F = oracle.Factor(g, models[r.rid], w)
             Xo = F.solve(oracle.unit_sources(g, src))
             F.close()
-            assert rel(r.X[q].cpu().numpy(), Xo) < 1e-9, (r.rid, q)
+            assert_cols(r.X[q].cpu().numpy(), Xo, 1e-9, what=f"request {r.rid}, frequency {q}")
 
 
 def test_serving_resident_factors_reused(helm):

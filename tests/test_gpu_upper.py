@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_cols, rel
 from paper_2301_10762_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -25,12 +26,6 @@ def helm():
     from paper_2301_10762_amd import helm as h
     h.lib()
     return h
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _points(g, n, seed, margin=0.0):
@@ -55,7 +50,7 @@ def test_restrict_matches_oracle(helm, nx, nz):
     for deriv in (0, 1, 2):
         out = helm.restrict(G, P, U, deriv).cpu().numpy()
         ref = (S.matrix(deriv) @ U.T).T
-        assert rel(out, ref) < 1e-13, deriv
+        assert_cols(out, ref, 1e-13, what=f"restriction, derivative {deriv}")
 
 
 def test_restrict_rejects_outside_points(helm):
@@ -89,7 +84,7 @@ def test_context_at_points_matches_oracle(helm, precision):
         hv, _ = Hc.apply(np.array(w.directions))
         assert abs(Hc.phi - phi_o) <= 1e-9 * phi_o
         assert rel(Hc.grad.cpu().numpy(), grad_o) < 1e-8
-        assert rel(hv.cpu().numpy(), Ho) < 1e-8
+        assert_cols(hv.cpu().numpy(), np.asarray(Ho), 1e-8, what="H m~ per direction")
     finally:
         Hc.close()
 
