@@ -111,6 +111,25 @@ int helm_solve(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, i
 int helm_adjoint_solve(helm_factor_t f, const double* R_dev, double* L_dev, int32_t S, int64_t ld,
                        double tol, void* stream, helm_info* info);
 
+/* helm_solve_noalloc: helm_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same arguments, kernels and results as helm_solve
+ * (bitwise), but every scratch buffer of the call (sweep coupling vectors,
+ * residual partials and norms, the complex64 right-hand side and correction
+ * of the refinement, or the complex128 ones of an FP64 refinement) comes
+ * from one fixed 256 MiB region of device memory that the library holds on
+ * each GPU it runs on until the process ends; the call performs no device
+ * allocation or free.  A solve whose scratch would exceed 256 MiB returns
+ * HELM_EINVAL before any launch (at 401^2: up to 64 columns with complex64
+ * factors; with complex128 factors up to 48 columns when tol > 0, any
+ * number otherwise).  The region of the current device is used, so call
+ * with the factor's device current.  Every call on one GPU shares that
+ * GPU's region: calls that overlap in time on one GPU (other threads, or
+ * other streams while an earlier call's kernels still run) race on it.
+ * Nothing in the region needs to start at zero.                            */
+int helm_solve_noalloc(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, int64_t ld,
+                       double tol, void* stream, helm_info* info);
+
 /* helm_solve_batch: the same as helm_solve for `count` factors at once (the
  * sweeps of all factors share kernel launches).  Bs/Xs/Ss/lds per factor.  */
 int helm_solve_batch(int32_t count, const helm_factor_t* fs, const double* const* B_devs,

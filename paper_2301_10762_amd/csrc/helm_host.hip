@@ -207,15 +207,45 @@ DevCache g_cache;
 
 // scratch memory, returned to the cache on scope exit (after the work that
 // uses it, in stream order)
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// A fixed device region lent to the Scratch objects of one call: bump
+// allocation in 256-byte steps, given back in LIFO order as the Scratch
+// scopes end.  While an Arena is installed on a thread (ArenaScope), every
+// Scratch of that thread takes its memory from it and none from the cache.
+struct Arena {
+    char* base;
+    size_t cap, used;
+};
+thread_local Arena* g_arena = nullptr;
+struct ArenaScope {
+    Arena* prev;
+    explicit ArenaScope(Arena* a) : prev(g_arena) { g_arena = a; }
+    ~ArenaScope() { g_arena = prev; }
+};
+
 struct Scratch {
     hipStream_t st;
     std::vector<std::pair<void*, size_t>> ptrs;
-    explicit Scratch(hipStream_t s) : st(s) {}
+    Arena* arena;
+    size_t mark;
+    explicit Scratch(hipStream_t s) : st(s), arena(g_arena), mark(g_arena ? g_arena->used : 0) {}
     ~Scratch() {
+        if (arena) {
+            arena->used = mark;
+            return;
+        }
         for (auto& pb : ptrs) g_cache.put(pb.first, pb.second, st);
     }
     template <typename T>
     int get(T** out, size_t bytes) {
+        if (arena) {
+            const size_t off = al256(arena->used);
+            if (off + bytes > arena->cap) return fail(HELM_ENOMEM, "scratch beyond the fixed region");
+            arena->used = off + bytes;
+            *out = (T*)(arena->base + off);
+            return HELM_OK;
+        }
         void* p = nullptr;
         hipError_t e = g_cache.get(&p, bytes, st);
         if (e != hipSuccess) return fail(HELM_ENOMEM, std::string("scratch allocation failed: ") + hipGetErrorString(e));
@@ -1778,6 +1808,52 @@ int fwi_run(Fwi& P, double* x, const helm_lbfgs_opts& o, double* hist, helm_fwi_
 
 }  // namespace
 
+// ------------------------------------------------------ allocation-free solve --
+// The scratch of helm_solve_noalloc: a fixed device array.  Host code never
+// passes `scratch` itself (on the host it names a stand-in, not device
+// memory); it uses the address hipGetSymbolAddress gives on each device.
+constexpr size_t NOALLOC_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+
+// device address of the current device's copy of `scratch`, looked up once
+// per device
+int noalloc_region(void** out) {
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return fail(HELM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(HELM_EDEVICE, "no device address for the fixed scratch region");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return HELM_OK;
+}
+
+// Peak scratch of solve_jobs for one factor and S right-hand sides: the
+// sweep buffers (sweep_group) or the residual partials and norms
+// (residual_norms*), on top of the complex64 right-hand side and correction
+// (complex64 factors) or, when a tolerance is given, the complex128
+// residual and correction of an FP64 refinement (complex128 factors).
+size_t solve_scratch_bytes(const helm_factor_s* f, int S, double tol) {
+    const size_t es = elem_bytes(f->prec), N = (size_t)N_of(f->g), s16 = (size_t)((S + 15) & ~15);
+    const size_t sweep = al256(5 * ((size_t)f->np * s16 * es + 256));
+    const size_t nblk = (N + 255) / 256;
+    const size_t resid = al256(sizeof(double) * 2 * nblk * S) + al256(sizeof(double) * 2 * S);
+    const size_t phase = std::max(sweep, resid);
+    if (f->prec == HELM_FP32_IR) return 2 * al256(sizeof(float) * 2 * N * S) + phase;
+    if (tol <= 0.0) return sweep;
+    return 2 * al256(sizeof(double) * 2 * N * S) + phase;
+}
+}  // namespace
+
 // ======================================================================= ABI ==
 extern "C" {
 
@@ -1845,6 +1921,23 @@ int helm_solve(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, i
                helm_info* info) {
     int rc = check_solve_args(f, B_dev, X_dev, S, ld);
     if (rc) return rc;
+    std::vector<SolveJob> jobs{{f, B_dev, X_dev, S, ld, info}};
+    return solve_jobs(jobs, false, tol, S_(stream));
+}
+
+int helm_solve_noalloc(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, int64_t ld, double tol,
+                       void* stream, helm_info* info) {
+    int rc = check_solve_args(f, B_dev, X_dev, S, ld);
+    if (rc) return rc;
+    const size_t need = solve_scratch_bytes(f, S, tol);
+    if (need > NOALLOC_BYTES)
+        return fail(HELM_EINVAL, "this solve needs " + std::to_string(need) +
+                                     " bytes of scratch; the allocation-free limit is " +
+                                     std::to_string(NOALLOC_BYTES) + " bytes");
+    void* base = nullptr;
+    if ((rc = noalloc_region(&base))) return rc;
+    Arena arena{(char*)base, NOALLOC_BYTES, 0};
+    ArenaScope scope(&arena);
     std::vector<SolveJob> jobs{{f, B_dev, X_dev, S, ld, info}};
     return solve_jobs(jobs, false, tol, S_(stream));
 }

@@ -100,6 +100,7 @@ def lib():
     L.helm_factor_destroy.restype = None
     L.helm_solve.argtypes = [_vp, _vp, _vp, i32, i64, f64, _vp, I]
     L.helm_adjoint_solve.argtypes = [_vp, _vp, _vp, i32, i64, f64, _vp, I]
+    L.helm_solve_noalloc.argtypes = [_vp, _vp, _vp, i32, i64, f64, _vp, I]
     L.helm_solve_batch.argtypes = [i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                    ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.c_int, f64, _vp, I]
     L.helm_misfit_grad.argtypes = [G, _vp, i32, ctypes.POINTER(f64), _vp, i32, ctypes.POINTER(i32), i32,
@@ -304,6 +305,21 @@ def solve(F: Factor, B, tol: float = 0.0, stream=None):
     _check(lib().helm_solve(F.handle, _ptr(B), _ptr(X), B.shape[0], F.grid.N, float(tol), _stream(stream),
                             ctypes.byref(info)))
     return X, Info.of(info)
+
+
+def solve_noalloc(F: Factor, B, X, tol: float = 0.0, stream=None):
+    """X = A^{-1} B into the caller's X with no device allocation: the
+    call's scratch comes from the library's fixed per-device region
+    (helm_solve_noalloc).  B and X are complex128 [S][nx*nz] device tensors.
+    Returns Info."""
+    if B.dtype != X.dtype or B.shape != X.shape or B.dim() != 2 or B.shape[-1] != F.grid.N:
+        raise ValueError("B and X must be [S][nx*nz] tensors of the same shape")
+    if not (B.is_contiguous() and X.is_contiguous()) or str(B.dtype) != "torch.complex128":
+        raise ValueError("B and X must be contiguous complex128")
+    info = _Info()
+    _check(lib().helm_solve_noalloc(F.handle, _ptr(B), _ptr(X), B.shape[0], F.grid.N, float(tol), _stream(stream),
+                                    ctypes.byref(info)))
+    return Info.of(info)
 
 
 def adjoint_solve(F: Factor, R, tol: float = 0.0, stream=None):
