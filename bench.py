@@ -62,6 +62,9 @@ def parse():
                    help="only run phi + grad phi (forward + adjoint + gradient assembly) at the 401^2 workload")
     p.add_argument("--hessian-only", action="store_true",
                    help="only run the full-Hessian, PCG, upper-level gradient and FWI measurements at 201^2")
+    p.add_argument("--oracle-worker", action="store_true",
+                   help="internal: time the CPU oracle on one 401^2 frequency and print one JSON line "
+                        "(the single-core leg of the CPU baseline, run as a child process)")
     return p.parse_args()
 
 
@@ -101,6 +104,104 @@ def read_traffic(prec):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model():
+    """The host CPU's model name and the cores this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def oracle_worker():
+    """Single-core leg of the CPU baseline (run with OMP_NUM_THREADS=1 as a
+    child process): the oracle's banded-LU factor and all 64 source solves of
+    the 6 Hz system of the 401^2 workload."""
+    import oracle
+    from paper_2301_10762_amd import inputs as I
+    w = I.config_c3()
+    g = oracle.Grid.of(w)
+    t0 = time.perf_counter()
+    F = oracle.Factor(g, w.m, w.omegas[-1])
+    F.solve(oracle.unit_sources(g, w.sources))
+    t = time.perf_counter() - t0
+    F.close()
+    print(json.dumps({"seconds": t, "threads": oracle.num_threads(), "solves": len(w.sources)}), flush=True)
+
+
+def start_single_core_oracle():
+    """Start the single-core oracle timing in a child process (it runs while
+    the GPU is measured, on one of the host's cores)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker"], env=env,
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_baseline(w, X_gpu, proc1):
+    """The CPU oracle on the whole 401^2 workload with all host cores: the
+    banded-LU factor of each of the five systems and all 64 source solves,
+    timed per frequency.  Its solutions also give the error of the GPU's
+    solutions (X_gpu: precision -> five [S][N] arrays) per frequency: the
+    relative 2-norm error of every column, the worst over the 64 sources,
+    and the same in the max-norm.  proc1: the single-core child process."""
+    import numpy as np
+    import oracle
+    # the single-core child first: a busy core would slow the all-core run
+    one = None
+    if proc1 is not None:
+        out, errtxt = proc1.communicate(timeout=1800)
+        if proc1.returncode == 0 and out.strip():
+            r = json.loads(out.strip().splitlines()[-1])
+            one = {"value": round(r["solves"] / r["seconds"], 3), "seconds": round(r["seconds"], 2),
+                   "threads": r["threads"]}
+        else:
+            one = {"error": (errtxt or "")[-300:]}
+    g = oracle.Grid.of(w)
+    E = oracle.unit_sources(g, w.sources)
+    S = len(w.sources)
+    per, err = [], {}
+    total = 0.0
+    worst_rr = 0.0
+    for iw, om in enumerate(w.omegas):
+        t0 = time.perf_counter()
+        F = oracle.Factor(g, w.m, om)
+        Xo = F.solve(E)
+        tc = time.perf_counter() - t0
+        F.close()
+        total += tc
+        worst_rr = max(worst_rr, float(oracle.relres(g, w.m, om, Xo[:4], E[:4]).max()))
+        key = f"{om / (2 * math.pi):.2f}Hz"
+        per.append({"frequency": key, "seconds": round(tc, 2)})
+        err[key] = {}
+        for prec, Xs in X_gpu.items():
+            d = Xs[iw] - Xo
+            e2 = np.linalg.norm(d, axis=1) / np.linalg.norm(Xo, axis=1)
+            ei = np.abs(d).max(axis=1) / np.abs(Xo).max(axis=1)
+            err[key][prec] = {"max_over_sources": float(e2.max()), "max_norm": float(ei.max())}
+    name, avail = cpu_model()
+    n_omega = len(w.omegas)
+    base = {"value": round(n_omega * S / total, 3), "unit": "solves/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"the whole 401^2 workload: banded-LU factor + all {S} source solves of each of the "
+                      f"{n_omega} frequencies, {total:.1f} s in all; rel. residual <= {worst_rr:.1e}",
+            "per_frequency": per, "cpu_model": name, "cores_available": avail}
+    if one is not None:
+        base["cores_1_value"] = one.get("value")
+        base["cores_1_sample"] = ("one frequency (6 Hz) of the 401^2 workload, factor + 64 solves, "
+                                  f"{one.get('seconds')} s on {one.get('threads')} thread(s), timed while the "
+                                  "GPU part of the benchmark ran") if "value" in one else one.get("error")
+    worst = {p: max(err[k][p]["max_over_sources"] for k in err) for p in X_gpu}
+    return base, {"per_frequency": err, "worst": worst,
+                  "definition": "per frequency: max over the 64 sources of ||x_s - x_s^oracle|| / "
+                                "||x_s^oracle|| (and of the max-norm form), x from the GPU's serial step"}
 
 
 def per_omega_latency(helm, w, G, m_dev, E, prec, reps=20, warm=3):
@@ -351,6 +452,9 @@ def fwi_extra(helm, I, precision="fp64", max_iters=20, n_data=301):
 
 def main():
     args = parse()
+    if args.oracle_worker:
+        oracle_worker()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the systems of this workload are independent per "
@@ -396,6 +500,9 @@ def main():
         return
     X = [torch.empty_like(E) for _ in range(n_omega)]
     torch.cuda.synchronize()
+    # the single-core oracle runs beside the GPU measurements
+    proc1 = None if args.no_cpu_baseline else start_single_core_oracle()
+    X_gpu = {}
 
     def step(precision):
         Fs = helm.factor_batch([G] * n_omega, [m_dev] * n_omega, w.omegas, precision)
@@ -459,6 +566,8 @@ def main():
     solves = n_omega * S * args.steps
     serial = {"value": round(solves / total_s, 2), "ms_per_step": round(total_s / args.steps * 1e3, 3),
               "p50_ms": round(percentile(lat, 0.5), 3), "p99_ms": round(percentile(lat, 0.99), 3)}
+    if not args.no_cpu_baseline:
+        X_gpu["c64_ir" if prec == "fp32_ir" else "c128"] = [x.cpu().numpy() for x in X]
     # headline: the pipelined schedule
     if args.schedule == "both":
         total, infos_p = run_pipelined(prec, args.warmup, args.steps)
@@ -494,6 +603,8 @@ def main():
     fsteps = args.fp64_steps if args.fp64_steps is not None else args.steps
     if prec != "fp64" and fsteps > 0:
         t64, lat64, inf64, _ = run("fp64", 1, fsteps, False)
+        if not args.no_cpu_baseline:
+            X_gpu["c128"] = [x.cpu().numpy() for x in X]
         tp64 = run_pipelined("fp64", 1, fsteps)[0] if args.schedule == "both" else t64
         v64 = n_omega * S * fsteps / tp64
         fp64 = {"value": round(v64, 2), "ms_per_step": round(tp64 / fsteps * 1e3, 3),
@@ -558,20 +669,9 @@ def main():
         extras["serving_c5_pipelined"] = SV.run_c5(requests=192, rate=200.0, precision=prec)
         extras["serving_150"] = SV.run_c5(requests=192, rate=150.0, precision=prec, lanes=3)
 
-    cpu = None
+    cpu, oracle_err = None, None
     if not args.no_cpu_baseline:
-        import oracle
-        g = oracle.Grid.of(w)
-        om = w.omegas[-1]
-        t0 = time.perf_counter()
-        F = oracle.Factor(g, w.m, om)
-        Xo = F.solve(oracle.unit_sources(g, w.sources))
-        tc = time.perf_counter() - t0
-        rr = float(oracle.relres(g, w.m, om, Xo[:4], oracle.unit_sources(g, w.sources[:4])).max())
-        F.close()
-        cpu = {"value": round(S / tc, 3), "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"one of the five frequencies (6 Hz, 10 PPW) of the 401^2 workload: banded-LU factor "
-                         f"+ all {S} source solves, {tc:.1f} s, rel. residual {rr:.1e}"}
+        cpu, oracle_err = cpu_baseline(w, X_gpu, proc1)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -590,7 +690,8 @@ def main():
         "serial": serial,
         "p50_ms": serial["p50_ms"], "p99_ms": serial["p99_ms"],
         "ir_iters": max(i.ir_iters for i in infos), "max_relres": max(i.max_relres for i in infos),
-        "fp64_plain": fp64, "extras": extras, "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+        "fp64_plain": fp64, "error_vs_oracle": oracle_err, "extras": extras, "roofline": roofline,
+        "kernels": kernels, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
