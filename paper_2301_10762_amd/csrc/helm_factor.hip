@@ -470,13 +470,13 @@ int factor_step_blocks(int np) { return step_blocks(np); }
 // D = A_{row0} into the first block of each front, and the inverse of its
 // first diagonal tile
 template <typename T>
-__global__ __launch_bounds__(256) void k_factor_init(const ChainTab tab, int n) {
+__global__ __launch_bounds__(256) void k_factor_init(const ChainTab* __restrict__ tab, int n) {
     using C = typename CT<T>::c;
     __shared__ C M[32][33];
     __shared__ C L2[2 * 32 * 33];
     __shared__ GJScratch<T> sh;
-    const int ci = find_chain(tab.c, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
-    const ChainInfo d = tab.c[ci];
+    const int ci = find_chain(tab->c, n, blockIdx.x, [](const ChainInfo& c) { return c.itile0; });
+    const ChainInfo d = load_entry(tab->c, ci);
     const int local = blockIdx.x - d.itile0;
     const int np = d.np;
     const int nfill = init_blocks(np) - 1;
@@ -841,18 +841,37 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 // Workgroups 0 .. n-1 of a step launch prepare the next diagonal tile of
 // chains 0 .. n-1 (the critical path of the step, so they are dispatched
 // first); the rest update the 64 x 64 tiles, chain by chain (ftile0).
-// uni > 0: every chain has uni - 1 update workgroups.
+// uni > 0: every chain has uni - 1 update workgroups, laid out by XCD
+// (xcd_tile); otherwise in launch order.
+// Update tile served by workgroup b (>= n) when consecutive tiles (front by
+// front, tile row by tile row) are kept on one XCD: workgroup b runs on XCD
+// b % 8, so XCD x takes the contiguous range of tiles after those of XCDs
+// 0 .. x-1, and the panel rows, columns and T of a front are fetched into
+// one or two L2s instead of all eight.  total = n + update tiles.
+__device__ __forceinline__ int xcd_tile(int b, int n, int total) {
+    const int x = b & 7, k = b >> 3;
+    int start = 0, leads_x = 0;
+#pragma unroll
+    for (int y = 0; y < 8; ++y) {
+        const int wgs = total > y ? (total - 1 - y) / 8 + 1 : 0;
+        const int leads = n > y ? (n - 1 - y) / 8 + 1 : 0;
+        if (y < x) start += wgs - leads;
+        if (y == x) leads_x = leads;
+    }
+    return start + k - leads_x;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_factor_step(int n, int tstep, int uni, const ChainTab tab) {
+__global__ __launch_bounds__(256, 2) void k_factor_step(int n, int tstep, int uni, const ChainTab* __restrict__ tab) {
     using C = typename CT<T>::c;
     __shared__ __attribute__((aligned(16))) char smem[sm_bytes<T>()];
     const int b = blockIdx.x;
     const bool nxt = b < n;
-    const int u = b - n;
+    const int u = (!nxt && uni > 0) ? xcd_tile(b, n, n * uni) : b - n;
     const int ci = nxt ? b
                        : uni > 0 ? (int)((unsigned)u / (unsigned)(uni - 1))
-                                 : find_chain(tab.c, n, u, [](const ChainInfo& c) { return c.ftile0; });
-    const ChainInfo d = load_entry(tab.c, ci);
+                                 : find_chain(tab->c, n, u, [](const ChainInfo& c) { return c.ftile0; });
+    const ChainInfo d = load_entry(tab->c, ci);
     if (tstep >= d.T) return;
     const PanelStep ps = panel_step(d, tstep);
     const int np = d.np;
@@ -894,16 +913,19 @@ __global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const d
     if (t == 0 && small) status[blockIdx.x] = -1;
 }
 
-void launch_factor_init(const ChainTab& tab, int n, int total, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_factor_init<float>, dim3(total), dim3(256), 0, st, tab, n);
-    else hipLaunchKernelGGL(k_factor_init<double>, dim3(total), dim3(256), 0, st, tab, n);
+void launch_factor_init(const ChainTab* dtab, int n, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_factor_init<float>, dim3(total), dim3(256), 0, st, dtab, n);
+    else hipLaunchKernelGGL(k_factor_init<double>, dim3(total), dim3(256), 0, st, dtab, n);
 }
-void launch_factor_step(const ChainTab& tab, int n, int t, int total, bool fp32, hipStream_t st) {
+int factor_uniform(const ChainTab& tab, int n) {
     int uni = step_blocks(tab.c[0].np);
     for (int q = 0; q < n; ++q)
         if (tab.c[q].ftile0 != q * (uni - 1) || step_blocks(tab.c[q].np) != uni) uni = 0;
-    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, n, t, uni, tab);
-    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, n, t, uni, tab);
+    return uni;
+}
+void launch_factor_step(const ChainTab* dtab, int n, int t, int uni, int total, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_factor_step<float>, dim3(total), dim3(256), 0, st, n, t, uni, dtab);
+    else hipLaunchKernelGGL(k_factor_step<double>, dim3(total), dim3(256), 0, st, n, t, uni, dtab);
 }
 void launch_tile_inverse(int count, int kb, int pivot, const double* A, double* T, int* status, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_inverse, dim3(count), dim3(256), 0, st, kb, pivot, (const double2*)A, (double2*)T,

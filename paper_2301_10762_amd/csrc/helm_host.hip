@@ -365,6 +365,8 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
     int* status;
     if ((rc = sc.get(&status, sizeof(int) * 4 * 2 * n))) return rc;
     launch_zero(status, sizeof(int) * 4 * 2 * n, st);
+    ChainTab* dtab;
+    if ((rc = sc.get(&dtab, sizeof(ChainTab)))) return rc;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void* p = arena + off;
@@ -412,17 +414,19 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
             ++nf;
         }
     }
+    launch_put_chain_table(ctab, dtab, st);
     {
         KernelTimer::Pair pi;
         const bool ti = g_timer.begin(1, st, &pi);
-        launch_factor_init(ctab, nf, itot, fp32, st);
+        launch_factor_init(dtab, nf, itot, fp32, st);
         if (ti) g_timer.end(pi, 1, st);
     }
+    const int uni = factor_uniform(ctab, nf);
     KernelTimer::Pair pu;
     const bool tu = g_timer.begin(0, st, &pu);
-    for (int t = 0; t < Tmax; ++t) launch_factor_step(ctab, nf, t, utot, fp32, st);
+    for (int t = 0; t < Tmax; ++t) launch_factor_step(dtab, nf, t, uni, utot, fp32, st);
     if (tu) g_timer.end(pu, Tmax, st);
-    g_launches += 1 + (int64_t)Tmax;
+    g_launches += 2 + (int64_t)Tmax;
     HIPCHECK(hipGetLastError());
     std::vector<int> hs(4 * 2 * n);   // statuses (room for 2 fronts per system)
     HIPCHECK(hipMemcpyAsync(hs.data(), status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, st));
@@ -525,6 +529,8 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     char* arena;
     int rc = sc.get(&arena, buf);
     if (rc) return rc;
+    SweepTab* dtab;
+    if ((rc = sc.get(&dtab, sizeof(SweepTab)))) return rc;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void* p = arena + off;
@@ -580,20 +586,22 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
         }
         g_solves += Ss[c];
     }
-    launch_sweep_init(stab, nf, itot, fp32, conj_b, st);
+    launch_put_sweep_table(stab, dtab, st);
+    launch_sweep_init(dtab, nf, itot, fp32, conj_b, st);
+    const int uni = sweep_uniform(stab, nf);
     {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < fsteps; ++t) launch_sweep(stab, nf, t, groups, st_max, fp32, true, conj_b, st);
+        for (int t = 0; t < fsteps; ++t) launch_sweep(dtab, nf, t, uni, groups, st_max, fp32, true, conj_b, st);
         if (tm) g_timer.end(p, fsteps, st);
     }
     if (bsteps > 0) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < bsteps; ++t) launch_sweep(stab, nf, t, groups, st_max, fp32, false, false, st);
+        for (int t = 0; t < bsteps; ++t) launch_sweep(dtab, nf, t, uni, groups, st_max, fp32, false, false, st);
         if (tm) g_timer.end(p, bsteps, st);
     }
-    g_launches += 1 + (int64_t)fsteps + bsteps;
+    g_launches += 2 + (int64_t)fsteps + bsteps;
     HIPCHECK(hipGetLastError());
     return HELM_OK;
 }
@@ -1844,7 +1852,7 @@ int noalloc_region(void** out) {
 // residual and correction of an FP64 refinement (complex128 factors).
 size_t solve_scratch_bytes(const helm_factor_s* f, int S, double tol) {
     const size_t es = elem_bytes(f->prec), N = (size_t)N_of(f->g), s16 = (size_t)((S + 15) & ~15);
-    const size_t sweep = al256(5 * ((size_t)f->np * s16 * es + 256));
+    const size_t sweep = al256(5 * ((size_t)f->np * s16 * es + 256)) + al256(sizeof(SweepTab));
     const size_t nblk = (N + 255) / 256;
     const size_t resid = al256(sizeof(double) * 2 * nblk * S) + al256(sizeof(double) * 2 * S);
     const size_t phase = std::max(sweep, resid);

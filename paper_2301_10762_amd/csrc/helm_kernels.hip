@@ -502,6 +502,23 @@ __global__ void k_mfma_probe(int prec, const double* A, const double* B, double*
 // ---------------------------------------------------------------- launchers --
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+// A group's front table into device memory (one workgroup, one dword per
+// thread), in stream order before the group's launches.
+template <typename Tab>
+__global__ __launch_bounds__(256) void k_put_table(const Tab src, Tab* dst) {
+    static_assert(sizeof(Tab) % 4 == 0, "tables are whole dwords");
+    constexpr int W = (int)(sizeof(Tab) / 4);
+    const uint32_t* s = (const uint32_t*)&src;
+    uint32_t* d = (uint32_t*)dst;
+    for (int i = threadIdx.x; i < W; i += 256) d[i] = s[i];
+}
+void launch_put_chain_table(const ChainTab& tab, ChainTab* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_put_table<ChainTab>, dim3(1), dim3(256), 0, st, tab, dst);
+}
+void launch_put_sweep_table(const SweepTab& tab, SweepTab* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_put_table<SweepTab>, dim3(1), dim3(256), 0, st, tab, dst);
+}
+
 void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_check_model, grid1(n), dim3(256), 0, st, m, n, flag);
 }

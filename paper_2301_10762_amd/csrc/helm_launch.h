@@ -8,14 +8,23 @@ namespace helm {
 // workgroups per chain of the factorisation launches
 int factor_init_blocks(int np);
 int factor_step_blocks(int np);
-void launch_factor_init(const ChainTab& tab, int n, int total_blocks, bool fp32, hipStream_t st);
-void launch_factor_step(const ChainTab& tab, int n, int t, int total_blocks, bool fp32, hipStream_t st);
+// The per-front tables are read by the kernels from device memory: the host
+// writes a group's table once (launch_put_*_table, a one-workgroup copy in
+// stream order) and every launch of the group reads it there.
+void launch_put_chain_table(const ChainTab& tab, ChainTab* dst, hipStream_t st);
+void launch_put_sweep_table(const SweepTab& tab, SweepTab* dst, hipStream_t st);
+void launch_factor_init(const ChainTab* dtab, int n, int total_blocks, bool fp32, hipStream_t st);
+// uni: factor_uniform() of the group's table (every front has uni workgroups, or 0)
+int factor_uniform(const ChainTab& tab, int n);
+void launch_factor_step(const ChainTab* dtab, int n, int t, int uni, int total_blocks, bool fp32, hipStream_t st);
 // y = b_{row0} (conjugated for adjoint solves) into Y0 of every front
-void launch_sweep_init(const SweepTab& tab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
+void launch_sweep_init(const SweepTab* dtab, int n, int total_blocks, bool fp32, bool conj_b, hipStream_t st);
 // forward step t: row row0 + dir * t of each front; backward step t: row
 // brow0 - dir * t.  `groups` row tiles (16 rows) over all fronts, `st` column
 // tiles (16 columns).
-void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp32, bool forward,
+// uni: sweep_uniform() of the group's table (every front has uni row tiles, or 0)
+int sweep_uniform(const SweepTab& tab, int n);
+void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int groups, int st, bool fp32, bool forward,
                   bool conj_b, hipStream_t st_);
 int sweep_row_tiles(int np);
 int sweep_col_tiles(int S);

@@ -32,10 +32,10 @@ __device__ __forceinline__ C conj_if(C v, bool c) {
 
 // y = b_{row0} into Y0 (B-operand layout; rows >= nx and columns >= S zero)
 template <typename T, bool CONJB>
-__global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
+__global__ __launch_bounds__(256) void k_sweep_init(const SweepTab* __restrict__ tab, int n) {
     using C = typename CT<T>::c;
-    const int ci = find_chain(tab.c, n, blockIdx.x, [](const SweepInfo& c) { return c.itile0; });
-    const SweepInfo d = tab.c[ci];
+    const int ci = find_chain(tab->c, n, blockIdx.x, [](const SweepInfo& c) { return c.itile0; });
+    const SweepInfo d = load_entry(tab->c, ci);
     const int s16 = (d.S + 15) & ~15;
     const int64_t e = (int64_t)(blockIdx.x - d.itile0) * 256 + threadIdx.x;
     if (e >= (int64_t)d.np * s16) return;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab tab, int n) {
 // (consecutive workgroups go to consecutive XCDs) and share its L2.
 template <typename T, bool FWD, bool CONJB>
 __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int groups, int cgroups, int uni,
-                                                        const SweepTab tab) {
+                                                        const SweepTab* __restrict__ tab) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     __shared__ T red[SW_WAVES][2][4][64];
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
     if (g >= groups) return;
     // uni > 0: every front of the launch has uni row tiles
     const int ci = uni > 0 ? (int)((unsigned)g / (unsigned)uni)
-                           : find_chain(tab.c, n, g, [](const SweepInfo& c) { return c.tile0; });
-    const SweepInfo d = load_entry(tab.c, ci);
+                           : find_chain(tab->c, n, g, [](const SweepInfo& c) { return c.tile0; });
+    const SweepInfo d = load_entry(tab->c, ci);
     if (tstep >= (FWD ? d.nfwd : d.nbwd)) return;
     const int nct = (d.S + 15) >> 4, ct0 = SW_CTG * cgi;
     if (ct0 >= nct) return;
@@ -231,32 +231,36 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
     }
 }
 
-void launch_sweep_init(const SweepTab& tab, int n, int total, bool fp32, bool conj_b, hipStream_t st) {
+void launch_sweep_init(const SweepTab* dtab, int n, int total, bool fp32, bool conj_b, hipStream_t st) {
     if (fp32) {
-        if (conj_b) hipLaunchKernelGGL((k_sweep_init<float, true>), dim3(total), dim3(256), 0, st, tab, n);
-        else hipLaunchKernelGGL((k_sweep_init<float, false>), dim3(total), dim3(256), 0, st, tab, n);
+        if (conj_b) hipLaunchKernelGGL((k_sweep_init<float, true>), dim3(total), dim3(256), 0, st, dtab, n);
+        else hipLaunchKernelGGL((k_sweep_init<float, false>), dim3(total), dim3(256), 0, st, dtab, n);
     } else {
-        if (conj_b) hipLaunchKernelGGL((k_sweep_init<double, true>), dim3(total), dim3(256), 0, st, tab, n);
-        else hipLaunchKernelGGL((k_sweep_init<double, false>), dim3(total), dim3(256), 0, st, tab, n);
+        if (conj_b) hipLaunchKernelGGL((k_sweep_init<double, true>), dim3(total), dim3(256), 0, st, dtab, n);
+        else hipLaunchKernelGGL((k_sweep_init<double, false>), dim3(total), dim3(256), 0, st, dtab, n);
     }
 }
 
-void launch_sweep(const SweepTab& tab, int n, int t, int groups, int st, bool fp32, bool forward, bool conj_b,
-                  hipStream_t st_) {
-    const dim3 grid(sweep_grid(groups, st)), block(64 * SW_WAVES);
+int sweep_uniform(const SweepTab& tab, int n) {
     int uni = sweep_row_tiles(tab.c[0].np);
     for (int q = 0; q < n; ++q)
         if (tab.c[q].tile0 != q * uni || sweep_row_tiles(tab.c[q].np) != uni) uni = 0;
+    return uni;
+}
+
+void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int groups, int st, bool fp32, bool forward,
+                  bool conj_b, hipStream_t st_) {
+    const dim3 grid(sweep_grid(groups, st)), block(64 * SW_WAVES);
     if (fp32) {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, n, t, groups, st, uni, tab);
-            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
-        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
     } else {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, n, t, groups, st, uni, tab);
-            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
-        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, n, t, groups, st, uni, tab);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
     }
 }
 

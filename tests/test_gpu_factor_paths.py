@@ -73,11 +73,11 @@ def test_step_schedule_matches_oracle(helm, nx, nz, hx, hz, precision):
     launches = helm.counters()["launches"] - before
     X, info = helm.solve(F, torch.as_tensor(B, device="cuda"), tol=1e-10)
     F.close()
-    # zeroing + model check, then the initial launch and the panel steps; a
-    # group whose unpivoted tiles met a small pivot is factored again with
-    # pivoting inside the tiles
+    # zeroing + model check, then the table upload, the initial launch and the
+    # panel steps; a group whose unpivoted tiles met a small pivot is factored
+    # again with pivoting inside the tiles
     T = _steps(nx, nz)
-    assert launches in (3 + T, 4 + 2 * T), (launches, T)
+    assert launches in (4 + T, 6 + 2 * T), (launches, T)
     assert_cols(X.cpu().numpy(), _oracle(nx, nz, hx, hz, m, w, B), 1e-9, what=f"{nx}x{nz} {precision}")
     assert info.max_relres <= 1e-10
 
