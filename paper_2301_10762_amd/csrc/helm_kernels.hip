@@ -45,56 +45,96 @@ __global__ void k_zero(uint32_t* p, size_t n32) {
 
 // r = B - A X (or A^*), FP64; per-block partial sums of |r|^2 and |B|^2
 //
-// Workgroups go to the eight XCDs in turn, so the (column, 256-node block)
+// A workgroup takes one block of 256 nodes and a group of RES_CS columns:
+// each thread forms its node's stencil (the diagonal entry from m, the two
+// couplings, the boundary cases) once and applies it to every column of the
+// group.  All loads of all the group's columns are issued first, at clamped
+// (in-range) addresses, and the boundary cases are applied afterwards, so
+// none of them waits on another (with the neighbours loaded behind their
+// boundary tests, every load was followed by its own wait).  Two columns
+// per workgroup measured best at 401^2 (four and eight were slower).  The per-(column, block) partial sums keep
+// one fixed order: a shuffle tree within each wavefront, then the four
+// wavefront sums.
+//
+// Workgroups go to the eight XCDs in turn, so the (column group, block)
 // pairs are numbered to give each XCD one contiguous range of them: the rows
 // above and below a block, which the stencil reads, then belong to blocks
 // on the same XCD and come from its L2 instead of being fetched again by
 // every neighbour's XCD.  The grid has 8 * per_xcd workgroups; numbers past
-// the nblk * S pairs return at once.
-__global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const double2* B, int64_t ldb,
-                                                  const double2* X, int64_t ldx, double2* R, int64_t ldr,
-                                                  float2* R32, int S, double* partial, int nblk, int per_xcd) {
-    __shared__ double sr[4], sb[4];
+// the nblk * ceil(S / RES_CS) pairs return at once.
+constexpr int RES_CS = 2;
+
+__global__ __launch_bounds__(256) void k_residual(Coef cf, int adjoint, const double2* __restrict__ B, int64_t ldb,
+                                                  const double2* __restrict__ X, int64_t ldx,
+                                                  double2* __restrict__ R, int64_t ldr, float2* __restrict__ R32,
+                                                  int S, double* __restrict__ partial, int nblk, int per_xcd) {
+    __shared__ double sr[RES_CS][4], sb[RES_CS][4];
     const int pair = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
-    if ((int64_t)pair >= (int64_t)nblk * S) return;
-    const int s = pair / nblk, kb = pair - s * nblk;
-    const int64_t N = (int64_t)cf.nx * cf.nz;
-    const int64_t k = (int64_t)kb * 256 + threadIdx.x;
-    double rr = 0.0, bb = 0.0;
-    if (k < N) {
-        const int i = (int)(k % cf.nx), j = (int)(k / cf.nx);
+    const int ncg = (S + RES_CS - 1) / RES_CS;
+    if ((int64_t)pair >= (int64_t)nblk * ncg) return;
+    const int cg = pair / nblk, kb = pair - cg * nblk;
+    const int s0 = cg * RES_CS, ns = min(RES_CS, S - s0);
+    const int nx = cf.nx, nz = cf.nz;
+    const int N = nx * nz;                         // below 2^30 (grid check)
+    const int k0 = kb * 256 + (int)threadIdx.x;
+    const bool in = k0 < N;
+    const int k = in ? k0 : N - 1;
+    const int j = k / nx, i = k - j * nx;
+    const bool hl = i > 0, hr = i < nx - 1, hu = j > 0, hd = j < nz - 1;
+    const int kl = hl ? k - 1 : k, kr = hr ? k + 1 : k, ku = hu ? k - nx : k, kd = hd ? k + nx : k;
+    double2 xc[RES_CS], xl[RES_CS], xr[RES_CS], xu[RES_CS], xd[RES_CS], bv[RES_CS];
+#pragma unroll
+    for (int c = 0; c < RES_CS; ++c) {
+        const int s = s0 + min(c, ns - 1);
         const double2* x = X + (size_t)s * ldx;
-        double2 dg = diag_entry(cf, i, j);
-        if (adjoint) dg.y = -dg.y;
-        double2 xk = x[k];
-        double ar = dg.x * xk.x - dg.y * xk.y, ai = dg.x * xk.y + dg.y * xk.x;
-        const double cx = x_coupling(cf, j), cz = z_coupling(cf, i);
-        if (i > 0) { ar -= cx * x[k - 1].x; ai -= cx * x[k - 1].y; }
-        if (i < cf.nx - 1) { ar -= cx * x[k + 1].x; ai -= cx * x[k + 1].y; }
-        if (j > 0) { ar -= cz * x[k - cf.nx].x; ai -= cz * x[k - cf.nx].y; }
-        if (j < cf.nz - 1) { ar -= cz * x[k + cf.nx].x; ai -= cz * x[k + cf.nx].y; }
-        double2 bk = B[(size_t)s * ldb + k];
-        double2 r = make_double2(bk.x - ar, bk.y - ai);
-        if (R) R[(size_t)s * ldr + k] = r;
-        if (R32) R32[(size_t)s * ldr + k] = make_float2((float)r.x, (float)(adjoint ? -r.y : r.y));
-        rr = r.x * r.x + r.y * r.y;
-        bb = bk.x * bk.x + bk.y * bk.y;
+        xc[c] = x[k];
+        xl[c] = x[kl];
+        xr[c] = x[kr];
+        xu[c] = x[ku];
+        xd[c] = x[kd];
+        bv[c] = B[(size_t)s * ldb + k];
     }
-    // fixed-order sums: a shuffle tree within each wavefront, then the four
-    // wavefront sums in order
-    for (int o = 32; o > 0; o >>= 1) {
-        rr += __shfl_down(rr, o, 64);
-        bb += __shfl_down(bb, o, 64);
+    double2 dg = diag_entry(cf, i, j);
+    if (adjoint) dg.y = -dg.y;
+    const double cx = x_coupling(cf, j), cz = z_coupling(cf, i);
+    double rr[RES_CS], bb[RES_CS];
+#pragma unroll
+    for (int c = 0; c < RES_CS; ++c) {
+        rr[c] = 0.0;
+        bb[c] = 0.0;
+        if (in && c < ns) {
+            const int s = s0 + c;
+            double ar = dg.x * xc[c].x - dg.y * xc[c].y, ai = dg.x * xc[c].y + dg.y * xc[c].x;
+            if (hl) { ar -= cx * xl[c].x; ai -= cx * xl[c].y; }
+            if (hr) { ar -= cx * xr[c].x; ai -= cx * xr[c].y; }
+            if (hu) { ar -= cz * xu[c].x; ai -= cz * xu[c].y; }
+            if (hd) { ar -= cz * xd[c].x; ai -= cz * xd[c].y; }
+            const double2 bk = bv[c];
+            const double2 r = make_double2(bk.x - ar, bk.y - ai);
+            if (R) R[(size_t)s * ldr + k] = r;
+            if (R32) R32[(size_t)s * ldr + k] = make_float2((float)r.x, (float)(adjoint ? -r.y : r.y));
+            rr[c] = r.x * r.x + r.y * r.y;
+            bb[c] = bk.x * bk.x + bk.y * bk.y;
+        }
     }
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sr[w] = rr;
-        sb[w] = bb;
+#pragma unroll
+    for (int c = 0; c < RES_CS; ++c) {
+        double a = rr[c], e = bb[c];
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_down(a, o, 64);
+            e += __shfl_down(e, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            sr[c][w] = a;
+            sb[c][w] = e;
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        partial[((size_t)s * nblk + kb) * 2 + 0] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
-        partial[((size_t)s * nblk + kb) * 2 + 1] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    if ((int)threadIdx.x < ns) {
+        const int c = threadIdx.x;
+        partial[((size_t)(s0 + c) * nblk + kb) * 2 + 0] = (sr[c][0] + sr[c][1]) + (sr[c][2] + sr[c][3]);
+        partial[((size_t)(s0 + c) * nblk + kb) * 2 + 1] = (sb[c][0] + sb[c][1]) + (sb[c][2] + sb[c][3]);
     }
 }
 
@@ -524,7 +564,7 @@ void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st) {
 }
 void launch_residual(const Coef& cf, int adjoint, const double* B, int64_t ldb, const double* X, int64_t ldx,
                      double* R, int64_t ldr, float* R32, int S, double* partial, int nblk, hipStream_t st) {
-    const int per_xcd = (int)(((int64_t)nblk * S + 7) / 8);
+    const int per_xcd = (int)(((int64_t)nblk * ((S + RES_CS - 1) / RES_CS) + 7) / 8);
     hipLaunchKernelGGL(k_residual, dim3(8 * per_xcd), dim3(256), 0, st, cf, adjoint, (const double2*)B, ldb,
                        (const double2*)X, ldx, (double2*)R, ldr, (float2*)R32, S, partial, nblk, per_xcd);
 }
