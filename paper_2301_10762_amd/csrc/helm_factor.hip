@@ -178,109 +178,13 @@ __device__ __forceinline__ int gj_invert(typename CT<T>::c (&a)[4], GJScratch<T>
     return zero;
 }
 
-// Unpivoted Gauss-Jordan in uniform form on the 256-thread layout above
-// (thread: row r = t/8, columns 4(t%8)..+3).  Step p, with d = 1 / a_pp and
-// f = (column p) - e_p scaled to f' = f d: every entry outside column p takes
-// a_ij -= f'_i a_pj, and column p becomes e_p - f', which leaves the inverse
-// in place with no special case for the pivot row.  Row p is published with
-// its pivot entry zeroed, so the general update leaves column p untouched
-// and only the threads holding it overwrite it.  During step p the threads
-// holding column p+1 and row p+1 publish them (and one of them 1 / a_{p+1,p+1})
-// for the next step: one barrier and one LDS round trip per pivot.  The pivot
-// loop runs over column groups of four with the four steps of a group
-// unrolled, so element indices and buffer parities are compile-time and the
-// loop body is a few hundred instructions.  A pivot with
-// |a_pp|^2 < tau2 * max|tile|^2 is reported (return true).
+// Scratch of the unpivoted inverses: the tile maximum of each wavefront and
+// the small-pivot flag.
 template <typename T>
 struct RowScratch {
-    typename CT<T>::c row[2][32];
-    typename CT<T>::c col[2][32];
-    typename CT<T>::c dinv[2];
     float amax[4];
     int small;
 };
-
-// Step p = 4 pc + PE of gj_rows.
-template <typename T, int KBT, int PE>
-__device__ __forceinline__ void gj_rows_step(typename CT<T>::c (&a)[4], RowScratch<T>& sh, int pc, int r, int rr,
-                                             int cg, bool act, float thr, bool& small) {
-    using C = typename CT<T>::c;
-    constexpr int PAR = PE & 1, PE1 = (PE + 1) & 3;
-    const int p = 4 * pc + PE;
-    C rw[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) rw[e] = sh.row[PAR][4 * cg + e];
-    const C d = sh.dinv[PAR];
-    C f = sh.col[PAR][rr];
-    if (r == p) f.x -= (T)1;
-    const C fs = cmul(f, d);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        a[e].x = fma(-fs.x, rw[e].x, fma(fs.y, rw[e].y, a[e].x));
-        a[e].y = fma(-fs.x, rw[e].y, fma(-fs.y, rw[e].x, a[e].y));
-    }
-    if (cg == pc) a[PE] = mk<C>((r == p ? (T)1 : (T)0) - fs.x, -fs.y);
-    const int p1 = p + 1, pc1 = p1 >> 2;
-    if (p1 < KBT && act) {
-        if (cg == pc1) sh.col[PAR ^ 1][r] = a[PE1];
-        if (r == p1) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                sh.row[PAR ^ 1][4 * cg + e] = (cg == pc1 && e == PE1) ? mk<C>(0.0, 0.0) : a[e];
-            if (cg == pc1) {
-                sh.dinv[PAR ^ 1] = crcp(a[PE1]);
-                if (!((float)(a[PE1].x * a[PE1].x + a[PE1].y * a[PE1].y) >= thr)) small = true;
-            }
-        }
-    }
-}
-
-template <typename T, int KBT>
-__device__ __forceinline__ bool gj_rows(typename CT<T>::c (&a)[4], RowScratch<T>& sh, float tau2) {
-    using C = typename CT<T>::c;
-    constexpr int NW = KBT / 8;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int r = t >> 3, cg = t & 7;
-    const bool act = (r < KBT) && (4 * cg < KBT);
-    const int rr = r < KBT ? r : 0;
-    {
-        float m2 = 0.0f;
-        if (act) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, (float)(a[e].x * a[e].x + a[e].y * a[e].y));
-        }
-        const uint32_t wm = wave_max_u32(__float_as_uint(m2));
-        if (l == 0) sh.amax[w] = (w < NW) ? __uint_as_float(wm) : 0.0f;
-        if (t == 0) sh.small = 0;
-        // step 0's operands
-        if (act && r == 0) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sh.row[0][4 * cg + e] = (cg == 0 && e == 0) ? mk<C>(0.0, 0.0) : a[e];
-            if (cg == 0) sh.dinv[0] = crcp(a[0]);
-        }
-        if (act && cg == 0) sh.col[0][r] = a[0];
-    }
-    __syncthreads();
-    float thr = sh.amax[0];
-#pragma unroll
-    for (int q = 1; q < NW; ++q) thr = fmaxf(thr, sh.amax[q]);
-    thr *= tau2;
-    bool small = act && r == 0 && cg == 0 && !((float)(a[0].x * a[0].x + a[0].y * a[0].y) >= thr);
-#pragma unroll 1
-    for (int pc = 0; pc < KBT / 4; ++pc) {
-        if (pc > 0) __syncthreads();
-        gj_rows_step<T, KBT, 0>(a, sh, pc, r, rr, cg, act, thr, small);
-        __syncthreads();
-        gj_rows_step<T, KBT, 1>(a, sh, pc, r, rr, cg, act, thr, small);
-        __syncthreads();
-        gj_rows_step<T, KBT, 2>(a, sh, pc, r, rr, cg, act, thr, small);
-        __syncthreads();
-        gj_rows_step<T, KBT, 3>(a, sh, pc, r, rr, cg, act, thr, small);
-    }
-    if (small) sh.small = 1;
-    __syncthreads();
-    return sh.small != 0;
-}
 
 // Unpivoted Gauss-Jordan with 2 x 2 diagonal pivot blocks (complex64 tiles).
 // The tile lives in registers (layout above) and, between steps, in one of
@@ -373,6 +277,173 @@ __device__ __forceinline__ bool gj_pairs(typename CT<T>::c (&a)[4], typename CT<
     return sh.small != 0;
 }
 
+// ------------------------------------------------ blocked unpivoted inverse --
+// The diagonal tile [[A, B], [C, D]] (16 x 16 quadrants) is inverted as
+//     A^-1,  X = A^-1 B,  Y = C A^-1,  S = D - Y B,  S^-1,
+//     T12 = -X S^-1,  T21 = -S^-1 Y,  T22 = S^-1,  T11 = A^-1 - X T21,
+// which is unpivoted Gauss-Jordan on the whole tile with its pivots taken in
+// the same order (those of A, then those of S), so the small-pivot test is
+// the same one.  The two 16 x 16 inverses are done by one wavefront each in
+// registers (lane l holds row l % 16, columns 4 (l / 16) .. +3), exchanging
+// the pivot row and column by cross-lane reads, with no barrier; the six
+// 16 x 16 products run on the matrix cores from LDS.
+
+template <typename C> __device__ __forceinline__ C lane_read(C v, int lane);
+template <> __device__ __forceinline__ float2 lane_read(float2 v, int lane) {
+    float2 r;
+    r.x = __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(v.x)));
+    r.y = __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(v.y)));
+    return r;
+}
+template <> __device__ __forceinline__ double2 lane_read(double2 v, int lane) {
+    const int a = lane << 2;
+    const int xl = __builtin_amdgcn_ds_bpermute(a, __double2loint(v.x));
+    const int xh = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v.x));
+    const int yl = __builtin_amdgcn_ds_bpermute(a, __double2loint(v.y));
+    const int yh = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v.y));
+    return make_double2(__hiloint2double(xh, xl), __hiloint2double(yh, yl));
+}
+// the value of lane `lane` in every lane (lane is wave-uniform)
+template <typename C> __device__ __forceinline__ C lane_bcast(C v, int lane);
+template <> __device__ __forceinline__ float2 lane_bcast(float2 v, int lane) {
+    return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), lane)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), lane)));
+}
+template <> __device__ __forceinline__ double2 lane_bcast(double2 v, int lane) {
+    const int xl = __builtin_amdgcn_readlane(__double2loint(v.x), lane);
+    const int xh = __builtin_amdgcn_readlane(__double2hiint(v.x), lane);
+    const int yl = __builtin_amdgcn_readlane(__double2loint(v.y), lane);
+    const int yh = __builtin_amdgcn_readlane(__double2hiint(v.y), lane);
+    return make_double2(__hiloint2double(xh, xl), __hiloint2double(yh, yl));
+}
+
+// Unpivoted Gauss-Jordan of a 16 x 16 tile held by one wavefront (layout
+// above), in a uniform form with no special case for the pivot row: for
+// pivot p, with f = (column p) - e_p and d = 1 / a_pp, every entry off
+// column p takes a_ij -= (f_i d) a_pj, and column p becomes e_p - f d, which
+// leaves the inverse in place.  Every lane reads the old pivot row at its columns and
+// its row's entry of column p from the lanes that hold them.  Sets small if
+// |a_pp|^2 < thr for some pivot.
+template <typename T>
+__device__ __forceinline__ void gj16_wave(typename CT<T>::c (&a)[4], float thr, bool& small) {
+    using C = typename CT<T>::c;
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int gp = p >> 2, ep = p & 3;
+        const C f0 = lane_read(a[ep], r + 16 * gp);        // a[r][p]
+        C pr[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pr[e] = lane_read(a[e], p + 16 * g);   // a[p][4g + e]
+        const C piv = lane_bcast(a[ep], p + 16 * gp);       // a[p][p]
+        if (!((float)(piv.x * piv.x + piv.y * piv.y) >= thr)) small = true;
+        const C dv = crcp(piv);
+        C f = f0;
+        if (r == p) f.x -= (T)1;
+        const C fs = cmul(f, dv);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const C up = mk<C>(fma(-fs.x, pr[e].x, fma(fs.y, pr[e].y, a[e].x)),
+                               fma(-fs.x, pr[e].y, fma(-fs.y, pr[e].x, a[e].y)));
+            if (e == ep) a[e] = (g == gp) ? mk<C>((r == p ? (T)1 : (T)0) - fs.x, -fs.y) : up;
+            else a[e] = up;
+        }
+    }
+}
+
+// D = Cadd + sign * A B for 16 x 16 complex blocks in LDS (row stride 33),
+// by one wavefront on the matrix cores; Cadd may be null.  D may alias Cadd
+// (each lane reads its own entries of Cadd before writing them) but not A
+// or B.
+template <typename T>
+__device__ __forceinline__ void mm16(const typename CT<T>::c* A, const typename CT<T>::c* B,
+                                     const typename CT<T>::c* Cadd, typename CT<T>::c* D, T sign) {
+    using C = typename CT<T>::c;
+    using V = typename CT<T>::v4;
+    const int l = threadIdx.x & 63, lr = l & 15, lg = l >> 4;
+    V re, im;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { re[e] = 0; im[e] = 0; }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const C x = A[lr * 33 + 4 * q + lg], y = B[(4 * q + lg) * 33 + lr];
+        cmfma<T, V>(re, im, x.x, x.y, y.x, y.y);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = acc_row<T>(lg, e);
+        C v = mk<C>(sign * re[e], sign * im[e]);
+        if (Cadd) v = cadd(Cadd[row * 33 + lr], v);
+        D[row * 33 + lr] = v;
+    }
+}
+
+// The unpivoted inverse of the kb x kb tile in a[] (256-thread layout of the
+// pivoted path: thread t holds row t / 8, columns 4 (t % 8) .. +3), kb = 16
+// or 32, left in L[0..kb)[0..kb) (row stride 33; L2 two such buffers).
+// Returns whether a pivot was below tau2 * max|tile|^2.
+template <typename T>
+__device__ __forceinline__ bool inv_blocked(typename CT<T>::c (&a)[4], int kb, typename CT<T>::c* L2,
+                                            RowScratch<T>& sh, float tau2) {
+    using C = typename CT<T>::c;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int r = t >> 3, cg = t & 7;
+    const bool act = (r < kb) && (4 * cg < kb);
+    C* L = L2;               // the tile, then its inverse
+    C* Lb = L2 + 32 * 33;    // X (rows 0..15) and Y (rows 16..31)
+    {
+        float m2 = 0.0f;
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, (float)(a[e].x * a[e].x + a[e].y * a[e].y));
+        }
+        const uint32_t wm = wave_max_u32(__float_as_uint(m2));
+        if (l == 0) sh.amax[w] = __uint_as_float(wm);
+        if (t == 0) sh.small = 0;
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L[r * 33 + 4 * cg + e] = a[e];
+        }
+    }
+    __syncthreads();
+    const float thr = tau2 * fmaxf(fmaxf(sh.amax[0], sh.amax[1]), fmaxf(sh.amax[2], sh.amax[3]));
+    const int lr = l & 15, lg = l >> 4;
+    bool small = false;
+    // A^-1 in place (wave 0)
+    if (w == 0) {
+        C q[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = L[lr * 33 + 4 * lg + e];
+        gj16_wave<T>(q, thr, small);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) L[lr * 33 + 4 * lg + e] = q[e];
+    }
+    if (kb == 32) {
+        __syncthreads();
+        if (w == 0) mm16<T>(L, L + 16, nullptr, Lb, (T)1);                          // X = A^-1 B
+        else if (w == 1) mm16<T>(L + 16 * 33, L, nullptr, Lb + 16 * 33, (T)1);       // Y = C A^-1
+        __syncthreads();
+        if (w == 0) mm16<T>(Lb + 16 * 33, L + 16, L + 16 * 33 + 16, L + 16 * 33 + 16, (T)-1);   // S = D - Y B
+        __syncthreads();
+        if (w == 0) {
+            C q[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q[e] = L[(16 + lr) * 33 + 16 + 4 * lg + e];
+            gj16_wave<T>(q, thr, small);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L[(16 + lr) * 33 + 16 + 4 * lg + e] = q[e];
+        }
+        __syncthreads();
+        if (w == 0) mm16<T>(Lb, L + 16 * 33 + 16, nullptr, L + 16, (T)-1);              // T12 = -X S^-1
+        else if (w == 1) mm16<T>(L + 16 * 33 + 16, Lb + 16 * 33, nullptr, L + 16 * 33, (T)-1);   // T21 = -S^-1 Y
+        __syncthreads();
+        if (w == 0) mm16<T>(Lb, L + 16 * 33, L, L, (T)-1);                              // T11 = A^-1 - X T21
+    }
+    if (small) sh.small = 1;
+    __syncthreads();
+    return sh.small != 0;
+}
+
 // Device-coherent store of one complex64 value: a relaxed agent-scope atomic
 // store, which writes through the XCD's L2 to memory.
 __device__ __forceinline__ void cst(float2* p, float2 v) {
@@ -411,16 +482,24 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
     const bool act = (r < kb) && (4 * cg < kb);
     if (!pivot) {
         // diagonal pivots: pairs for complex64 tiles (one barrier per two
-        // pivots), single pivots for complex128
+        // pivots); the blocked form for complex128 (two 16 x 16 inverses in
+        // one wavefront each, the rest on the matrix cores), which measured
+        // faster than one barrier per pivot there but not than the pairs
         RowScratch<T>& rs = *(RowScratch<T>*)&sh;
-        if constexpr (sizeof(T) == 4)
+        if constexpr (sizeof(T) == 4) {
             *small = (kb == 32) ? gj_pairs<T, 32>(a, L2, rs, TAU2) : gj_pairs<T, 16>(a, L2, rs, TAU2);
-        else
-            *small = (kb == 32) ? gj_rows<T, 32>(a, rs, TAU2) : gj_rows<T, 16>(a, rs, TAU2);
-        if (act) {
+            if (act) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                Tt[(4 * cg + e) * KB + r] = a[e];
+                for (int e = 0; e < 4; ++e) Tt[(4 * cg + e) * KB + r] = a[e];
+            }
+        } else {
+            *small = inv_blocked<T>(a, kb, L2, rs, TAU2);
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 4 * cg + e;
+                    Tt[c * KB + r] = L2[r * 33 + c];
+                }
             }
         }
         return -1;
@@ -892,6 +971,7 @@ __global__ __launch_bounds__(256, 2) void k_factor_step(int n, int tstep, int un
 // standalone tile inverses (the building block above, for tests)
 __global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const double2* A, double2* Tout, int* status) {
     __shared__ double2 M[32][33];
+    __shared__ double2 L2[2 * 32 * 33];
     __shared__ GJScratch<double> sh;
     __shared__ double2 Tt[KB * KB];
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
@@ -903,7 +983,7 @@ __global__ __launch_bounds__(256) void k_tile_inverse(int kb, int pivot, const d
         a[e] = (r < kb && c < kb) ? Am[r * kb + c] : make_double2(0.0, 0.0);
     }
     bool small;
-    const int zero = invert_and_store<double>(a, kb, pivot, sh, M, nullptr, Tt, &small);
+    const int zero = invert_and_store<double>(a, kb, pivot, sh, M, L2, Tt, &small);
     __syncthreads();
     for (int i = t; i < kb * kb; i += 256) {
         const int rr = i / kb, c = i % kb;
