@@ -186,97 +186,6 @@ struct RowScratch {
     int small;
 };
 
-// Unpivoted Gauss-Jordan with 2 x 2 diagonal pivot blocks (complex64 tiles).
-// The tile lives in registers (layout above) and, between steps, in one of
-// two LDS copies L[2][32][33]: every thread writes its four entries after a
-// step and reads what the next step needs (two pivot rows, its entries of
-// the two pivot columns, the 2 x 2 pivot block P) after one barrier, so a
-// barrier is paid per pair of pivots.  With F = (columns p, p+1) - (unit
-// columns) and Fs = F P^{-1}, a step is a_ij -= Fs_i . (rows p, p+1)_j off
-// the pivot columns and (pivot columns) = (unit columns) - Fs, which is two
-// consecutive steps of the uniform form above.  The pivots are flagged small
-// as in the 1 x 1 form: |a_pp|^2 < thr, or |det P|^2 < thr |a_pp|^2 (the
-// second pivot of the pair).
-template <typename T, int KBT, int PE>
-__device__ __forceinline__ void gj2_step(typename CT<T>::c (&a)[4], typename CT<T>::c* L, int pc, int r, int rr,
-                                         int cg, float thr, bool& small) {
-    using C = typename CT<T>::c;
-    constexpr int PAR = (PE >> 1) & 1;
-    const int p = 4 * pc + PE, q = p + 1;
-    const C* B = L + PAR * 32 * 33;
-    C* Bn = L + (PAR ^ 1) * 32 * 33;
-    const C pa = B[p * 33 + p], pb = B[p * 33 + q], pcc = B[q * 33 + p], pd = B[q * 33 + q];
-    C r1[4], r2[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        r1[e] = B[p * 33 + 4 * cg + e];
-        r2[e] = B[q * 33 + 4 * cg + e];
-    }
-    C f1 = B[rr * 33 + p], f2 = B[rr * 33 + q];
-    // P^{-1} = [[d, -b], [-c, a]] / det
-    const C det = csub(cmul(pa, pd), cmul(pb, pcc));
-    const T n1 = pa.x * pa.x + pa.y * pa.y, nd = det.x * det.x + det.y * det.y;
-    if (!((float)n1 >= thr) || !((float)nd >= thr * (float)n1)) small = true;
-    const C id = crcp(det);
-    const C i11 = cmul(pd, id), i22 = cmul(pa, id);
-    const C i12 = cmul(mk<C>(-pb.x, -pb.y), id), i21 = cmul(mk<C>(-pcc.x, -pcc.y), id);
-    if (r == p) f1.x -= (T)1;
-    if (r == q) f2.x -= (T)1;
-    const C s1 = cadd(cmul(f1, i11), cmul(f2, i21)), s2 = cadd(cmul(f1, i12), cmul(f2, i22));
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        a[e].x = fma(-s1.x, r1[e].x, fma(s1.y, r1[e].y, a[e].x));
-        a[e].y = fma(-s1.x, r1[e].y, fma(-s1.y, r1[e].x, a[e].y));
-        a[e].x = fma(-s2.x, r2[e].x, fma(s2.y, r2[e].y, a[e].x));
-        a[e].y = fma(-s2.x, r2[e].y, fma(-s2.y, r2[e].x, a[e].y));
-    }
-    if (cg == pc) {
-        a[PE] = mk<C>((r == p ? (T)1 : (T)0) - s1.x, -s1.y);
-        a[PE + 1] = mk<C>((r == q ? (T)1 : (T)0) - s2.x, -s2.y);
-    }
-    if (q + 1 < KBT) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Bn[r * 33 + 4 * cg + e] = a[e];
-        __syncthreads();
-    }
-}
-
-template <typename T, int KBT>
-__device__ __forceinline__ bool gj_pairs(typename CT<T>::c (&a)[4], typename CT<T>::c* L, RowScratch<T>& sh,
-                                         float tau2) {
-    constexpr int NW = KBT / 8;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int r = t >> 3, cg = t & 7;
-    const bool act = (r < KBT) && (4 * cg < KBT);
-    const int rr = r < KBT ? r : 0;
-    {
-        float m2 = 0.0f;
-        if (act) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, (float)(a[e].x * a[e].x + a[e].y * a[e].y));
-        }
-        const uint32_t wm = wave_max_u32(__float_as_uint(m2));
-        if (l == 0) sh.amax[w] = (w < NW) ? __uint_as_float(wm) : 0.0f;
-        if (t == 0) sh.small = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) L[r * 33 + 4 * cg + e] = a[e];
-    }
-    __syncthreads();
-    float thr = sh.amax[0];
-#pragma unroll
-    for (int q = 1; q < NW; ++q) thr = fmaxf(thr, sh.amax[q]);
-    thr *= tau2;
-    bool small = false;
-#pragma unroll 1
-    for (int pc = 0; pc < KBT / 4; ++pc) {
-        gj2_step<T, KBT, 0>(a, L, pc, r, rr, cg, thr, small);
-        gj2_step<T, KBT, 2>(a, L, pc, r, rr, cg, thr, small);
-    }
-    if (small) sh.small = 1;
-    __syncthreads();
-    return sh.small != 0;
-}
-
 // ------------------------------------------------ blocked unpivoted inverse --
 // The diagonal tile [[A, B], [C, D]] (16 x 16 quadrants) is inverted as
 //     A^-1,  X = A^-1 B,  Y = C A^-1,  S = D - Y B,  S^-1,
@@ -317,38 +226,71 @@ template <> __device__ __forceinline__ double2 lane_bcast(double2 v, int lane) {
     return make_double2(__hiloint2double(xh, xl), __hiloint2double(yh, yl));
 }
 
+// the value of lane P of each row of 16 lanes, in every lane of that row
+// (DPP row broadcast; P compile-time)
+template <int P> __device__ __forceinline__ int row_bcast_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + P, 0xF, 0xF, false);
+}
+template <int P> __device__ __forceinline__ float2 row_bcast(float2 v) {
+    return make_float2(__int_as_float(row_bcast_i<P>(__float_as_int(v.x))),
+                       __int_as_float(row_bcast_i<P>(__float_as_int(v.y))));
+}
+template <int P> __device__ __forceinline__ double2 row_bcast(double2 v) {
+    return make_double2(__hiloint2double(row_bcast_i<P>(__double2hiint(v.x)), row_bcast_i<P>(__double2loint(v.x))),
+                        __hiloint2double(row_bcast_i<P>(__double2hiint(v.y)), row_bcast_i<P>(__double2loint(v.y))));
+}
+
+// One pivot of gj16_wave (below).
+template <typename T, int P>
+__device__ __forceinline__ void gj16_pivot(typename CT<T>::c (&a)[4], float thr, bool& small, int r, int g) {
+    using C = typename CT<T>::c;
+    constexpr int GP = P >> 2, EP = P & 3;
+    const C f0 = lane_read(a[EP], r + 16 * GP);            // a[r][p], from another row of lanes
+    C pr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pr[e] = row_bcast<P>(a[e]);   // a[p][4g + e], lane p of this row of lanes
+    const C piv = lane_bcast(a[EP], P + 16 * GP);          // a[p][p]
+    if (!((float)(piv.x * piv.x + piv.y * piv.y) >= thr)) small = true;
+    const C dv = crcp(piv);
+    C f = f0;
+    if (r == P) f.x -= (T)1;
+    const C fs = cmul(f, dv);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const C up = mk<C>(fma(-fs.x, pr[e].x, fma(fs.y, pr[e].y, a[e].x)),
+                           fma(-fs.x, pr[e].y, fma(-fs.y, pr[e].x, a[e].y)));
+        if (e == EP) a[e] = (g == GP) ? mk<C>((r == P ? (T)1 : (T)0) - fs.x, -fs.y) : up;
+        else a[e] = up;
+    }
+}
+
 // Unpivoted Gauss-Jordan of a 16 x 16 tile held by one wavefront (layout
 // above), in a uniform form with no special case for the pivot row: for
 // pivot p, with f = (column p) - e_p and d = 1 / a_pp, every entry off
 // column p takes a_ij -= (f_i d) a_pj, and column p becomes e_p - f d, which
 // leaves the inverse in place.  Every lane reads the old pivot row at its columns and
-// its row's entry of column p from the lanes that hold them.  Sets small if
-// |a_pp|^2 < thr for some pivot.
+// its row's entry of column p from the lanes that hold them (the row by a
+// DPP broadcast within each row of 16 lanes, the column entry by a
+// cross-lane read).  Sets small if |a_pp|^2 < thr for some pivot.
 template <typename T>
 __device__ __forceinline__ void gj16_wave(typename CT<T>::c (&a)[4], float thr, bool& small) {
-    using C = typename CT<T>::c;
     const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        const int gp = p >> 2, ep = p & 3;
-        const C f0 = lane_read(a[ep], r + 16 * gp);        // a[r][p]
-        C pr[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) pr[e] = lane_read(a[e], p + 16 * g);   // a[p][4g + e]
-        const C piv = lane_bcast(a[ep], p + 16 * gp);       // a[p][p]
-        if (!((float)(piv.x * piv.x + piv.y * piv.y) >= thr)) small = true;
-        const C dv = crcp(piv);
-        C f = f0;
-        if (r == p) f.x -= (T)1;
-        const C fs = cmul(f, dv);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const C up = mk<C>(fma(-fs.x, pr[e].x, fma(fs.y, pr[e].y, a[e].x)),
-                               fma(-fs.x, pr[e].y, fma(-fs.y, pr[e].x, a[e].y)));
-            if (e == ep) a[e] = (g == gp) ? mk<C>((r == p ? (T)1 : (T)0) - fs.x, -fs.y) : up;
-            else a[e] = up;
-        }
-    }
+    gj16_pivot<T, 0>(a, thr, small, r, g);
+    gj16_pivot<T, 1>(a, thr, small, r, g);
+    gj16_pivot<T, 2>(a, thr, small, r, g);
+    gj16_pivot<T, 3>(a, thr, small, r, g);
+    gj16_pivot<T, 4>(a, thr, small, r, g);
+    gj16_pivot<T, 5>(a, thr, small, r, g);
+    gj16_pivot<T, 6>(a, thr, small, r, g);
+    gj16_pivot<T, 7>(a, thr, small, r, g);
+    gj16_pivot<T, 8>(a, thr, small, r, g);
+    gj16_pivot<T, 9>(a, thr, small, r, g);
+    gj16_pivot<T, 10>(a, thr, small, r, g);
+    gj16_pivot<T, 11>(a, thr, small, r, g);
+    gj16_pivot<T, 12>(a, thr, small, r, g);
+    gj16_pivot<T, 13>(a, thr, small, r, g);
+    gj16_pivot<T, 14>(a, thr, small, r, g);
+    gj16_pivot<T, 15>(a, thr, small, r, g);
 }
 
 // D = Cadd + sign * A B for 16 x 16 complex blocks in LDS (row stride 33),
@@ -472,8 +414,9 @@ constexpr float TAU2 = 1e-4f;
 
 // Invert the kb x kb tile in a[] and store its inverse transposed
 // (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
-// (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted complex64 path).  Returns the first zero-pivot step (pivoted path) or -1;
-// *small is set when the unpivoted path met a pivot below the tolerance.
+// (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted path).  Returns the
+// first zero-pivot step (pivoted path) or -1; *small is set when the
+// unpivoted path met a pivot below the tolerance.
 template <typename T>
 __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, int pivot, GJScratch<T>& sh,
                                                 typename CT<T>::c (*M)[33], typename CT<T>::c* L2,
@@ -481,25 +424,15 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
     const bool act = (r < kb) && (4 * cg < kb);
     if (!pivot) {
-        // diagonal pivots: pairs for complex64 tiles (one barrier per two
-        // pivots); the blocked form for complex128 (two 16 x 16 inverses in
-        // one wavefront each, the rest on the matrix cores), which measured
-        // faster than one barrier per pivot there but not than the pairs
+        // diagonal pivots: the blocked form (two 16 x 16 inverses in one
+        // wavefront each, the products around them on the matrix cores)
         RowScratch<T>& rs = *(RowScratch<T>*)&sh;
-        if constexpr (sizeof(T) == 4) {
-            *small = (kb == 32) ? gj_pairs<T, 32>(a, L2, rs, TAU2) : gj_pairs<T, 16>(a, L2, rs, TAU2);
-            if (act) {
+        *small = inv_blocked<T>(a, kb, L2, rs, TAU2);
+        if (act) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Tt[(4 * cg + e) * KB + r] = a[e];
-            }
-        } else {
-            *small = inv_blocked<T>(a, kb, L2, rs, TAU2);
-            if (act) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int c = 4 * cg + e;
-                    Tt[c * KB + r] = L2[r * 33 + c];
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int c = 4 * cg + e;
+                Tt[c * KB + r] = L2[r * 33 + c];
             }
         }
         return -1;
