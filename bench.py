@@ -661,13 +661,14 @@ def main():
         extras["fwi_201_fp32ir"] = fwi_extra(helm, I, precision="fp32_ir")
         # the Hessian systems of several training models in lockstep
         extras["pcg_batch_201"] = pcg_batch_extra(helm, I, w4, G4)
-        # the serving workload: 192 Poisson arrivals at 200 requests/s, three
-        # batches side by side (lanes) and, for comparison, two in flight
-        # (pipelined); and the lanes at 150 requests/s
+        # the serving workload: 384 Poisson arrivals at 200 requests/s, four
+        # batches side by side (lanes), at most 8 requests per batch (one
+        # factorisation group); the same stream with plain complex128 factors
+        # (the FP64 method served); and the lanes at 150 requests/s
         from paper_2301_10762_amd import serving as SV
-        extras["serving_c5"] = SV.run_c5(requests=192, rate=200.0, precision=prec, lanes=3)
-        extras["serving_c5_pipelined"] = SV.run_c5(requests=192, rate=200.0, precision=prec)
-        extras["serving_150"] = SV.run_c5(requests=192, rate=150.0, precision=prec, lanes=3)
+        extras["serving_c5"] = SV.run_c5(requests=384, rate=200.0, precision=prec, lanes=4, max_chains=8)
+        extras["serving_c5_fp64"] = SV.run_c5(requests=384, rate=200.0, precision="fp64", lanes=4, max_chains=8)
+        extras["serving_150"] = SV.run_c5(requests=384, rate=150.0, precision=prec, lanes=4, max_chains=8)
 
     cpu, oracle_err = None, None
     if not args.no_cpu_baseline:

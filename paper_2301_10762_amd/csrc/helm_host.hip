@@ -109,10 +109,11 @@ void keep_pool_memory() {
 
 // Device memory of factors and scratch goes through a small cache of freed
 // blocks.  A released block keeps an event recorded on the stream that last
-// used it; a later request of about the same size (on any stream of the same
-// device) takes it after queueing a wait on that event, so a factorisation
-// or a refinement step does not pay for a fresh allocation or a release
-// (each a driver call of tens to hundreds of microseconds for large blocks).
+// used it; a later request of about the same size on the same device takes
+// it when that use is in its own stream's order or already finished, so a
+// factorisation or a refinement step does not pay for a fresh allocation or
+// a release (each a driver call of tens to hundreds of microseconds for
+// large blocks).
 // Blocks beyond the cache limit are released to the device's stream-ordered
 // pool, oldest first, once their last use has finished.
 struct DevCache {
@@ -121,6 +122,7 @@ struct DevCache {
         size_t bytes;
         int dev;
         hipEvent_t ready;
+        hipStream_t st;   // the stream of the block's last use
     };
     std::mutex mu;
     std::vector<Blk> free;   // oldest first
@@ -147,19 +149,27 @@ struct DevCache {
         int dev = 0;
         (void)hipGetDevice(&dev);
         {
+            // Candidates, best first: last used on this stream (already in
+            // order), then last used elsewhere but finished (no wait); a block
+            // whose last use on another stream is still queued is not taken
+            // (the wait would chain this stream behind that work, e.g. one
+            // serving lane behind another), a fresh block is allocated.
             std::lock_guard<std::mutex> lk(mu);
-            int best = -1;
+            int best = -1, best_rank = 3;
             for (int i = 0; i < (int)free.size(); ++i) {
                 const Blk& b = free[i];
-                if (b.dev == dev && b.bytes >= rb && b.bytes <= rb + rb / 4 &&
-                    (best < 0 || b.bytes < free[best].bytes))
+                if (b.dev != dev || b.bytes < rb || b.bytes > rb + rb / 4) continue;
+                const int rank = b.st == st ? 0 : (hipEventQuery(b.ready) == hipSuccess ? 1 : 2);
+                if (rank == 2) continue;
+                if (rank < best_rank || (rank == best_rank && b.bytes < free[best].bytes)) {
                     best = i;
+                    best_rank = rank;
+                }
             }
             if (best >= 0) {
                 Blk b = free[best];
                 free.erase(free.begin() + best);
                 held -= b.bytes;
-                (void)hipStreamWaitEvent(st, b.ready, 0);
                 (void)hipEventDestroy(b.ready);
                 *out = b.p;
                 return hipSuccess;
@@ -179,7 +189,7 @@ struct DevCache {
     }
     void put(void* p, size_t bytes, hipStream_t st) {
         if (!p) return;
-        Blk b{p, rounded(bytes), 0, nullptr};
+        Blk b{p, rounded(bytes), 0, nullptr, st};
         (void)hipGetDevice(&b.dev);
         if (hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) {
             (void)hipFreeAsync(p, st);

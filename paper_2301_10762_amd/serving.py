@@ -52,6 +52,7 @@ class ServeRequest:
     B: object = None             # ... or an explicit [S][N] complex128 device block
     arrival: float = 0.0         # seconds, relative to the stream start
     model_key: object = None     # for resident factors
+    precision: str = None        # "fp64" or "fp32_ir"; None: the backend's
 
     @property
     def S(self) -> int:
@@ -83,6 +84,7 @@ class _Prepared:
     ms: list = dataclasses.field(default_factory=list)
     oms: list = dataclasses.field(default_factory=list)
     keys: set = dataclasses.field(default_factory=set)      # resident factors used
+    precision: str = None                                    # of every request of the batch
     bytes: int = 0
     Bs: dict = None
     be: object = None                                        # backend (lane) that runs the batch
@@ -120,12 +122,12 @@ class HelmBackend:
         import torch
         return torch.cuda.stream(self.own) if self.own is not None else contextlib.nullcontext()
 
-    def factor_bytes(self, grid) -> int:
-        return self.helm.factor_bytes(grid, self.precision)
+    def factor_bytes(self, grid, precision=None) -> int:
+        return self.helm.factor_bytes(grid, precision or self.precision)
 
-    def factor(self, grids, ms, omegas):
+    def factor(self, grids, ms, omegas, precision=None):
         self.factorisations += len(grids)
-        return self.helm.factor_batch(grids, ms, omegas, self.precision, self.stream)
+        return self.helm.factor_batch(grids, ms, omegas, precision or self.precision, self.stream)
 
     def rhs(self, req: ServeRequest):
         if req.B is not None:
@@ -156,8 +158,8 @@ class HelmBackend:
             torch.cuda.synchronize()
 
 
-def _grid_key(grid):
-    return tuple(getattr(grid, a, None) for a in ("nx", "nz", "hx", "hz"))
+def _grid_key(grid, precision=None):
+    return tuple(getattr(grid, a, None) for a in ("nx", "nz", "hx", "hz")) + (precision,)
 
 
 class Server:
@@ -192,9 +194,21 @@ class Server:
         self._inflight = []              # lane runs: the batches in flight
 
     # -- memory accounting --------------------------------------------------
+    def _prec(self, req: ServeRequest):
+        """The request's precision (its own, else the backend's)."""
+        return req.precision if req.precision is not None else getattr(self.be, "precision", None)
+
+    def _fkey(self, req: ServeRequest, w):
+        """Key of a resident factor: model, frequency and precision."""
+        return (req.model_key, float(w), self._prec(req))
+
+    def _fbytes(self, req: ServeRequest) -> int:
+        p = self._prec(req)
+        return self.be.factor_bytes(req.grid, p) if req.precision is not None else self.be.factor_bytes(req.grid)
+
     def _need(self, req: ServeRequest, reuse) -> int:
-        fb = self.be.factor_bytes(req.grid)
-        n_new = sum(1 for w in req.omegas if (req.model_key, float(w)) not in reuse)
+        fb = self._fbytes(req)
+        n_new = sum(1 for w in req.omegas if self._fkey(req, w) not in reuse)
         return n_new * fb + len(req.omegas) * BYTES_PER_UNKNOWN_RHS * req.grid.N * req.S
 
     def _evict(self, need: int, keep) -> bool:
@@ -230,18 +244,19 @@ class Server:
         keep = set(self.inflight_keys)
         if not self.queue:
             return batch
-        gk = _grid_key(self.queue[0].grid)
+        gk = _grid_key(self.queue[0].grid, self._prec(self.queue[0]))
         taken = []
         for idx, req in enumerate(self.queue):
             if self.max_overtakes is None:
-                pass
-            elif _grid_key(req.grid) != gk:
+                if self._prec(req) != gk[-1]:
+                    break              # first in, first out: a batch has one precision
+            elif _grid_key(req.grid, self._prec(req)) != gk:
                 if self.overtaken.get(req.rid, 0) >= self.max_overtakes:
                     break
                 continue
             if chains + len(req.omegas) > self.max_chains:
                 break
-            keys = {(req.model_key, float(w)) for w in req.omegas} if req.model_key is not None else set()
+            keys = {self._fkey(req, w) for w in req.omegas} if req.model_key is not None else set()
             hit = {k for k in keys if k in self.cache}
             need = self._need(req, hit)
             if not self._evict(used + need, keep | hit):
@@ -278,10 +293,11 @@ class Server:
         `be`: the lane that runs it, by default the server's backend)."""
         prep = _Prepared(batch, self.clock())
         prep.be = be if be is not None else self.be
+        prep.precision = batch[0].precision
         for r, req in enumerate(batch):
             m = prep.be.model(req)
             for q, w in enumerate(req.omegas):
-                key = (req.model_key, float(w))
+                key = self._fkey(req, w)
                 if req.model_key is not None and key in self.cache:
                     self.cache.move_to_end(key)
                     prep.Fs[(r, q)] = self.cache[key][0]
@@ -298,7 +314,9 @@ class Server:
 
     def _factor(self, prep: "_Prepared"):
         if prep.grids:
-            for slot, F in zip(prep.slots, prep.be.factor(prep.grids, prep.ms, prep.oms)):
+            Fs = (prep.be.factor(prep.grids, prep.ms, prep.oms, prep.precision) if prep.precision is not None
+                  else prep.be.factor(prep.grids, prep.ms, prep.oms))
+            for slot, F in zip(prep.slots, Fs):
                 prep.Fs[slot] = F
 
     def _solve(self, prep: "_Prepared"):
@@ -318,9 +336,9 @@ class Server:
         for r, q in prep.slots:
             req = prep.batch[r]
             F = prep.Fs[(r, q)]
-            key = (req.model_key, float(req.omegas[q]))
+            key = self._fkey(req, req.omegas[q])
             if self.resident and req.model_key is not None and key not in self.cache:
-                b = self.be.factor_bytes(req.grid)
+                b = self._fbytes(req)
                 if self._evict(b, set(self.inflight_keys)):
                     self.cache[key] = (F, b)
                     self.cache_bytes += b

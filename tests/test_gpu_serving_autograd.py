@@ -76,6 +76,45 @@ def test_serving_alone_equals_mixed_and_matches_oracle(helm, precision):
             assert_cols(r.X[q].cpu().numpy(), Xo, 1e-9, what=f"request {r.rid}, frequency {q}")
 
 
+@pytest.mark.parametrize("lanes", [0, 3])
+def test_mixed_precision_stream_equals_alone(helm, lanes):
+    """Requests that name their own precision (complex128, or complex64 +
+    FP64 refinement) in one stream: batches are formed per grid and
+    precision, and every result is bitwise the one of the same request
+    served alone in its precision, with the serial loop and with lanes."""
+    from paper_2301_10762_amd import serving as SV
+    precs = ["fp64", "fp32_ir", "fp32_ir", "fp64"]
+    alone = {}
+    for rid, (spec, p) in enumerate(zip(SPECS, precs)):
+        srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36)
+        req, _ = make_request(SV, helm, rid, *spec)
+        req.precision = p
+        srv.submit(req)
+        alone[rid] = [x.clone() for x in srv.step()[0].X]
+    reqs = []
+    for rid, (spec, p) in enumerate(zip(SPECS + SPECS, precs + precs[::-1])):
+        req, _ = make_request(SV, helm, rid % len(SPECS) + 10 * (rid // len(SPECS)), *spec)
+        req.precision = p
+        reqs.append(req)
+    # the second copy of each spec asks for the other precision: its solo result
+    for rid, (spec, p) in enumerate(zip(SPECS, precs[::-1])):
+        srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36)
+        req, _ = make_request(SV, helm, 10 + rid, *spec)
+        req.precision = p
+        srv.submit(req)
+        alone[10 + rid] = [x.clone() for x in srv.step()[0].X]
+    srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36, max_chains=8)
+    print(f"mixed-precision stream, lanes {lanes}", flush=True)
+    res = SV.run_lanes(srv, reqs, lanes=lanes, realtime=False) if lanes else SV.run_stream(srv, reqs, realtime=False)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == sorted(alone)
+    for r in res:
+        assert max(i.max_relres for i in r.infos) <= 1e-10
+        for q, X in enumerate(r.X):
+            assert torch.equal(X, alone[r.rid][q]), (r.rid, q)
+    srv.close()
+
+
 def test_serving_resident_factors_reused(helm):
     from paper_2301_10762_amd import serving as SV
     be = SV.HelmBackend("fp64", 1e-10)

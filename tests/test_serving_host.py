@@ -33,11 +33,12 @@ class FakeBackend:
     def __init__(self):
         self.made, self.calls = [], []
 
-    def factor_bytes(self, grid):
-        return 100 * grid.N
+    def factor_bytes(self, grid, precision=None):
+        return (50 if precision == "fp32_ir" else 100) * grid.N
 
-    def factor(self, grids, ms, omegas):
+    def factor(self, grids, ms, omegas, precision=None):
         self.calls.append(len(grids))
+        self.precisions = getattr(self, "precisions", []) + [precision]
         out = [FakeFactor(len(self.made) + c, g, w) for c, (g, w) in enumerate(zip(grids, omegas))]
         self.made += out
         self.max_live = max(getattr(self, "max_live", 0), self.live())
@@ -357,3 +358,32 @@ def test_lanes_need_a_backend_with_lanes():
         SV.run_lanes(srv, [req(0)], lanes=2, realtime=False)
     with pytest.raises(ValueError):
         SV.run_lanes(SV.Server(LaneFake(), 1 << 40), [req(0)], lanes=0, realtime=False)
+
+
+def test_batches_have_one_precision():
+    """Requests naming different precisions never share a batch (first in,
+    first out or grouped by grid); each batch is factored in its requests'
+    precision and counted with that precision's factor size."""
+    for overtakes in (None, 4):
+        be = FakeBackend()
+        srv = SV.Server(be, 1 << 40, max_chains=16, max_overtakes=overtakes)
+        precs = ["fp64", "fp64", "fp32_ir", "fp64", "fp32_ir", "fp32_ir"]
+        for r, p in enumerate(precs):
+            q = req(r)
+            q.precision = p
+            srv.submit(q)
+        batches = []
+        while srv.queue:
+            out = srv.step()
+            batches.append(sorted(x.rid for x in out))
+        for b, p in zip(batches, be.precisions):
+            assert {precs[r] for r in b} == {p}, (overtakes, batches, be.precisions)
+        assert sorted(r for b in batches for r in b) == list(range(len(precs)))
+        if overtakes is None:
+            assert batches == [[0, 1], [2], [3], [4, 5]]
+        else:
+            assert batches == [[0, 1, 3], [2, 4, 5]]
+    srv = SV.Server(FakeBackend(), 1 << 40)
+    q = req(9, n=10, S=4)
+    q.precision = "fp32_ir"
+    assert srv._need(q, set()) == 50 * 100 + SV.BYTES_PER_UNKNOWN_RHS * 100 * 4
