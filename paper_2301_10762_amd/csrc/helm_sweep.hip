@@ -22,7 +22,7 @@ constexpr int SW_UNROLL = 8;  // chunks per straight-line block of the contracti
 
 int sweep_row_tiles(int np) { return np / 16; }
 int sweep_col_tiles(int S) { return ((S + 15) / 16 + SW_CTG - 1) / SW_CTG; }
-int sweep_grid(int groups, int cgroups) { return 8 * ((groups + 7) / 8) * cgroups; }
+int sweep_grid(int groups, int cgroups) { return 8 * ((groups * cgroups + 7) / 8); }
 
 template <typename C>
 __device__ __forceinline__ C conj_if(C v, bool c) {
@@ -52,18 +52,21 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab* __restrict__
 // Gr Yr, Gi Yi and (Gr + Gi)(Yr + Yi), in separate accumulators).  The waves share out the column tiles and split the
 // contraction; the parts are summed in a fixed order through LDS.  Each wave
 // streams its operands with SW_DEPTH chunks of 16 in flight, and several
-// workgroups per compute unit hide the rest of the latency.  Workgroups are
-// numbered so that the column tiles of one row tile run on the same XCD
-// (consecutive workgroups go to consecutive XCDs) and share its L2.
+// workgroups per compute unit hide the rest of the latency.
 template <typename T, bool FWD, bool CONJB>
 __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int groups, int cgroups, int uni,
                                                         const SweepTab* __restrict__ tab) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
     __shared__ T red[SW_WAVES][2][4][64];
-    const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
-    const int g = (slot / cgroups) * 8 + xcd, cgi = slot % cgroups;
-    if (g >= groups) return;
+    // XCD x (workgroup b runs on XCD b % 8) takes one contiguous range of the
+    // (row tile, column tile) pairs, row tile by row tile and front by front:
+    // the column tiles of a row tile share its factor rows, and the row tiles
+    // of a front its coupling vectors, in one or two L2s.
+    const int total = groups * cgroups, per = (total + 7) >> 3;
+    const int q = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    if (q >= total) return;
+    const int g = q / cgroups, cgi = q - g * cgroups;
     // uni > 0: every front of the launch has uni row tiles
     const int ci = uni > 0 ? (int)((unsigned)g / (unsigned)uni)
                            : find_chain(tab->c, n, g, [](const SweepInfo& c) { return c.tile0; });
