@@ -599,16 +599,19 @@ int sweep_group(helm_factor_s* const* fs, int n, const void* const* Ys, const in
     launch_put_sweep_table(stab, dtab, st);
     launch_sweep_init(dtab, nf, itot, fp32, conj_b, st);
     const int uni = sweep_uniform(stab, nf);
+    int np_max = 16;
+    for (int c = 0; c < nf; ++c) np_max = std::max(np_max, tab[c].np);
+    const int unroll = sweep_unroll(np_max);
     {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < fsteps; ++t) launch_sweep(dtab, nf, t, uni, groups, st_max, fp32, true, conj_b, st);
+        for (int t = 0; t < fsteps; ++t) launch_sweep(dtab, nf, t, uni, unroll, groups, st_max, fp32, true, conj_b, st);
         if (tm) g_timer.end(p, fsteps, st);
     }
     if (bsteps > 0) {
         KernelTimer::Pair p;
         const bool tm = g_timer.begin(2, st, &p);
-        for (int t = 0; t < bsteps; ++t) launch_sweep(dtab, nf, t, uni, groups, st_max, fp32, false, false, st);
+        for (int t = 0; t < bsteps; ++t) launch_sweep(dtab, nf, t, uni, unroll, groups, st_max, fp32, false, false, st);
         if (tm) g_timer.end(p, bsteps, st);
     }
     g_launches += 2 + (int64_t)fsteps + bsteps;

@@ -24,8 +24,10 @@ void launch_sweep_init(const SweepTab* dtab, int n, int total_blocks, bool fp32,
 // tiles (16 columns).
 // uni: sweep_uniform() of the group's table (every front has uni row tiles, or 0)
 int sweep_uniform(const SweepTab& tab, int n);
-void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int groups, int st, bool fp32, bool forward,
-                  bool conj_b, hipStream_t st_);
+// unroll: sweep_unroll() of the largest padded block size np of the group
+int sweep_unroll(int np_max);
+void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int unroll, int groups, int st, bool fp32,
+                  bool forward, bool conj_b, hipStream_t st_);
 int sweep_row_tiles(int np);
 int sweep_col_tiles(int S);
 void launch_check_model(const double* m, int64_t n, int* flag, hipStream_t st);

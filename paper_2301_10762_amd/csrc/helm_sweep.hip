@@ -12,13 +12,17 @@
 #include "helm_device.h"
 #include "helm_launch.h"
 
+#include <algorithm>
+
 namespace helm {
 
 constexpr int SW_WAVES = 4;
 constexpr int SW_CTG = 1;     // 16-column tiles per workgroup (the waves split them, then K)
 constexpr int SW_GDEPTH = 2;  // 16-wide K chunks of the factor block in flight per wave
 constexpr int SW_YDEPTH = 2;  // and of the coupling vector
-constexpr int SW_UNROLL = 8;  // chunks per straight-line block of the contraction
+// chunks per straight-line block of the contraction: a template parameter,
+// chosen per launch as the smallest even count that covers one wave's
+// chunks (at most 8), so a wave does not refill chunks it never uses
 
 int sweep_row_tiles(int np) { return np / 16; }
 int sweep_col_tiles(int S) { return ((S + 15) / 16 + SW_CTG - 1) / SW_CTG; }
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab* __restrict__
 // contraction; the parts are summed in a fixed order through LDS.  Each wave
 // streams its operands with SW_DEPTH chunks of 16 in flight, and several
 // workgroups per compute unit hide the rest of the latency.
-template <typename T, bool FWD, bool CONJB>
+template <typename T, bool FWD, bool CONJB, int SW_UNROLL>
 __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int groups, int cgroups, int uni,
                                                         const SweepTab* __restrict__ tab) {
     using C = typename CT<T>::c;
@@ -251,19 +255,35 @@ int sweep_uniform(const SweepTab& tab, int n) {
     return uni;
 }
 
-void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int groups, int st, bool fp32, bool forward,
-                  bool conj_b, hipStream_t st_) {
+int sweep_unroll(int np_max) {
+    const int per_wave = ((np_max >> 4) + SW_WAVES - 1) / SW_WAVES;
+    return std::min(8, (per_wave + 1) & ~1);
+}
+
+template <int U>
+static void launch_sweep_u(const SweepTab* dtab, int n, int t, int uni, int groups, int st, bool fp32, bool forward,
+                           bool conj_b, hipStream_t st_) {
     const dim3 grid(sweep_grid(groups, st)), block(64 * SW_WAVES);
     if (fp32) {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
-            else hipLaunchKernelGGL((k_sweep<float, true, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
-        } else hipLaunchKernelGGL((k_sweep<float, false, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<float, true, true, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            else hipLaunchKernelGGL((k_sweep<float, true, false, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+        } else hipLaunchKernelGGL((k_sweep<float, false, false, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
     } else {
         if (forward) {
-            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
-            else hipLaunchKernelGGL((k_sweep<double, true, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
-        } else hipLaunchKernelGGL((k_sweep<double, false, false>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            if (conj_b) hipLaunchKernelGGL((k_sweep<double, true, true, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+            else hipLaunchKernelGGL((k_sweep<double, true, false, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+        } else hipLaunchKernelGGL((k_sweep<double, false, false, U>), grid, block, 0, st_, n, t, groups, st, uni, dtab);
+    }
+}
+
+void launch_sweep(const SweepTab* dtab, int n, int t, int uni, int unroll, int groups, int st, bool fp32, bool forward,
+                  bool conj_b, hipStream_t st_) {
+    switch (unroll) {
+        case 2: launch_sweep_u<2>(dtab, n, t, uni, groups, st, fp32, forward, conj_b, st_); break;
+        case 4: launch_sweep_u<4>(dtab, n, t, uni, groups, st, fp32, forward, conj_b, st_); break;
+        case 6: launch_sweep_u<6>(dtab, n, t, uni, groups, st, fp32, forward, conj_b, st_); break;
+        default: launch_sweep_u<8>(dtab, n, t, uni, groups, st, fp32, forward, conj_b, st_); break;
     }
 }
 
