@@ -576,9 +576,8 @@ def main():
     value = solves / total
     ms_per_step = total / args.steps * 1e3
 
-    # roofline of the dominant kernel: the factorisation (one persistent
-    # launch k_factor_persist per group of systems, or one k_factor_step
-    # launch per panel step).  Algorithmic work: the block factorisation's
+    # roofline of the dominant kernel: the factorisation (one k_factor_step
+    # launch per panel step of all the systems of a group).  Algorithmic work: the block factorisation's
     # canonical count 8 * (4/3) * n_z * n_x^3 flops per frequency; the timed
     # region factors all five frequencies once per step.
     nx, nz = w.nx, w.nz
