@@ -324,15 +324,18 @@ __device__ __forceinline__ void mm16(const typename CT<T>::c* A, const typename 
 // pivoted path: thread t holds row t / 8, columns 4 (t % 8) .. +3), kb = 16
 // or 32, left in L[0..kb)[0..kb) (row stride 33; L2 two such buffers).
 // Returns whether a pivot was below tau2 * max|tile|^2.
+// The second half: the tile already in L2 (rows 0 .. kb-1, stride 33),
+// each wavefront's largest |a_ij|^2 in sh.amax and sh.small cleared, all
+// visible to the workgroup.
+template <typename T>
+__device__ __forceinline__ bool inv_blocked_core(int kb, typename CT<T>::c* L2, RowScratch<T>& sh, float tau2);
+
 template <typename T>
 __device__ __forceinline__ bool inv_blocked(typename CT<T>::c (&a)[4], int kb, typename CT<T>::c* L2,
                                             RowScratch<T>& sh, float tau2) {
-    using C = typename CT<T>::c;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int r = t >> 3, cg = t & 7;
     const bool act = (r < kb) && (4 * cg < kb);
-    C* L = L2;               // the tile, then its inverse
-    C* Lb = L2 + 32 * 33;    // X (rows 0..15) and Y (rows 16..31)
     {
         float m2 = 0.0f;
         if (act) {
@@ -344,10 +347,19 @@ __device__ __forceinline__ bool inv_blocked(typename CT<T>::c (&a)[4], int kb, t
         if (t == 0) sh.small = 0;
         if (act) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) L[r * 33 + 4 * cg + e] = a[e];
+            for (int e = 0; e < 4; ++e) L2[r * 33 + 4 * cg + e] = a[e];
         }
     }
     __syncthreads();
+    return inv_blocked_core<T>(kb, L2, sh, tau2);
+}
+
+template <typename T>
+__device__ __forceinline__ bool inv_blocked_core(int kb, typename CT<T>::c* L2, RowScratch<T>& sh, float tau2) {
+    using C = typename CT<T>::c;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    C* L = L2;               // the tile, then its inverse
+    C* Lb = L2 + 32 * 33;    // X (rows 0..15) and Y (rows 16..31)
     const float thr = tau2 * fmaxf(fmaxf(sh.amax[0], sh.amax[1]), fmaxf(sh.amax[2], sh.amax[3]));
     const int lr = l & 15, lg = l >> 4;
     bool small = false;
@@ -412,6 +424,19 @@ __device__ __forceinline__ void yst(double2* p, double2 v) {
 // Pivot tolerance of the unpivoted path: |a_pp|^2 >= TAU2 * max|a|^2.
 constexpr float TAU2 = 1e-4f;
 
+// The unpivoted inverse in L2 (stride 33) to Tt, transposed, row stride KB.
+template <typename T>
+__device__ __forceinline__ void store_inverse(int kb, const typename CT<T>::c* L2, typename CT<T>::c* Tt) {
+    const int t = threadIdx.x, r = t >> 3, cg = t & 7;
+    if ((r < kb) && (4 * cg < kb)) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * cg + e;
+            Tt[c * KB + r] = L2[r * 33 + c];
+        }
+    }
+}
+
 // Invert the kb x kb tile in a[] and store its inverse transposed
 // (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
 // (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted path).  Returns the
@@ -428,13 +453,7 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
         // wavefront each, the products around them on the matrix cores)
         RowScratch<T>& rs = *(RowScratch<T>*)&sh;
         *small = inv_blocked<T>(a, kb, L2, rs, TAU2);
-        if (act) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = 4 * cg + e;
-                Tt[c * KB + r] = L2[r * 33 + c];
-            }
-        }
+        store_inverse<T>(kb, L2, Tt);
         return -1;
     }
     *small = false;
@@ -521,6 +540,21 @@ __global__ __launch_bounds__(256) void k_factor_init(const ChainTab* __restrict_
 template <typename C>
 __device__ __forceinline__ const C* next_a_source(const ChainInfo& d, int jl) {
     return (d.Ain && jl + 1 == d.nblk - 1) ? (const C*)d.Ain : nullptr;
+}
+
+// Entry (r, c) of the next block's first diagonal tile, A_{j+1} - E G_j E,
+// from the entry g of G_j (the Schur complement on a block's last panel).
+template <typename C>
+__device__ __forceinline__ C next_schur(const ChainInfo& d, const C* Asrc, int jn, int r, int c, C g) {
+    double2 a1;
+    if (Asrc) {
+        const C v = Asrc[(size_t)r * d.np + c];
+        a1 = make_double2(v.x, v.y);
+    } else {
+        a1 = block_entry(d.cf, jn, r, c);
+    }
+    const double s = row_coupling(d.cf, r) * row_coupling(d.cf, c);
+    return mk<C>(a1.x - s * (double)g.x, a1.y - s * (double)g.y);
 }
 
 // workgroup that prepares the next step's inverted diagonal tile
@@ -614,6 +648,33 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
             const C x = sP[16 * wr + lr][4 * s8 + lg], y = sXb[4 * s8 + lg][16 * wc + lr];
             cmfma<T, V>(zr, zi, x.x, x.y, y.x, y.y);
         }
+        if (!d.pivot) {
+            // unpivoted: each wave puts its block of the tile (after the
+            // Schur complement of the next block on a last panel) straight
+            // into the inversion buffer and reports its largest |a_ij|^2
+            C* L2 = &sT[0][0];   // T and X_{KK'} are no longer read there
+            RowScratch<T>& rs = *(RowScratch<T>*)&sh;
+            float m2 = 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
+                C v = mk<C>(0.0, 0.0);
+                if (rr < kbn && cc < kbn) {
+                    v = mk<C>(zr[e], zi[e]);
+                    if (ps.last_panel) v = next_schur<C>(d, Asrc, jn, rr, cc, v);
+                    m2 = fmaxf(m2, (float)(v.x * v.x + v.y * v.y));
+                }
+                L2[rr * 33 + cc] = v;
+            }
+            const uint32_t wm = wave_max_u32(__float_as_uint(m2));
+            if (l == 0) rs.amax[w] = __uint_as_float(wm);
+            if (t == 0) rs.small = 0;
+            __syncthreads();
+            const bool small = inv_blocked_core<T>(kbn, L2, rs, TAU2);
+            store_inverse<T>(kbn, L2, Tnext);
+            if (small && t == 0) d.status[3] = 1;
+            return;
+        }
         // to the Gauss-Jordan layout through sXa (no longer read)
 #pragma unroll
         for (int e = 0; e < 4; ++e) sXa[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(zr[e], zi[e]);
@@ -622,20 +683,8 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
         for (int e = 0; e < 4; ++e) a[e] = act ? sXa[r][4 * cg + e] : mk<C>(0.0, 0.0);
     }
     if (ps.last_panel && act) {
-        // Schur complement of the next block: A_{j+1} - E G_j E on this tile
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = 4 * cg + e;
-            double2 a1;
-            if (Asrc) {
-                const C v = Asrc[(size_t)r * np + c];
-                a1 = make_double2(v.x, v.y);
-            } else {
-                a1 = block_entry(d.cf, jn, r, c);
-            }
-            const double s = row_coupling(d.cf, r) * row_coupling(d.cf, c);
-            a[e] = mk<C>(a1.x - s * (double)a[e].x, a1.y - s * (double)a[e].y);
-        }
+        for (int e = 0; e < 4; ++e) a[e] = next_schur<C>(d, Asrc, jn, r, 4 * cg + e, a[e]);
     }
     __syncthreads();   // sXa is reused as the inversion buffer
     bool small;
