@@ -699,8 +699,10 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                             typename CT<T>::c* Y, const typename CT<T>::c* Tcur, char* smem) {
     using C = typename CT<T>::c;
     using V = typename CT<T>::v4;
-    // three real products per complex one in complex128 only: in complex64
-    // the larger rounding of the imaginary parts costs a refinement step
+    // three real products per complex one (Gauss) for the Y product in
+    // complex128 only: in complex64 its larger rounding of the imaginary
+    // parts costs a refinement step.  The W product takes three in both
+    // precisions (the complex64 refinement count is unchanged).
     constexpr bool GAUSS = sizeof(T) == 8;
     const int np = d.np, kb = ps.kb, k0 = ps.k0;
     const int tiles_x = (np + TILE - 1) / TILE;
@@ -799,9 +801,9 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
             for (int s8 = 0; s8 < 8; ++s8) {
                 const int k = 4 * s8 + lg;
                 const C av = sW[16 * w + lr][k], bv = sT[k][cb * 16 + lr];
-                cacc<GAUSS, T, V>(q1, q2, q3, av.x, av.y, bv.x, bv.y);
+                cacc<true, T, V>(q1, q2, q3, av.x, av.y, bv.x, bv.y);
             }
-            cacc_final<GAUSS, V>(q1, q2, q3, wre[cb], wim[cb]);
+            cacc_final<true, V>(q1, q2, q3, wre[cb], wim[cb]);
         }
         C tk[2][4];   // rows of K: T - I, read before the buffers are rewritten
 #pragma unroll
