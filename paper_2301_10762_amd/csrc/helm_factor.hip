@@ -629,14 +629,19 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
 #pragma unroll
         for (int e = 0; e < 4; ++e) a[e] = act ? sT[r][4 * cg + e] : mk<C>(0.0, 0.0);
     } else {
-        // P = X_{K'K} T on the matrix cores (zero padding beyond kb, kbn)
+        // P = X_{K'K} T on the matrix cores (zero padding beyond kb, kbn), in
+        // three real products per complex one like the update tiles' W
         V pr, pim;
+        {
+            V p1, p2, p3;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { pr[e] = 0; pim[e] = 0; }
+            for (int e = 0; e < 4; ++e) { p1[e] = 0; p2[e] = 0; p3[e] = 0; }
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-            const C x = sXa[16 * wr + lr][4 * s8 + lg], y = sT[4 * s8 + lg][16 * wc + lr];
-            cmfma<T, V>(pr, pim, x.x, x.y, y.x, y.y);
+            for (int s8 = 0; s8 < 8; ++s8) {
+                const C x = sXa[16 * wr + lr][4 * s8 + lg], y = sT[4 * s8 + lg][16 * wc + lr];
+                cacc<true, T, V>(p1, p2, p3, x.x, x.y, y.x, y.y);
+            }
+            cacc_final<true, V>(p1, p2, p3, pr, pim);
         }
         // -P into sP (accumulator layout -> row-major)
 #pragma unroll
