@@ -100,7 +100,9 @@ void helm_factor_destroy(helm_factor_t f);
  * "Computing the wavefield", is the case B = e_s).  helm_adjoint_solve:
  * L = A^{-*} R, the conjugate-transpose solve behind eq (lambda), reusing the
  * same factors.  B/R and X/L: device complex128, column-major with leading
- * dimension ld (>= nx*nz); X must not overlap B.  For an FP32 factor the
+ * dimension ld (>= nx*nz; entries past nx*nz in a column are neither read
+ * nor written); X must not overlap B.  S >= 1; S <= 0, ld < nx*nz or
+ * overlapping buffers return HELM_EINVAL before any launch.  For an FP32 factor the
  * result is refined in FP64 until max_s ||b_s - A x_s|| / ||b_s|| <= tol
  * (tol <= 0 selects 1e-10), at most 10 corrections, else HELM_ENOCONV.  For
  * an FP64 factor tol > 0 also measures the residual into info (and refines
@@ -131,7 +133,9 @@ int helm_solve_noalloc(helm_factor_t f, const double* B_dev, double* X_dev, int3
                        double tol, void* stream, helm_info* info);
 
 /* helm_solve_batch: the same as helm_solve for `count` factors at once (the
- * sweeps of all factors share kernel launches).  Bs/Xs/Ss/lds per factor.  */
+ * sweeps of all factors share kernel launches).  Bs/Xs/Ss/lds per factor;
+ * count >= 1 and every entry valid as for helm_solve, else HELM_EINVAL
+ * before any launch.                                                        */
 int helm_solve_batch(int32_t count, const helm_factor_t* fs, const double* const* B_devs,
                      double* const* X_devs, const int32_t* S, const int64_t* ld, int adjoint,
                      double tol, void* stream, helm_info* infos);
