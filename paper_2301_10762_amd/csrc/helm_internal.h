@@ -94,16 +94,17 @@ struct SweepInfo {
     int itile0;             // first workgroup of the initial launch
 };
 
-// The per-front tables travel as kernel arguments (by value), so a
-// workgroup finds its front and reads its fields without a dependent load
-// through a device pointer.
+// The per-front tables of a group: written once per factorisation or solve
+// group into a small device buffer by a one-workgroup kernel (they reach it
+// as its kernel argument, hence the size limit), then read by every step
+// launch of the group, each entry in one round of scalar loads.
 struct ChainTab {
     ChainInfo c[MAXB];
 };
 struct SweepTab {
     SweepInfo c[MAXB];
 };
-static_assert(sizeof(ChainTab) <= 4000 && sizeof(SweepTab) <= 4000, "kernel argument tables too large");
+static_assert(sizeof(ChainTab) <= 4000 && sizeof(SweepTab) <= 4000, "tables pass through a kernel argument");
 
 constexpr int RTAP = 16;   // taps per sensor of the restriction tables (4 x 4 bicubic)
 
