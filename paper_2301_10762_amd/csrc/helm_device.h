@@ -135,7 +135,7 @@ __device__ __forceinline__ double2 diag_entry(const Coef& c, int i, int j) {
     double bnd = 0.0;
     if (j == 0 || j == c.nz - 1) bnd += 0.5 * c.hx * ((i > 0 ? 1 : 0) + (i < c.nx - 1 ? 1 : 0));
     if (i == 0 || i == c.nx - 1) bnd += 0.5 * c.hz * ((j > 0 ? 1 : 0) + (j < c.nz - 1 ? 1 : 0));
-    double mk_ = c.m[(size_t)j * c.nx + i];
+    double mk_ = *((const HELM_GLOBAL double*)c.m + (size_t)j * c.nx + i);
     return make_double2(s - c.omega * c.omega * mass * mk_, -c.omega * bnd * sqrt(mk_));
 }
 

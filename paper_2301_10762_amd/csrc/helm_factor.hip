@@ -403,7 +403,7 @@ __device__ __forceinline__ bool inv_blocked_core(int kb, typename CT<T>::c* L2, 
 __device__ __forceinline__ void cst(float2* p, float2 v) {
     const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
                                  ((unsigned long long)__float_as_uint(v.y) << 32);
-    __hip_atomic_store((unsigned long long*)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((HELM_GLOBAL unsigned long long*)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Store of an updated panel element.  Complex64: a device-coherent store
@@ -432,7 +432,7 @@ __device__ __forceinline__ void store_inverse(int kb, const typename CT<T>::c* L
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            Tt[c * KB + r] = L2[r * 33 + c];
+            gst(Tt + c * KB + r, L2[r * 33 + c]);
         }
     }
 }
@@ -467,7 +467,7 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            Tt[c * KB + r] = M[sh.rowOf[r]][sh.stepOf[c]];
+            gst(Tt + c * KB + r, M[sh.rowOf[r]][sh.stepOf[c]]);
         }
     }
     return zero;
@@ -548,7 +548,7 @@ template <typename C>
 __device__ __forceinline__ C next_schur(const ChainInfo& d, const C* Asrc, int jn, int r, int c, C g) {
     double2 a1;
     if (Asrc) {
-        const C v = Asrc[(size_t)r * d.np + c];
+        const C v = gld(Asrc + (size_t)r * d.np + c);
         a1 = make_double2(v.x, v.y);
     } else {
         a1 = block_entry(d.cf, jn, r, c);
@@ -894,7 +894,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                 if (schur) {
                     double2 a1;
                     if (Asrc) {
-                        const C v = Asrc[(size_t)row * np + col];
+                        const C v = gld(Asrc + (size_t)row * np + col);
                         a1 = make_double2(v.x, v.y);
                     } else {
                         a1 = block_entry(d.cf, rn, row, col);
