@@ -425,6 +425,8 @@ __device__ __forceinline__ void yst(double2* p, double2 v) {
 constexpr float TAU2 = 1e-4f;
 
 // The unpivoted inverse in L2 (stride 33) to Tt, transposed, row stride KB.
+// Tt is device memory (the factor's tile slots) or LDS (the standalone
+// tile-inverse kernel), so it is written through a generic pointer.
 template <typename T>
 __device__ __forceinline__ void store_inverse(int kb, const typename CT<T>::c* L2, typename CT<T>::c* Tt) {
     const int t = threadIdx.x, r = t >> 3, cg = t & 7;
@@ -432,7 +434,7 @@ __device__ __forceinline__ void store_inverse(int kb, const typename CT<T>::c* L
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            gst(Tt + c * KB + r, L2[r * 33 + c]);
+            Tt[c * KB + r] = L2[r * 33 + c];
         }
     }
 }
@@ -441,7 +443,8 @@ __device__ __forceinline__ void store_inverse(int kb, const typename CT<T>::c* L
 // (Tt[c][k] = T^{-1}[k][c]) with row stride KB.  M is a kb x 33 LDS buffer
 // (pivoted path), L2 two 32 x 33 LDS buffers (unpivoted path).  Returns the
 // first zero-pivot step (pivoted path) or -1; *small is set when the
-// unpivoted path met a pivot below the tolerance.
+// unpivoted path met a pivot below the tolerance.  Tt may be device memory
+// or LDS (generic stores).
 template <typename T>
 __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int kb, int pivot, GJScratch<T>& sh,
                                                 typename CT<T>::c (*M)[33], typename CT<T>::c* L2,
@@ -467,7 +470,7 @@ __device__ __forceinline__ int invert_and_store(typename CT<T>::c (&a)[4], int k
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int c = 4 * cg + e;
-            gst(Tt + c * KB + r, M[sh.rowOf[r]][sh.stepOf[c]]);
+            Tt[c * KB + r] = M[sh.rowOf[r]][sh.stepOf[c]];
         }
     }
     return zero;
