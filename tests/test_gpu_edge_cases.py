@@ -14,6 +14,9 @@
   refined complex64 solutions agree.
 * Calls with no columns, a negative count, ld below nx*nz or an empty
   batch are rejected with HELM_EINVAL before any launch.
+* One batched solve over complex128 and complex64 factors gives each
+  factor bitwise its result in a batch of its own precision, forward and
+  adjoint.
 """
 import ctypes
 
@@ -164,3 +167,30 @@ def test_rejects_empty_and_bad_counts(helm):
     assert L.helm_solve_batch(ctypes.c_int32(1), fs, ps, xs, ss, lds, 0, 0.0, helm._stream(None), None) == helm.EINVAL
     F.close()
     assert bool((X == 0).all())                                   # nothing was written
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_solve_batch_mixes_precisions(helm, adjoint):
+    """One helm_solve_batch call over complex128 and complex64 factors (the
+    library splits it by precision; each group shares its sweep launches):
+    every result is bitwise the same as that factor's solve within a batch of
+    its own precision, and matches the oracle."""
+    specs = [(23, 19, "fp64"), (17, 13, "fp32_ir"), (30, 11, "fp64"), (9, 25, "fp32_ir")]
+    Fs, Bs, data = [], [], []
+    for k, (nx, nz, prec) in enumerate(specs):
+        m, w, B = _system(nx, nz, 300 + k, 2 + k)
+        Fs.append(helm.factor(helm.Grid(nx, nz, 0.05, 0.05), torch.as_tensor(m, device="cuda"), w, prec))
+        Bs.append(torch.as_tensor(B, device="cuda"))
+        data.append((nx, nz, m, w, B))
+    print(f"mixed-precision batch, adjoint {adjoint}", flush=True)
+    Xm, infos = helm.solve_batch(Fs, Bs, adjoint=adjoint, tol=1e-10)
+    for prec in ("fp64", "fp32_ir"):
+        idx = [k for k, sp in enumerate(specs) if sp[2] == prec]
+        Xs, _ = helm.solve_batch([Fs[k] for k in idx], [Bs[k] for k in idx], adjoint=adjoint, tol=1e-10)
+        for k, X in zip(idx, Xs):
+            assert torch.equal(Xm[k], X), (k, prec)
+    for F, X, info, (nx, nz, m, w, B) in zip(Fs, Xm, infos, data):
+        F.close()
+        assert info.max_relres <= 1e-10
+        Xo = _oracle_solve(oracle.Grid(nx, nz, 0.05, 0.05), m, w, B, adjoint)
+        assert_cols(X.cpu().numpy(), Xo, 1e-9, what=f"{nx}x{nz} in a mixed-precision batch")
