@@ -14,6 +14,19 @@ template <> struct CT<double> { using c = double2; using v4 = v4d; };
 template <> struct CT<float> { using c = float2; using v4 = v4f; };
 
 template <typename C> __device__ __forceinline__ C mk(double re, double im) { C r; r.x = re; r.y = im; return r; }
+// p ? a : b for complex values.  A select of whole double2 values can be
+// lowered to a copy of both into a stack array and a load from the chosen
+// address (which also waits for every load in flight), so complex128 values
+// are chosen part by part.  float2 values keep the plain conditional, which
+// the compiler handles well (the size test is a constant: only one arm is
+// emitted).
+template <typename C> __device__ __forceinline__ C csel_parts(bool p, C a, C b) {
+    C r;
+    r.x = p ? a.x : b.x;
+    r.y = p ? a.y : b.y;
+    return r;
+}
+#define HELM_CSEL(p, a, b) (sizeof((a).x) == 8 ? csel_parts((p), (a), (b)) : ((p) ? (a) : (b)))
 
 // Loads and stores through pointers read from the device-side tables.  The
 // compiler cannot tell that such generic pointers address global memory and

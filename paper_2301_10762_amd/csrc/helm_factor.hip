@@ -143,7 +143,7 @@ __device__ __forceinline__ int gj_invert(typename CT<T>::c (&a)[4], GJScratch<T>
 #pragma unroll
         for (int e = 0; e < 4; ++e) pr[e] = sh.row[par][wb][4 * cg + e];
         const C f = swz_row_c<T>(a[pe], pc);
-        const C dv = good ? crcp(piv) : mk<C>(0.0, 0.0);
+        const C dv = HELM_CSEL(good, crcp(piv), mk<C>(0.0, 0.0));
         if (act) {
             if (r == rp) {
 #pragma unroll
@@ -259,7 +259,7 @@ __device__ __forceinline__ void gj16_pivot(typename CT<T>::c (&a)[4], float thr,
     for (int e = 0; e < 4; ++e) {
         const C up = mk<C>(fma(-fs.x, pr[e].x, fma(fs.y, pr[e].y, a[e].x)),
                            fma(-fs.x, pr[e].y, fma(-fs.y, pr[e].x, a[e].y)));
-        if (e == EP) a[e] = (g == GP) ? mk<C>((r == P ? (T)1 : (T)0) - fs.x, -fs.y) : up;
+        if (e == EP) a[e] = HELM_CSEL(g == GP, mk<C>((r == P ? (T)1 : (T)0) - fs.x, -fs.y), up);
         else a[e] = up;
     }
 }
@@ -612,16 +612,16 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     for (int i = 0; i < 4; ++i) {
         const int idx = t + 256 * i;
         const int hi = idx >> 5, lo = idx & 31;
-        sT[lo][hi] = (hi < kb && lo < kb) ? tl[i] : cz;
-        sXa[hi][lo] = (!single && hi < kbn && lo < kb) ? xa[i] : cz;
-        sXb[hi][lo] = (!single && hi < kb && lo < kbn) ? xb[i] : cz;
+        sT[lo][hi] = HELM_CSEL(hi < kb && lo < kb, tl[i], cz);
+        sXa[hi][lo] = HELM_CSEL(!single && hi < kbn && lo < kb, xa[i], cz);
+        sXb[hi][lo] = HELM_CSEL(!single && hi < kb && lo < kbn, xb[i], cz);
     }
     using V = typename CT<T>::v4;
     V zr, zi;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int rr = 16 * wr + acc_row<T>(lg, e), cc = 16 * wc + lr;
-        const C v = (!single && rr < kbn && cc < kbn) ? xz[e] : cz;
+        const C v = HELM_CSEL(!single && rr < kbn && cc < kbn, xz[e], cz);
         zr[e] = v.x;
         zi[e] = v.y;
     }
@@ -630,7 +630,7 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     __syncthreads();
     if (single) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = act ? sT[r][4 * cg + e] : mk<C>(0.0, 0.0);
+        for (int e = 0; e < 4; ++e) a[e] = HELM_CSEL(act, sT[r][4 * cg + e], mk<C>(0.0, 0.0));
     } else {
         // P = X_{K'K} T on the matrix cores (zero padding beyond kb, kbn), in
         // three real products per complex one like the update tiles' W
@@ -688,7 +688,7 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
         for (int e = 0; e < 4; ++e) sXa[16 * wr + acc_row<T>(lg, e)][16 * wc + lr] = mk<C>(zr[e], zi[e]);
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = act ? sXa[r][4 * cg + e] : mk<C>(0.0, 0.0);
+        for (int e = 0; e < 4; ++e) a[e] = HELM_CSEL(act, sXa[r][4 * cg + e], mk<C>(0.0, 0.0));
     }
     if (ps.last_panel && act) {
 #pragma unroll
@@ -699,6 +699,34 @@ __device__ __forceinline__ void next_tile(const ChainInfo& d, const PanelStep& p
     const int zero = invert_and_store<T>(a, kbn, d.pivot, sh, sXa, &sT[0][0], Tnext, &small);
     if (zero >= 0 && t == 0) report_zero_pivot(d.status, jn, kn0 + zero);
     if (small && t == 0) d.status[3] = 1;
+}
+
+// Accumulators of the update tile's product seeded with its tile of X'
+// (identity on the panel columns K, zero outside the block)
+template <bool GAUSS, typename T, typename V, typename C>
+__device__ __forceinline__ void seed_y(V (&a1)[2][2], V (&a2)[2][2], V (&a3)[2][2], const C (&xt)[2][2][4],
+                                       const int (&R)[2], const int (&Cc)[2], const bool (&vr)[2], const bool (&vc)[2],
+                                       int k0, int kb, int lr, int lg) {
+    const C zero = mk<C>(0.0, 0.0);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = Cc[bj] + lr;
+            const bool inK = col >= k0 && col < k0 + kb;
+            V sre, sim;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = R[bi] + acc_row<T>(lg, e);
+                C v = HELM_CSEL(inK, mk<C>(row == col ? 1.0 : 0.0, 0.0), xt[bi][bj][e]);
+                // complex128 selects part by part; complex64 keeps the branch
+                if constexpr (sizeof(T) == 8) v = HELM_CSEL(vr[bi] && vc[bj], v, zero);
+                else if (!(vr[bi] && vc[bj])) v = zero;
+                sre[e] = v.x;
+                sim[e] = v.y;
+            }
+            cacc_seed<GAUSS, V>(a1[bi][bj], a2[bi][bj], a3[bi][bj], sre, sim);
+        }
 }
 
 // update of one 64 x 64 tile of Y
@@ -762,38 +790,30 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int i = t + 256 * q, k = i >> 6, col = J0 + (i & 63);
-        if (!(k < kb && col < np)) vv[q] = zero;
-        else if (col >= k0 && col < k0 + kb) vv[q] = mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0);
-    }
-    // Y = X' + W V, accumulated from X'
-    V a1[2][2], a2[2][2], a3[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int col = Cc[bj] + lr;
-            const bool inK = col >= k0 && col < k0 + kb;
-            V sre, sim;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = R[bi] + acc_row<T>(lg, e);
-                C v = inK ? mk<C>(row == col ? 1.0 : 0.0, 0.0) : xt[bi][bj][e];
-                if (!(vr[bi] && vc[bj])) v = zero;
-                sre[e] = v.x;
-                sim[e] = v.y;
-            }
-            cacc_seed<GAUSS, V>(a1[bi][bj], a2[bi][bj], a3[bi][bj], sre, sim);
+        if constexpr (sizeof(T) == 8) {   // part by part, as above
+            vv[q] = HELM_CSEL(col >= k0 && col < k0 + kb, mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0), vv[q]);
+            vv[q] = HELM_CSEL(k < kb && col < np, vv[q], zero);
+        } else {
+            if (!(k < kb && col < np)) vv[q] = zero;
+            else if (col >= k0 && col < k0 + kb) vv[q] = mk<C>(k == col - k0 ? 1.0 : 0.0, 0.0);
         }
+    }
+    // Y = X' + W V, accumulated from X'.  complex128 seeds its three
+    // accumulators after the W product: across it the tile of X' (64
+    // registers) is live instead of them (96), which keeps the kernel from
+    // spilling
+    V a1[2][2], a2[2][2], a3[2][2];
+    if constexpr (!GAUSS) seed_y<GAUSS, T>(a1, a2, a3, xt, R, Cc, vr, vc, k0, kb, lr, lg);
     // 2. X_{I,K} and T into LDS
     {
         const int rr = t >> 2, c8 = 8 * (t & 3);
         const bool rok = I0 + rr < np;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = (rok && c8 + q < kb) ? xik[q] : zero;
+        for (int q = 0; q < 8; ++q) sW[rr][c8 + q] = HELM_CSEL(rok && c8 + q < kb, xik[q], zero);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = t + 256 * q, c = i >> 5, k = i & 31;
-            sT[k][c] = (k < kb && c < kb) ? tv[q] : mk<C>(0.0, 0.0);
+            sT[k][c] = HELM_CSEL(k < kb && c < kb, tv[q], mk<C>(0.0, 0.0));
         }
     }
     __syncthreads();
@@ -819,7 +839,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = I0 + 16 * w + acc_row<T>(lg, e), c = cb * 16 + lr;
-                tk[cb][e] = (row >= k0 && row < k0 + kb) ? sT[row - k0][c] : mk<C>(0.0, 0.0);
+                tk[cb][e] = HELM_CSEL(row >= k0 && row < k0 + kb, sT[row - k0][c], mk<C>(0.0, 0.0));
             }
         __syncthreads();   // every wave has read X_{I,K} and T
 #pragma unroll
@@ -844,6 +864,7 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
             sV[cc][k] = vv[q];
         }
     }
+    if constexpr (GAUSS) seed_y<GAUSS, T>(a1, a2, a3, xt, R, Cc, vr, vc, k0, kb, lr, lg);
     __syncthreads();
     // 4. Y_IJ = X'_IJ + W_I V_J
     for (int kk = 0; kk < kb; kk += 16) {
