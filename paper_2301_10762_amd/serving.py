@@ -90,6 +90,25 @@ class _Prepared:
     be: object = None                                        # backend (lane) that runs the batch
 
 
+_STREAMS = {}   # (device, key) -> stream, made once per process
+
+
+def pooled_stream(key):
+    """The process's stream for `key` on the current device, made on first
+    use.  torch's caching allocator keeps a block freed on a stream for later
+    allocations on that same stream, so each run of the server must use the
+    streams of the runs before it: with new streams every run, the results of
+    each earlier run would stay cached, unusable, until the device is full
+    (and the library's own allocations then fall back to emptying its block
+    cache, synchronously, on every factorisation)."""
+    import torch
+    k = (torch.cuda.current_device(), key)
+    s = _STREAMS.get(k)
+    if s is None:
+        s = _STREAMS[k] = torch.cuda.Stream()
+    return s
+
+
 class HelmBackend:
     """The device path: helm.factor_batch / helm.solve_batch.  Factors are
     made on one stream and solved on another, so that a pipelined server
@@ -105,13 +124,15 @@ class HelmBackend:
         self.factorisations = 0
         self.own = None          # a lane's stream: sync() waits for it alone
 
-    def lane(self):
-        """A backend for one lane of run_lanes: factors, solves and its
-        right-hand sides on one stream of its own, and sync() waiting for
-        that stream only (a device-wide synchronisation would make a lane
-        wait for the others' batches)."""
-        import torch
-        s = torch.cuda.Stream()
+    def lane(self, k: int = 0):
+        """A backend for lane k of run_lanes: factors, solves and its
+        right-hand sides on a stream of its own, and sync() waiting for that
+        stream only (a device-wide synchronisation would make a lane wait for
+        the others' batches).  Lane k of every run uses the same pooled
+        stream (pooled_stream), so memory freed by one run serves the next;
+        two runs at once in one process share their lanes' streams, which
+        orders their work but does not change results."""
+        s = pooled_stream(("lane", k))
         b = HelmBackend(self.precision, self.tol, stream=s, solve_stream=s)
         b.own = s
         return b
@@ -437,7 +458,7 @@ def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
     """Feed `requests` (sorted by arrival) to the server and run `lanes`
     batches side by side until all are done; results in completion order.
 
-    Each lane is a host thread with a backend of its own (backend.lane():
+    Each lane is a host thread with a backend of its own (backend.lane(k):
     one stream).  A free lane admits the next batch (the server's admission
     rules, with the memory of every batch in flight counted against the
     budget), factors and solves it, and hands the results back.  Admission,
@@ -449,12 +470,12 @@ def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
     if lanes < 1:
         raise ValueError("lanes must be >= 1")
     if not callable(getattr(server.be, "lane", None)):
-        raise TypeError("run_lanes needs a backend with lane() (a backend per lane, on a stream of its own)")
+        raise TypeError("run_lanes needs a backend with lane(k) (a backend per lane, on a stream of its own)")
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     results, err = [], []
     cv = threading.Condition()
     t0 = server.clock()
-    backends = [server.be.lane() for _ in range(lanes)]
+    backends = [server.be.lane(k) for k in range(lanes)]
 
     def arrivals():
         now = server.clock() - t0 if realtime else math.inf
@@ -568,7 +589,7 @@ def run_c5(requests: int = 32, rate: float = 200.0, seed: int = 0, budget_gb: fl
         g = helm.Grid(q.n, q.n, I.H_KM, I.H_KM)
         reqs.append(ServeRequest(q.rid, g, torch.as_tensor(m.reshape(-1), device="cuda"), [omega], list(src),
                                  arrival=q.t_arrival))
-    be = HelmBackend(precision, 1e-10, stream=torch.cuda.Stream(), solve_stream=torch.cuda.Stream())
+    be = HelmBackend(precision, 1e-10, stream=pooled_stream("factor"), solve_stream=pooled_stream("solve"))
     srv = Server(be, int(budget_gb * 2**30), max_chains, max_overtakes=max_overtakes)
     # warm-up: one small request through the whole path
     warm = ServeRequest(-1, helm.Grid(33, 33, I.H_KM, I.H_KM), torch.full((33 * 33,), 0.25, device="cuda",

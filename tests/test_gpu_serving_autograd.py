@@ -188,6 +188,34 @@ def test_pipelined_serving_equals_serial(helm):
             assert torch.equal(x, y), r.rid
 
 
+def test_lane_runs_reuse_memory(helm):
+    """Consecutive lane runs in one process reuse the memory of the runs
+    before them.  torch keeps a block freed on a stream for that stream;
+    lane k of every run uses the same pooled stream, so three more runs add
+    less than one run's results to the reserved memory (with new streams
+    every run they would add about three)."""
+    from paper_2301_10762_amd import serving as SV
+
+    def run():
+        reqs = [make_request(SV, helm, rid, 101, 40 + rid, (10.0 + rid,), 48)[0] for rid in range(6)]
+        srv = SV.Server(SV.HelmBackend("fp32_ir", 1e-10), 1 << 36, max_chains=4)
+        res = SV.run_lanes(srv, reqs, lanes=3, realtime=False)
+        torch.cuda.synchronize()
+        srv.close()
+        assert all(max(i.max_relres for i in r.infos) <= 1e-10 for r in res)
+        return sum(x.numel() * x.element_size() for r in res for x in r.X)
+
+    print("lane runs: memory reuse", flush=True)
+    nbytes = run()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_reserved()
+    for _ in range(3):
+        assert run() == nbytes
+    torch.cuda.synchronize()
+    growth = torch.cuda.memory_reserved() - before
+    assert growth < nbytes, (growth, nbytes)
+
+
 @pytest.mark.parametrize("lanes", [2, 3])
 def test_lane_serving_equals_serial(helm, lanes):
     """Batches run side by side on lanes (one stream and host thread each)

@@ -252,7 +252,7 @@ class LaneFake(FakeBackend):
         self.delay, self.busy, self.max_busy = delay, 0, 0
         self.lock = threading.Lock()
 
-    def lane(self):
+    def lane(self, k=0):
         return self
 
     def solve(self, Fs, Bs):
