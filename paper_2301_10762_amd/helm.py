@@ -163,9 +163,26 @@ def _torch():
 
 
 def _stream(stream=None):
+    """Handle of the stream a call runs on: `stream`, else the current one.
+    A stream other than the current one first waits for the work already
+    queued on the current stream, in whose order the call's inputs were
+    written and its outputs allocated."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return _vp(s.cuda_stream)
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return _vp(cur.cuda_stream)
+    stream.wait_stream(cur)
+    return _vp(stream.cuda_stream)
+
+
+def _written_on(stream, *outs):
+    """Outputs allocated here (on the current stream) and written on another
+    `stream` by a call that may return before its kernels end: the caching
+    allocator must not reuse their memory until that stream is done."""
+    torch = _torch()
+    if stream is not None and stream != torch.cuda.current_stream():
+        for t in outs:
+            t.record_stream(stream)
 
 
 def _ptr(t) -> _vp:
@@ -304,6 +321,7 @@ def solve(F: Factor, B, tol: float = 0.0, stream=None):
     info = _Info()
     _check(lib().helm_solve(F.handle, _ptr(B), _ptr(X), B.shape[0], F.grid.N, float(tol), _stream(stream),
                             ctypes.byref(info)))
+    _written_on(stream, X)
     return X, Info.of(info)
 
 
@@ -330,6 +348,7 @@ def adjoint_solve(F: Factor, R, tol: float = 0.0, stream=None):
     info = _Info()
     _check(lib().helm_adjoint_solve(F.handle, _ptr(R), _ptr(L), R.shape[0], F.grid.N, float(tol), _stream(stream),
                                     ctypes.byref(info)))
+    _written_on(stream, L)
     return L, Info.of(info)
 
 
@@ -346,6 +365,8 @@ def solve_batch(Fs, Bs, adjoint: bool = False, tol: float = 0.0, stream=None, ou
     larr = (ctypes.c_int64 * n)(*[F.grid.N for F in Fs])
     infos = (_Info * n)()
     _check(lib().helm_solve_batch(n, harr, barr, xarr, sarr, larr, int(adjoint), float(tol), _stream(stream), infos))
+    if out is None:
+        _written_on(stream, *Xs)
     return Xs, [Info.of(infos[c]) for c in range(n)]
 
 
@@ -368,6 +389,8 @@ def misfit_grad(grid: Grid, m, omegas, d_obs, sources, receivers, alpha: float =
     _check(lib().helm_misfit_grad(ctypes.byref(grid.c()), _ptr(md), n_omega, warr, _ptr(dd), len(src), psrc,
                                   len(rec), prec, float(alpha), float(mu), _PREC[precision], float(tol),
                                   _stream(stream), ctypes.byref(phi), _ptr(g), ctypes.byref(info)))
+    if grad_out is None:
+        _written_on(stream, g)
     return float(phi.value), g, Info.of(info)
 
 
@@ -387,6 +410,7 @@ def gn_hvp(grid: Grid, m, omegas, sources, receivers, directions, alpha: float =
     _check(lib().helm_gn_hvp(ctypes.byref(grid.c()), _ptr(md), n_omega, warr, len(src), psrc, len(rec), prec,
                              mt.shape[0], _ptr(mt), float(alpha), float(mu), _PREC[precision], float(tol),
                              _stream(stream), _ptr(hv), ctypes.byref(info)))
+    _written_on(stream, hv)
     return hv, Info.of(info)
 
 
@@ -517,6 +541,7 @@ class Hessian:
         hv = torch.empty_like(mt)
         info = _Info()
         _check(lib().helm_hess_apply(self.h, mt.shape[0], _ptr(mt), _ptr(hv), _stream(stream), ctypes.byref(info)))
+        _written_on(stream, hv)
         return hv, Info.of(info)
 
     def pcg(self, b, x0=None, prec_alpha: float = 0.0, prec_mu: float = 0.0, rtol: float = 1e-6,
@@ -576,6 +601,7 @@ def point_sources(grid: Grid, positions, stream=None):
     _check(lib().helm_point_sources(ctypes.byref(grid.c()), len(pos),
                                     pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(B), grid.N,
                                     _stream(stream)))
+    _written_on(stream, B)
     return B
 
 
@@ -588,6 +614,7 @@ def restrict(grid: Grid, positions, U, deriv: int = 0, stream=None):
     out = torch.empty((Ud.shape[0], len(pos)), dtype=torch.complex128, device="cuda")
     _check(lib().helm_restrict(ctypes.byref(grid.c()), len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                int(deriv), _ptr(Ud), Ud.shape[0], grid.N, _ptr(out), _stream(stream)))
+    _written_on(stream, out)
     return out
 
 
@@ -624,6 +651,7 @@ def gamma_solve(grid: Grid, alpha: float, mu: float, Y, stream=None):
     X = torch.empty_like(Yd)
     _check(lib().helm_gamma_solve(ctypes.byref(grid.c()), float(alpha), float(mu), Yd.shape[0], _ptr(Yd), _ptr(X),
                                   _stream(stream)))
+    _written_on(stream, X)
     return X
 
 
@@ -637,6 +665,7 @@ def residual(grid: Grid, m, omega: float, B, X, adjoint: bool = False, stream=No
     norms = torch.empty(B.shape[0], 2, dtype=torch.float64, device="cuda")
     _check(lib().helm_residual(ctypes.byref(grid.c()), _ptr(md), float(omega), int(adjoint), _ptr(B), _ptr(X),
                                _ptr(r), B.shape[0], grid.N, _ptr(norms), _stream(stream)))
+    _written_on(stream, r, norms)
     return r, norms
 
 

@@ -17,6 +17,10 @@
 * One batched solve over complex128 and complex64 factors gives each
   factor bitwise its result in a batch of its own precision, forward and
   adjoint.
+* A solve on a stream other than the current one sees a right-hand side
+  whose writer was still queued on the current stream (behind a bounded
+  sleep kernel) when the call was made: the binding orders the side stream
+  after the current one.
 """
 import ctypes
 
@@ -194,3 +198,25 @@ def test_solve_batch_mixes_precisions(helm, adjoint):
         assert info.max_relres <= 1e-10
         Xo = _oracle_solve(oracle.Grid(nx, nz, 0.05, 0.05), m, w, B, adjoint)
         assert_cols(X.cpu().numpy(), Xo, 1e-9, what=f"{nx}x{nz} in a mixed-precision batch")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_side_stream_waits_for_inputs(helm, precision):
+    nx, nz, S = 23, 19, 4
+    m, w, B = _system(nx, nz, 77, S)
+    grid = helm.Grid(nx, nz, 0.05, 0.05)
+    F = helm.factor(grid, torch.as_tensor(m, device="cuda"), w, precision)
+    B0 = torch.as_tensor(B, device="cuda")
+    Xref, _ = helm.solve(F, B0, tol=1e-10)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    print(f"side-stream solve, {precision}", flush=True)
+    Bd = torch.zeros_like(B0)
+    torch.cuda._sleep(20_000_000)        # a bounded spin on the current stream
+    Bd.copy_(B0)                         # queued behind it
+    X, info = helm.solve(F, Bd, tol=1e-10, stream=side)
+    side.synchronize()
+    torch.cuda.synchronize()
+    F.close()
+    assert info.max_relres <= 1e-10
+    assert torch.equal(X, Xref)
