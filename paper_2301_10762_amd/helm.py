@@ -175,6 +175,29 @@ def _stream(stream=None):
     return _vp(stream.cuda_stream)
 
 
+_POOL = {}   # (device, key) -> stream, made once per process
+
+
+def pooled_stream(key):
+    """The process's stream for `key` on the current device, made on first
+    use; the serving lanes and the pipeline take their streams from here.
+    * torch's caching allocator keeps a block freed on a stream for later
+      allocations on that same stream: runs that made new streams each time
+      would leave every earlier run's results cached where no later run can
+      use them, until the device is full.
+    * The runtime maps streams onto a few hardware queues per process as
+      they come into use; a second set of new streams can land on one
+      shared queue, and the work meant to overlap then runs in turn.
+    Users of one key at the same time (threads) share its stream: their
+    work is ordered, results are unchanged."""
+    torch = _torch()
+    k = (torch.cuda.current_device(), key)
+    s = _POOL.get(k)
+    if s is None:
+        s = _POOL[k] = torch.cuda.Stream()
+    return s
+
+
 def _written_on(stream, *outs):
     """Outputs allocated here (on the current stream) and written on another
     `stream` by a call that may return before its kernels end: the caching

@@ -38,6 +38,8 @@ import sys
 import threading
 import time
 
+from .helm import pooled_stream
+
 MAX_CHAINS = 16
 BYTES_PER_UNKNOWN_RHS = 48
 
@@ -88,25 +90,6 @@ class _Prepared:
     bytes: int = 0
     Bs: dict = None
     be: object = None                                        # backend (lane) that runs the batch
-
-
-_STREAMS = {}   # (device, key) -> stream, made once per process
-
-
-def pooled_stream(key):
-    """The process's stream for `key` on the current device, made on first
-    use.  torch's caching allocator keeps a block freed on a stream for later
-    allocations on that same stream, so each run of the server must use the
-    streams of the runs before it: with new streams every run, the results of
-    each earlier run would stay cached, unusable, until the device is full
-    (and the library's own allocations then fall back to emptying its block
-    cache, synchronously, on every factorisation)."""
-    import torch
-    k = (torch.cuda.current_device(), key)
-    s = _STREAMS.get(k)
-    if s is None:
-        s = _STREAMS[k] = torch.cuda.Stream()
-    return s
 
 
 class HelmBackend:
