@@ -137,8 +137,9 @@ def oracle_worker():
 
 
 def start_single_core_oracle():
-    """Start the single-core oracle timing in a child process (it runs while
-    the GPU is measured, on one of the host's cores)."""
+    """Start the single-core oracle timing in a child process (one of the
+    host's cores; it runs after the GPU measurements, before the all-core
+    run)."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
     return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker"], env=env,
@@ -196,8 +197,8 @@ def cpu_baseline(w, X_gpu, proc1):
     if one is not None:
         base["cores_1_value"] = one.get("value")
         base["cores_1_sample"] = ("one frequency (6 Hz) of the 401^2 workload, factor + 64 solves, "
-                                  f"{one.get('seconds')} s on {one.get('threads')} thread(s), timed while the "
-                                  "GPU part of the benchmark ran") if "value" in one else one.get("error")
+                                  f"{one.get('seconds')} s on {one.get('threads')} thread(s), timed after the "
+                                  "GPU part of the benchmark") if "value" in one else one.get("error")
     worst = {p: max(err[k][p]["max_over_sources"] for k in err) for p in X_gpu}
     return base, {"per_frequency": err, "worst": worst,
                   "definition": "per frequency: max over the 64 sources of ||x_s - x_s^oracle|| / "
@@ -503,8 +504,6 @@ def main():
         return
     X = [torch.empty_like(E) for _ in range(n_omega)]
     torch.cuda.synchronize()
-    # the single-core oracle runs beside the GPU measurements
-    proc1 = None if args.no_cpu_baseline else start_single_core_oracle()
     X_gpu = {}
 
     def step(precision):
@@ -674,7 +673,8 @@ def main():
 
     cpu, oracle_err = None, None
     if not args.no_cpu_baseline:
-        cpu, oracle_err = cpu_baseline(w, X_gpu, proc1)
+        # after the GPU part: host work beside it disturbed its timings
+        cpu, oracle_err = cpu_baseline(w, X_gpu, start_single_core_oracle())
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
