@@ -89,10 +89,12 @@ int helm_factor_batch(int32_t count, const helm_grid* grids, const double* const
 /* Bytes of HBM a factor of this grid and precision holds (for admission). */
 int helm_factor_bytes(const helm_grid* grid, int precision, size_t* bytes);
 
-/* Releases a factor.  Its device memory goes back to the device's
- * stream-ordered pool in the order of the stream the factor was made on, so
- * work on other streams that uses the factor must be complete before the
- * call.  NULL is ignored. */
+/* Releases a factor without waiting for the GPU.  Its device memory goes
+ * back to the library's cache in the order of the stream the factor was made
+ * on, after the factor's last use by a solve call on any other stream (the
+ * solve calls record it; helm_solve_noalloc does not, so work it queued with
+ * the factor must be complete before this call).  No call that uses the
+ * factor may run concurrently with this one.  NULL is ignored. */
 void helm_factor_destroy(helm_factor_t f);
 
 /* ---- solves ----------------------------------------------------------------

@@ -27,7 +27,31 @@ struct helm_factor_s {
     size_t bytes;
     size_t gbytes;    // size of G
     hipStream_t st;   // the stream it was made on (its memory is released there)
+    // last use on every other stream a solve ran it on (an event each); at
+    // release the factor's own stream waits for them, so the memory is not
+    // handed out again before those solves end, and no host wait is needed
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
+
+// Record that the factors of a solve were used on stream st.
+void note_use(helm_factor_s* f, hipStream_t st) {
+    if (!f || st == f->st) return;
+    std::lock_guard<std::mutex> lk(f->mu);
+    for (auto& u : f->uses)
+        if (u.first == st) {
+            (void)hipEventRecord(u.second, st);
+            return;
+        }
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(st);   // no event: wait for the use here instead
+        return;
+    }
+    (void)hipEventRecord(ev, st);
+    f->uses.push_back({st, ev});
+}
 
 // Lower-level state at one model for Hessian products (the appendix on
 // products with the Hessian): the factors of A(m, w) for every frequency,
@@ -453,6 +477,14 @@ int factor_group(helm_factor_s* const* fs, int n, int pivot, hipStream_t st, boo
 
 void destroy(helm_factor_s* f) {
     if (!f) return;
+    {
+        std::lock_guard<std::mutex> lk(f->mu);
+        for (auto& u : f->uses) {
+            (void)hipStreamWaitEvent(f->st, u.second, 0);
+            (void)hipEventDestroy(u.second);
+        }
+        f->uses.clear();
+    }
     if (f->G) g_cache.put(f->G, f->gbytes, f->st);
     if (f->m) g_cache.put(f->m, sizeof(double) * N_of(f->g), f->st);
     delete f;
@@ -708,7 +740,15 @@ int residual_norms_batch(const std::vector<ResidualReq>& rq, int adjoint, hipStr
 constexpr int MAX_IR = 10;
 
 // Solve a group of jobs that share one precision.
+int solve_jobs_on(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_t st);
+
 int solve_jobs(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_t st) {
+    const int rc = solve_jobs_on(jobs, adjoint, tol, st);
+    for (auto& jb : jobs) note_use(jb.f, st);
+    return rc;
+}
+
+int solve_jobs_on(std::vector<SolveJob>& jobs, bool adjoint, double tol, hipStream_t st) {
     const int n = (int)jobs.size();
     if (n == 0) return HELM_OK;
     const bool fp32 = jobs[0].f->prec == HELM_FP32_IR;
@@ -1933,10 +1973,7 @@ int helm_factor_batch(int32_t count, const helm_grid* grids, const double* const
     return factor_many(count, grids, m_devs, omegas, precision, S_(stream), outs);
 }
 
-void helm_factor_destroy(helm_factor_t f) {
-    if (f) (void)hipDeviceSynchronize();
-    destroy(f);
-}
+void helm_factor_destroy(helm_factor_t f) { destroy(f); }
 
 int helm_solve(helm_factor_t f, const double* B_dev, double* X_dev, int32_t S, int64_t ld, double tol, void* stream,
                helm_info* info) {
@@ -1960,7 +1997,9 @@ int helm_solve_noalloc(helm_factor_t f, const double* B_dev, double* X_dev, int3
     Arena arena{(char*)base, NOALLOC_BYTES, 0};
     ArenaScope scope(&arena);
     std::vector<SolveJob> jobs{{f, B_dev, X_dev, S, ld, info}};
-    return solve_jobs(jobs, false, tol, S_(stream));
+    // untracked (tracking would create an event): the caller keeps f alive
+    // until work on `stream` that uses it has ended
+    return solve_jobs_on(jobs, false, tol, S_(stream));
 }
 
 int helm_adjoint_solve(helm_factor_t f, const double* R_dev, double* L_dev, int32_t S, int64_t ld, double tol,

@@ -21,8 +21,13 @@
   whose writer was still queued on the current stream (behind a bounded
   sleep kernel) when the call was made: the binding orders the side stream
   after the current one.
+* Releasing a factor returns without waiting for the GPU, yet its memory
+  is not reused before a solve still queued on another stream has read it:
+  a new factor made at once on the released factor's stream (which takes
+  over that memory) leaves the queued solve's result bitwise unchanged.
 """
 import ctypes
+import time
 
 import numpy as np
 import pytest
@@ -220,3 +225,32 @@ def test_side_stream_waits_for_inputs(helm, precision):
     F.close()
     assert info.max_relres <= 1e-10
     assert torch.equal(X, Xref)
+
+
+def test_release_while_a_solve_is_queued(helm):
+    nx, nz, S = 37, 29, 6
+    m, w, B = _system(nx, nz, 91, S)
+    grid = helm.Grid(nx, nz, 0.04, 0.03)
+    own, side = torch.cuda.Stream(), torch.cuda.Stream()
+    md = torch.as_tensor(m, device="cuda")
+    md2 = torch.as_tensor(m[::-1].copy(), device="cuda")
+    B0 = torch.as_tensor(B, device="cuda")
+    F = helm.factor(grid, md, w, "fp64", stream=own)
+    Xref, _ = helm.solve(F, B0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    torch.cuda._sleep(20_000_000)
+    torch.cuda.synchronize()
+    t_sleep = time.perf_counter() - t0
+    print(f"release while a solve is queued (sleep {t_sleep * 1e3:.1f} ms)", flush=True)
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(20_000_000)
+        X, _ = helm.solve(F, B0, stream=side)       # tol 0: queued behind the sleep, no wait
+    t0 = time.perf_counter()
+    F.close()
+    t_close = time.perf_counter() - t0
+    F2 = helm.factor(grid, md2, w, "fp64", stream=own)   # takes over F's memory on its stream
+    torch.cuda.synchronize()
+    F2.close()
+    assert torch.equal(X, Xref)
+    assert t_close < 0.5 * t_sleep, (t_close, t_sleep)
