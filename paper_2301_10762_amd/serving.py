@@ -291,10 +291,12 @@ class Server:
         self.inflight_bytes = sum(p.bytes for p in self._inflight)
         self.inflight_keys = set().union(*[p.keys for p in self._inflight])
 
-    def _begin(self, batch, be=None) -> "_Prepared":
+    def _begin(self, batch, be=None, rhs=True) -> "_Prepared":
         """Bookkeeping of an admitted batch: resident factors it reuses, the
-        systems to factor, its right-hand sides (host thread of the caller;
-        `be`: the lane that runs it, by default the server's backend)."""
+        systems to factor, and (rhs=True) its right-hand sides (host thread of
+        the caller; `be`: the lane that runs it, by default the server's
+        backend).  rhs=False leaves the right-hand sides to _rhs, which needs
+        no lock."""
         prep = _Prepared(batch, self.clock())
         prep.be = be if be is not None else self.be
         prep.precision = batch[0].precision
@@ -312,9 +314,14 @@ class Server:
                     prep.oms.append(float(w))
                     prep.slots.append((r, q))
             prep.bytes += self._need(req, prep.keys)
-        prep.Bs = {r: prep.be.rhs(req) for r, req in enumerate(batch)}
-        prep.be.sync()
+        if rhs:
+            self._rhs(prep)
         return prep
+
+    def _rhs(self, prep: "_Prepared"):
+        """The batch's right-hand sides, on its lane, complete on return."""
+        prep.Bs = {r: prep.be.rhs(req) for r, req in enumerate(prep.batch)}
+        prep.be.sync()
 
     def _factor(self, prep: "_Prepared"):
         if prep.grids:
@@ -478,7 +485,7 @@ def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
                         arrivals()
                         batch = server.admit() if server.queue else []
                         if batch:
-                            prep = server._begin(batch, be)
+                            prep = server._begin(batch, be, rhs=False)
                             server._track(prep, True)
                             break
                         if not pending and not server.queue:
@@ -488,6 +495,7 @@ def run_lanes(server: Server, requests, lanes: int = 2, realtime: bool = True):
                             wait = max(0.0, pending[0].arrival - (server.clock() - t0))
                         cv.wait(wait)
                 try:
+                    server._rhs(prep)                # outside the lock
                     server._factor(prep)
                     X, infos = server._solve(prep)
                 except BaseException as e:      # re-raised on the calling thread
