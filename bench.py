@@ -670,6 +670,9 @@ def main():
         extras["serving_c5"] = SV.run_c5(requests=384, rate=200.0, precision=prec, lanes=4, max_chains=8)
         extras["serving_c5_fp64"] = SV.run_c5(requests=384, rate=200.0, precision="fp64", lanes=4, max_chains=8)
         extras["serving_150"] = SV.run_c5(requests=384, rate=150.0, precision=prec, lanes=4, max_chains=8)
+        # above the configured load: the capacity of each precision on the same stream
+        extras["serving_250"] = SV.run_c5(requests=384, rate=250.0, precision=prec, lanes=4, max_chains=8)
+        extras["serving_250_fp64"] = SV.run_c5(requests=384, rate=250.0, precision="fp64", lanes=4, max_chains=8)
 
     cpu, oracle_err = None, None
     if not args.no_cpu_baseline:
