@@ -2,8 +2,10 @@
 
 Every step of the hot path runs in the HIP kernels behind the C ABI declared
 in include/helm.h; this module turns torch device tensors into raw pointers
-and the current torch stream into a hipStream_t.  There is no CPU fallback:
-if the library is missing or the GPU is absent the calls raise.
+and the current torch stream (or a stream given, ordered after the current
+one) into a hipStream_t, and keeps the process's pool of streams for the
+serving lanes and the pipeline.  There is no CPU fallback: if the library is
+missing or the GPU is absent the calls raise.
 """
 from __future__ import annotations
 
