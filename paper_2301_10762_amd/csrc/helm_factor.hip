@@ -914,7 +914,9 @@ __device__ __forceinline__ void update_tile(const ChainInfo& d, const PanelStep&
                 const int row = R[bi] + acc_row<T>(lg, e);
                 const C g = mk<C>(gre[e], gim[e]);
                 // the finished inverse goes to the sweeps' operand layout
-                yst(Y + (ps.last_panel ? a_tiled(row, col, np) : (size_t)row * np + col), g);
+                yst(Y + (ps.last_panel ? (sizeof(T) == 4 ? a_tiled4(row, col, np) : a_tiled(row, col, np))
+                                       : (size_t)row * np + col),
+                    g);
                 if (schur) {
                     double2 a1;
                     if (Asrc) {

@@ -52,11 +52,25 @@ struct ChainInfo {
 __host__ __device__ inline size_t a_tiled(int row, int col, int np) {
     return ((size_t)(row >> 4) * (np >> 2) + (col >> 2)) * 64 + (col & 3) * 16 + (row & 15);
 }
+// complex64 blocks keep the same 16 x 16 tiles (256 elements, at the same
+// places), with the four values a lane takes in the four MFMA steps of a
+// tile next to each other (lane 16 g + r, step q: row 16 I + r, column
+// 16 T + 4 q + g), so that two 16-byte loads fetch them
+__host__ __device__ inline size_t a_tiled4(int row, int col, int np) {
+    return ((size_t)(row >> 4) * (np >> 4) + (col >> 4)) * 256 + (size_t)((col & 3) * 16 + (row & 15)) * 4 +
+           ((col >> 2) & 3);
+}
 // and a block of coupling vectors (np rows x S columns, S padded to 16) as
 // 4 x 16 tiles, each the B operand of one step (lane 16 g + r holds row
 // 4 K + g, column 16 T + r):
 __host__ __device__ inline size_t b_tiled(int row, int col, int np) {
     return ((size_t)(col >> 4) * (np >> 2) + (row >> 2)) * 64 + (row & 3) * 16 + (col & 15);
+}
+// and for complex64 the same 16 x 16 tiles with a lane's four values of a
+// tile adjacent (lane 16 g + r, step q: row 16 K + 4 q + g, column 16 T + r)
+__host__ __device__ inline size_t b_tiled4(int row, int col, int np) {
+    return ((size_t)(col >> 4) * (np >> 4) + (row >> 4)) * 256 + (size_t)((row & 3) * 16 + (col & 15)) * 4 +
+           ((row >> 2) & 3);
 }
 
 // Row k at which the two fronts of an nz-row system meet (the top front ends

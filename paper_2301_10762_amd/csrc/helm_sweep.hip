@@ -28,6 +28,12 @@ int sweep_row_tiles(int np) { return np / 16; }
 int sweep_col_tiles(int S) { return ((S + 15) / 16 + SW_CTG - 1) / SW_CTG; }
 int sweep_grid(int groups, int cgroups) { return 8 * ((groups * cgroups + 7) / 8); }
 
+// coupling-vector layout of the precision (b_tiled4 for complex64)
+template <typename T>
+__device__ __forceinline__ size_t bt(int row, int col, int np) {
+    return sizeof(T) == 4 ? b_tiled4(row, col, np) : b_tiled(row, col, np);
+}
+
 template <typename C>
 __device__ __forceinline__ C conj_if(C v, bool c) {
     if (c) v.y = -v.y;
@@ -47,7 +53,7 @@ __global__ __launch_bounds__(256) void k_sweep_init(const SweepTab* __restrict__
     C v = mk<C>(0.0, 0.0);
     if (k < d.nx && s < d.S)
         v = conj_if(gld((const C*)d.B + (size_t)s * d.ldb + (size_t)d.row0 * d.nx + k), CONJB);
-    gst((C*)d.Y0 + b_tiled(k, s, d.np), v);
+    gst((C*)d.Y0 + bt<T>(k, s, d.np), v);
 }
 
 // One workgroup per 16-row tile of a front's block row and group of SW_CTG
@@ -90,6 +96,7 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
     // operand streams: this row tile of G_j and this column tile of Y, each
     // 64 consecutive elements per MFMA step (the tiled layouts)
     const C* Gt = (const C*)d.G + (size_t)j * np * np + (size_t)(i0 >> 4) * (np >> 2) * 64 + l;
+    const C* Gt4 = Gt - l + 4 * l;   // complex64 layout: a lane's four values of a chunk adjacent
     // steps of one front alternate the coupling buffers: forward step t is
     // step t, backward step t is step nfwd + t of the front
     const int u = FWD ? tstep : d.nfwd + tstep;
@@ -98,6 +105,7 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
     const int s = 16 * (ct0 + myct) + lr;
     const bool scol = s < d.S;
     const C* Yt = Yin + (size_t)(ct0 + myct) * (np >> 2) * 64 + l;
+    const C* Yt4 = Yt - l + 4 * l;   // complex64 layout
 
     // epilogue operands (next block's right-hand side, or this block's
     // forward result), fetched before the contraction.  Forward: `more` -
@@ -120,7 +128,7 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
         for (int e = 0; e < 4; ++e) {
             const int ic = min(i0 + acc_row<T>(lg, e), nx - 1);
             const C* src = !FWD      ? X + (size_t)sc * d.ldx + (size_t)j * nx + ic
-                           : merge_in ? (const C*)d.Bm + b_tiled(ic, sc, np)
+                           : merge_in ? (const C*)d.Bm + bt<T>(ic, sc, np)
                                       : Bv + (size_t)sc * d.ldb + (size_t)jr * nx + ic;
             pre[e] = gld(src);
         }
@@ -138,13 +146,36 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
     C ga[SW_GDEPTH][4], ya[SW_YDEPTH][4];
     auto gload = [&](C (&gq)[4], int c) {
         const int cc = min(c, c_end - 1);
+        if constexpr (sizeof(T) == 4) {
+            // complex64 blocks (a_tiled4): a lane's four values of the chunk
+            // are adjacent, two 16-byte loads
+            typedef float gv4f __attribute__((ext_vector_type(4)));
+            const HELM_GLOBAL gv4f* p = (const HELM_GLOBAL gv4f*)(Gt4 + (size_t)cc * 256);
+            const gv4f a = p[0], b = p[1];
+            gq[0] = mk<C>(a.x, a.y);
+            gq[1] = mk<C>(a.z, a.w);
+            gq[2] = mk<C>(b.x, b.y);
+            gq[3] = mk<C>(b.z, b.w);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gq[q] = gld(Gt + (size_t)(4 * cc + q) * 64);
+            for (int q = 0; q < 4; ++q) gq[q] = gld(Gt + (size_t)(4 * cc + q) * 64);
+        }
     };
     auto yload = [&](C (&yq)[4], int c) {
         const int cc = min(c, c_end - 1);
+        if constexpr (sizeof(T) == 4) {
+            // complex64 coupling vectors (b_tiled4): two 16-byte loads
+            typedef float gv4f __attribute__((ext_vector_type(4)));
+            const HELM_GLOBAL gv4f* p = (const HELM_GLOBAL gv4f*)(Yt4 + (size_t)cc * 256);
+            const gv4f a = p[0], b = p[1];
+            yq[0] = mk<C>(a.x, a.y);
+            yq[1] = mk<C>(a.z, a.w);
+            yq[2] = mk<C>(b.x, b.y);
+            yq[3] = mk<C>(b.z, b.w);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) yq[q] = gld(Yt + (size_t)(4 * cc + q) * 64);
+            for (int q = 0; q < 4; ++q) yq[q] = gld(Yt + (size_t)(4 * cc + q) * 64);
+        }
     };
     // The chunks run in straight-line blocks of SW_UNROLL, each starting
     // with empty queues: the products of a chunk past the end are skipped (a
@@ -219,12 +250,12 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
             if (more || hand_over) {
                 if (i < nx) nxt = mk<C>(pre[e].x - ei * sr, pre[e].y - ei * si);
                 if (hand_over) {
-                    gst((C*)d.Mout + b_tiled(i, s, np), nxt);
+                    gst((C*)d.Mout + bt<T>(i, s, np), nxt);
                     continue;
                 }
             } else {
                 nxt = mk<C>(ei * sr, ei * si);
-                if (d.Zp) gst((C*)d.Zp + b_tiled(i, s, np), nxt);
+                if (d.Zp) gst((C*)d.Zp + bt<T>(i, s, np), nxt);
             }
         } else {
             // x_j = w_j - G_j z_j; the next step's z = E x_j
@@ -234,7 +265,7 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(int n, int tstep, int g
                 nxt = mk<C>(ei * xn.x, ei * xn.y);
             }
         }
-        gst(Yout + b_tiled(i, s, np), nxt);
+        gst(Yout + bt<T>(i, s, np), nxt);
     }
 }
 
