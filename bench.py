@@ -14,8 +14,8 @@ resident in HBM before the timed region.
 
 Schedule: the K timed steps run as a pipeline of independent batches
 (paper_2301_10762_amd.pipeline): the factorisations of the next F steps run
-side by side, each on a stream of its own (F = --factor-streams, default 1:
-two batches in flight), while step k is solved on another stream; every step
+side by side, each on a stream of its own (F = --factor-streams, default 2:
+three batches in flight), while step k is solved on another stream; every step
 is still factored and solved in full, with the same kernels.  The serial schedule (one step at a time) is timed first and reported
 beside it, with the per-step latency percentiles and the per-kernel timings
 that the roofline figure uses.
@@ -52,8 +52,8 @@ def parse():
     p.add_argument("--schedule", default="both", choices=["both", "serial"],
                    help="both: serial steps (kernel timings, latency) then the headline with batches in "
                         "flight; serial: the serial steps only (value = their throughput)")
-    p.add_argument("--factor-streams", type=int, default=1,
-                   help="factorisations side by side in the pipelined schedule (1: two batches in flight)")
+    p.add_argument("--factor-streams", type=int, default=2,
+                   help="factorisations side by side in the pipelined schedule (2: three batches in flight)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
