@@ -54,6 +54,9 @@ def parse():
                         "flight; serial: the serial steps only (value = their throughput)")
     p.add_argument("--factor-streams", type=int, default=2,
                    help="factorisations side by side in the pipelined schedule (2: three batches in flight)")
+    p.add_argument("--fp64-factor-streams", type=int, default=1,
+                   help="the same for plain complex128 factors, whose heavier steps gain nothing from a second "
+                        "factorisation beside the first (1: two batches in flight)")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the factor-only, forward+adjoint (misfit and gradient) and Gauss-Newton timings")
     p.add_argument("--profile-copy", action="store_true",
@@ -538,12 +541,12 @@ def main():
             helm.kernel_timing(False)
         return total, lat, infos, kt
 
-    def run_pipelined(precision, warmup, steps):
-        """The same steps as a pipeline: the next F batches are factored side
+    def run_pipelined(precision, warmup, steps, nf):
+        """The same steps as a pipeline: the next nf batches are factored side
         by side (one stream each) while batch k is solved
-        (paper_2301_10762_amd.pipeline); at most F + 1 batches hold factors."""
+        (paper_2301_10762_amd.pipeline); at most nf + 1 batches hold factors."""
         from paper_2301_10762_amd.pipeline import Batch, Pipeline
-        nf = max(1, args.factor_streams)
+        nf = max(1, nf)
         pipe = Pipeline(factor_streams=nf)
         outs = [[torch.empty_like(E) for _ in range(n_omega)] for _ in range(nf + 1)]
 
@@ -563,6 +566,7 @@ def main():
         return total, res[-1][1]
 
     prec = args.precision
+    nf_head = args.factor_streams if prec == "fp32_ir" else args.fp64_factor_streams
     # serial schedule (one batch at a time), with the per-kernel timing
     total_s, lat, infos, kt = run(prec, args.warmup, args.steps, True)
     solves = n_omega * S * args.steps
@@ -572,7 +576,7 @@ def main():
         X_gpu["c64_ir" if prec == "fp32_ir" else "c128"] = [x.cpu().numpy() for x in X]
     # headline: the pipelined schedule
     if args.schedule == "both":
-        total, infos_p = run_pipelined(prec, args.warmup, args.steps)
+        total, infos_p = run_pipelined(prec, args.warmup, args.steps, nf_head)
     else:
         total = total_s
     value = solves / total
@@ -606,7 +610,7 @@ def main():
         t64, lat64, inf64, _ = run("fp64", 1, fsteps, False)
         if not args.no_cpu_baseline:
             X_gpu["c128"] = [x.cpu().numpy() for x in X]
-        tp64 = run_pipelined("fp64", 1, fsteps)[0] if args.schedule == "both" else t64
+        tp64 = run_pipelined("fp64", 1, fsteps, args.fp64_factor_streams)[0] if args.schedule == "both" else t64
         v64 = n_omega * S * fsteps / tp64
         fp64 = {"value": round(v64, 2), "ms_per_step": round(tp64 / fsteps * 1e3, 3),
                 "serial_value": round(n_omega * S * fsteps / t64, 2),
@@ -689,7 +693,7 @@ def main():
                                "per frequency, all solved to rel. residual <= 1e-10",
                    "grid": [nx, nz], "n_omega": n_omega, "sources": S, "parallelism": "single GPU",
                    "precision": prec},
-        "schedule": (f"pipelined: the factorisations of the next {max(1, args.factor_streams)} batches run side by "
+        "schedule": (f"pipelined: the factorisations of the next {max(1, nf_head)} batches run side by "
                      "side (one stream each) while batch k is solved on another stream (each batch = the five "
                      "systems factored and all 5 x 64 right-hand sides solved)")
                     if args.schedule == "both" else "serial: one batch at a time",
